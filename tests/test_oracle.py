@@ -1,0 +1,442 @@
+"""Pins for the CPU oracle: each check comes from the paper or from the
+mathematics, never from the oracle itself, so a dropped term, a wrong sign,
+a transposed operand or a wrong preconditioner fails at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads.meshes import CSR
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def random_csr(n_rows, n_cols, lengths, seed):
+    """Non-symmetric CSR with the given row lengths (distinct sorted
+    columns per row, values U(-1,1))."""
+    g = np.random.default_rng(seed)
+    cols, vals, rp = [], [], [0]
+    for L in lengths:
+        c = np.sort(g.choice(n_cols, size=L, replace=False))
+        cols.append(c)
+        vals.append(g.uniform(-1, 1, L))
+        rp.append(rp[-1] + L)
+    col = np.concatenate(cols).astype(np.int32) if cols else \
+        np.zeros(0, np.int32)
+    val = np.concatenate(vals) if vals else np.zeros(0)
+    return CSR(n_rows, n_cols, np.array(rp, np.int32), col, val)
+
+
+def tiny_meshes():
+    out = []
+    for n in (3, 5, 8):
+        out.append(W.poisson_2d_p1(n, seed=(90, n), bc="none"))
+        out.append(W.poisson_2d_p1(n, seed=(90, n), bc="all", permute=True))
+    for n in (3, 4, 5):
+        out.append(W.tet_p1(n, "laplace", seed=(91, n)))
+        out.append(W.tet_p1(n, "elastic", seed=(91, n), permute=True))
+        out.append(W.hex_q1(n, "laplace", seed=(92, n)))
+        out.append(W.hex_q1(n, "elastic", seed=(92, n), bc="x0"))
+    for c in (1, 2):
+        out.append(W.tet_p2(c, "laplace", seed=(93, c)))
+        out.append(W.tet_p2(c, "elastic", seed=(93, c), permute=True))
+    return out
+
+
+# ---------------------------------------------------------------- SpMV
+def test_worked_example_renumbering(orc):
+    """The K1r / K1rs worked example: c' = P^{-1}(c), x' = x(P), sorted
+    c'' and A'', and the row's product is 121 in all three numberings."""
+    g = json.load(open(os.path.join(GOLD, "worked_example.json")))
+    P = np.array(g["P"]) - 1
+    Pinv = orc.inverse_perm(P)
+    row = CSR(1, 7, np.array([0, 5], np.int32),
+              np.array(g["c"], np.int32) - 1, np.array(g["A"], float))
+    x = np.array(g["x"], float)
+    xp = orc.gather(P, x)
+    assert list(xp) == g["x_prime"]
+    _, c1, v1 = orc.permute(row, ciperm=Pinv, sort_cols=False)
+    assert list(c1 + 1) == g["c_prime"]
+    assert list(v1) == g["A"]
+    _, c2, v2 = orc.permute(row, ciperm=Pinv, sort_cols=True)
+    assert list(c2 + 1) == g["c_dprime"]
+    assert list(v2) == g["A_dprime"]
+    y0 = orc.spmv(row, x)[0]
+    y1 = orc.spmv(CSR(1, 7, row.rowptr, c1, v1), xp)[0]
+    y2 = orc.spmv(CSR(1, 7, row.rowptr, c2, v2), xp)[0]
+    assert y0 == y1 == y2 == g["y"]
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_spmv_random_nonsymmetric_vs_dense(orc, case):
+    """Ragged rows (empty, single, long), non-square, non-symmetric:
+    catches a transposed operand, a dropped first/last entry, x[i] for
+    x[col]."""
+    g = np.random.default_rng(case)
+    nr, nc = [(50, 70), (64, 64), (200, 31)][case]
+    lengths = g.integers(0, min(nc, 25), nr)
+    lengths[0] = 0
+    lengths[-1] = min(nc, 30)
+    A = random_csr(nr, nc, lengths, seed=case)
+    x = g.uniform(-1, 1, nc)
+    y = orc.spmv(A, x)
+    ref = A.to_dense() @ x
+    scale = np.abs(A.to_dense()) @ np.abs(x)
+    assert np.all(np.abs(y - ref) <= 1e-14 * scale + 1e-300)
+    assert np.all(y[lengths == 0] == 0.0)
+    # pure-python row loop on a few rows
+    for i in (1, nr // 2, nr - 1):
+        s = sum(A.val[k] * x[A.col[k]] for k in range(A.rowptr[i],
+                                                       A.rowptr[i + 1]))
+        assert y[i] == s
+
+
+@pytest.mark.parametrize("idx", range(20))
+def test_spmv_fem_vs_dense(orc, idx):
+    A = tiny_meshes()[idx]
+    x = W.random_vector(A.n_cols, 90, W.XVEC, idx)
+    D = A.to_dense()
+    y = orc.spmv(A, x)
+    scale = orc.spmv_abs(A, x)
+    assert np.allclose(scale, np.abs(D) @ np.abs(x), rtol=1e-14)
+    assert np.all(np.abs(y - D @ x) <= 1e-14 * scale)
+
+
+@pytest.mark.parametrize("idx", range(20))
+def test_spmv_symmetry(orc, idx):
+    """x^T (A y) = y^T (A x) for the symmetric stiffness matrices."""
+    A = tiny_meshes()[idx]
+    x = W.random_vector(A.n_cols, 90, W.XVEC, 100 + idx)
+    y = W.random_vector(A.n_cols, 90, W.BVEC, 100 + idx)
+    lhs = x @ orc.spmv(A, y)
+    rhs = y @ orc.spmv(A, x)
+    bound = np.abs(x) @ orc.spmv_abs(A, y)
+    assert abs(lhs - rhs) <= 1e-13 * bound
+
+
+@pytest.mark.parametrize("gen", [
+    lambda: W.poisson_2d_p1(9, seed=(94, 0), bc="none"),
+    lambda: W.tet_p1(6, "laplace", seed=(94, 1), permute=True),
+    lambda: W.tet_p2(2, "laplace", seed=(94, 2)),
+    lambda: W.hex_q1(5, "laplace", seed=(94, 3)),
+])
+def test_neumann_laplacian_zero_row_sums(orc, gen):
+    A = gen()
+    y = orc.spmv(A, np.ones(A.n_cols))
+    scale = orc.spmv_abs(A, np.ones(A.n_cols))
+    assert np.all(np.abs(y) <= 1e-13 * scale)
+    # and the sum is not trivially zero because of a dropped row
+    assert np.all(scale > 0)
+
+
+def rigid_body_modes(A):
+    X = A.meta["coords"]
+    n = len(X)
+    modes = []
+    for c in range(3):
+        u = np.zeros((n, 3))
+        u[:, c] = 1.0
+        modes.append(u.reshape(-1))
+    for w in np.eye(3):
+        modes.append(np.cross(w, X).reshape(-1))
+    return modes
+
+
+@pytest.mark.parametrize("gen", [
+    lambda: W.tet_p1(5, "elastic", seed=(95, 0), permute=True),
+    lambda: W.tet_p2(2, "elastic", seed=(95, 1)),
+    lambda: W.hex_q1(4, "elastic", seed=(95, 2), permute=True),
+])
+def test_elasticity_rigid_body_null_space(orc, gen):
+    A = gen()
+    for u in rigid_body_modes(A):
+        y = orc.spmv(A, u)
+        assert np.all(np.abs(y) <= 1e-12 * orc.spmv_abs(A, u) + 1e-14)
+    # a non-rigid field (stretch) is not annihilated
+    X = A.meta["coords"]
+    u = np.zeros((len(X), 3))
+    u[:, 0] = X[:, 0]
+    assert np.abs(orc.spmv(A, u.reshape(-1))).max() > 1e-3
+
+
+def test_linear_patch_interior_rows(orc):
+    """Interior rows of a jittered P1 Laplacian annihilate any linear
+    field (P1 reproduces linears)."""
+    A = W.poisson_2d_p1(10, seed=(96, 0), bc="none")
+    X = A.meta["coords"]
+    u = 1.0 + 2.0 * X[:, 0] + 3.0 * X[:, 1]
+    y = orc.spmv(A, u)
+    interior = np.all((X > 0) & (X < 1), axis=1)
+    assert np.all(np.abs(y[interior]) <= 1e-12 * orc.spmv_abs(A, u)[interior])
+    assert np.abs(y[~interior]).max() > 1e-3
+
+
+def test_2d_unjittered_is_five_point_stencil(orc):
+    """Without jitter the P1 right-triangle Laplacian is the 5-point
+    stencil [4, -1 x 4]; its sine modes are eigenvectors with
+    lambda = 4 - 2 cos(k pi/(N+1)) - 2 cos(l pi/(N+1))."""
+    n = 12
+    A = W.poisson_2d_p1(n, jitter=0.0, bc="all")
+    N = n - 2
+    D = A.to_dense()
+    off = D - np.diag(np.diag(D))
+    assert np.allclose(np.diag(D), 4.0, atol=1e-14)
+    assert np.all(np.isclose(off, 0.0, atol=1e-15) |
+                  np.isclose(off, -1.0, atol=1e-15))
+    j = np.arange(1, N + 1)
+    for k, l in [(1, 1), (2, 5), (N, N), (3, 7)]:
+        v = np.outer(np.sin(l * np.pi * j / (N + 1)),
+                     np.sin(k * np.pi * j / (N + 1))).reshape(-1)
+        lam = 4 - 2 * np.cos(k * np.pi / (N + 1)) - \
+            2 * np.cos(l * np.pi / (N + 1))
+        assert np.allclose(orc.spmv(A, v), lam * v, atol=1e-12)
+
+
+def test_3d_unjittered_kuhn_is_seven_point_stencil(orc):
+    n = 7
+    h = 1.0 / (n - 1)
+    A = W.tet_p1(n, "laplace", jitter=0.0, bc="all")
+    N = n - 2
+    j = np.arange(1, N + 1)
+    for k in [(1, 1, 1), (2, 3, 1), (N, 1, 4)]:
+        s = [np.sin(kk * np.pi * j / (N + 1)) for kk in k]
+        v = np.einsum("k,j,i->kji", s[2], s[1], s[0]).reshape(-1)
+        lam = h * sum(2 - 2 * np.cos(kk * np.pi / (N + 1)) for kk in k)
+        assert np.allclose(orc.spmv(A, v), lam * v, atol=1e-12)
+    # face and body diagonal couplings are structurally present, value 0
+    D = A.to_dense()
+    assert A.row_lengths().max() == 15
+    nz = D[np.abs(D) > 1e-14]
+    assert np.allclose(np.sort(np.unique(np.round(nz / h, 12))), [-1, 6])
+
+
+def test_spmm_is_columnwise_spmv(orc):
+    A = W.tet_p1(4, "elastic", seed=(97, 0), permute=True)
+    X = W.random_vector(A.n_cols, 97, W.XVEC, 0, k=5)
+    Y = orc.spmm(A, X)
+    for c in range(5):
+        assert np.array_equal(Y[:, c], orc.spmv(A, X[:, c].copy()))
+    assert np.allclose(Y, A.to_dense() @ X, rtol=0, atol=1e-13)
+
+
+def test_symmetric_renumbering_preserves_product(orc):
+    """(P A P^T) x' equals (A x) renumbered, for a random P."""
+    A = W.tet_p1(5, "elastic", seed=(98, 0))
+    P = np.random.default_rng(5).permutation(A.n_rows).astype(np.int32)
+    Pinv = orc.inverse_perm(P)
+    rp, c, v = orc.permute(A, rperm=P, ciperm=Pinv, sort_cols=True)
+    Ap = CSR(A.n_rows, A.n_cols, rp, c, v)
+    assert np.all(np.diff(c.reshape(-1)[:0]) >= 0)
+    for i in range(0, A.n_rows, 97):
+        assert np.all(np.diff(c[rp[i]:rp[i + 1]]) > 0)
+    x = W.random_vector(A.n_cols, 98, W.XVEC)
+    y = orc.spmv(A, x)
+    yp = orc.spmv(Ap, orc.gather(P, x))
+    assert np.all(np.abs(yp - y[P]) <= 1e-14 * orc.spmv_abs(A, x)[P])
+    assert np.array_equal(orc.scatter(P, orc.gather(P, x)), x)
+
+
+# ------------------------------------------------------------ rounding
+def test_round_f32_matches_numpy(orc):
+    g = np.random.default_rng(1)
+    v = np.concatenate([g.standard_normal(10000) * 10.0 ** g.integers(
+        -40, 40, 10000), [0.0, -0.0, 1e-46, 3.4028235677973366e38,
+                          3.5e38, np.inf, -np.inf]])
+    # exact ties between two floats
+    f = g.standard_normal(1000).astype(np.float32)
+    nxt = np.nextafter(f, np.float32(np.inf))
+    v = np.concatenate([v, (f.astype(float) + nxt.astype(float)) / 2])
+    with np.errstate(over="ignore"):
+        ref = v.astype(np.float32)
+    assert np.array_equal(orc.round_f32(v).view(np.uint32),
+                          ref.view(np.uint32))
+
+
+def test_round_bf16_matches_torch(orc):
+    torch = pytest.importorskip("torch")
+    g = np.random.default_rng(2)
+    f = (g.standard_normal(20000) * 10.0 ** g.integers(-38, 38, 20000)
+         ).astype(np.float32)
+    bits = f.view(np.uint32)
+    # exact ties (low 16 bits = 0x8000) with even and odd kept parts
+    ties = ((bits & 0xFFFF0000) | 0x8000).view(np.float32)
+    special = np.array([0.0, -0.0, 1e-40, -1e-40, 3.3895314e38, 3.39e38,
+                        np.inf, -np.inf, 1.0, -2.5], np.float32)
+    f = np.concatenate([f, ties, special])
+    ours = np.array([orc.f32_to_bf16_bits(x) for x in f], np.uint16)
+    ref = torch.from_numpy(f).to(torch.bfloat16).view(torch.int16).numpy(
+    ).view(np.uint16)
+    assert np.array_equal(ours, ref)
+    nan = orc.f32_to_bf16_bits(np.float32(np.nan))
+    assert np.isnan(orc.bf16_bits_to_f32(np.array([nan]))[0])
+    # two-step rounding from double
+    d = g.standard_normal(1000)
+    assert np.array_equal(
+        orc.round_bf16(d),
+        np.array([orc.f32_to_bf16_bits(np.float32(x)) for x in d]))
+
+
+def test_spmv_f32_error_bound(orc):
+    A = W.tet_p1(6, "elastic", seed=(99, 0), permute=True)
+    a = orc.round_f32(A.val)
+    x = W.random_vector(A.n_cols, 99, W.XVEC).astype(np.float32)
+    y = orc.spmv_f32(A, a, x)
+    Af = CSR(A.n_rows, A.n_cols, A.rowptr, A.col, a.astype(float))
+    exact = orc.spmv(Af, x.astype(float))
+    scale = orc.spmv_abs(Af, x.astype(float))
+    m = A.row_lengths().max()
+    u = 2.0 ** -24
+    assert np.all(np.abs(y - exact) <= (m * u / (1 - m * u)) * scale * 1.01)
+    assert np.abs(y - exact).max() > 0  # really single precision
+
+
+# ------------------------------------------------------------------ CG
+def small_spd():
+    return [
+        W.poisson_2d_p1(12, seed=(80, 0), bc="all"),
+        W.poisson_2d_p1(10, seed=(80, 1), bc="all", permute=True),
+        W.tet_p1(5, "elastic", seed=(80, 2), bc="x0", permute=True),
+        W.tet_p1(6, "laplace", seed=(80, 3), bc="all"),
+        W.hex_q1(4, "elastic", seed=(80, 4), bc="x0"),
+        W.tet_p2(2, "laplace", seed=(80, 5), bc="all"),
+    ]
+
+
+@pytest.mark.parametrize("idx", range(6))
+@pytest.mark.parametrize("precond", [0, 1])
+def test_cg_matches_dense_solve(orc, idx, precond):
+    A = small_spd()[idx]
+    b = W.random_vector(A.n_rows, 80, W.BVEC, idx)
+    D = A.to_dense()
+    xs = np.linalg.solve(D, b)
+    kappa = np.linalg.cond(D)
+    x, st, it, rr = orc.pcg(A, b, precond=precond, rtol=1e-8, maxit=10000)
+    assert st == orc.OK
+    assert rr <= 1e-8
+    assert np.linalg.norm(D @ x - b) <= 1.0001e-8 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xs) <= 2e-8 * kappa * np.linalg.norm(xs)
+    assert 0 < it <= A.n_rows + 5
+
+
+def test_cg_manufactured_1d_nodal_exact(orc):
+    """P1 with a unit source on [0,1] is nodally exact: u = x(1-x)/2."""
+    A, b = W.laplace_1d_p1(200)
+    x, st, it, rr = orc.pcg(A, b, precond=0, rtol=1e-12, maxit=1000)
+    X = A.meta["coords"]
+    assert st == orc.OK
+    assert np.abs(x - X * (1 - X) / 2).max() <= 1e-10
+    # finite termination: at most n steps (n = 199 unknowns)
+    assert it <= A.n_rows
+
+
+def test_cg_linear_patch_2d(orc):
+    """Jittered P1 mesh, linear u = 1 + 2x + 3y: lifting the boundary
+    values into b, CG returns the interior nodal values of u."""
+    A = W.poisson_2d_p1(20, seed=(81, 0), bc="none")
+    X = A.meta["coords"]
+    u = 1.0 + 2.0 * X[:, 0] + 3.0 * X[:, 1]
+    inner = np.all((X > 0) & (X < 1), axis=1)
+    D = A.to_dense()
+    Aii = D[np.ix_(inner, inner)]
+    b = -D[np.ix_(inner, ~inner)] @ u[~inner]
+    sp = CSR(int(inner.sum()), int(inner.sum()),
+             *_dense_to_csr(Aii))
+    x, st, it, rr = orc.pcg(sp, b, precond=1, rtol=1e-12)
+    assert st == orc.OK
+    assert np.abs(x - u[inner]).max() <= 1e-9
+
+
+def _dense_to_csr(D):
+    rows, cols = np.nonzero(D != 0)
+    rp = np.zeros(D.shape[0] + 1, np.int32)
+    np.add.at(rp, rows + 1, 1)
+    return np.cumsum(rp).astype(np.int32), cols.astype(np.int32), D[rows, cols]
+
+
+def test_cg_iteration_bound_unjittered_config0(orc):
+    """For config 0 without jitter the matrix is the 5-point stencil, with
+    closed-form extreme eigenvalues, kappa = 1607.9.  CG's residual obeys
+    |r_k| / |r_0| <= 2 sqrt(kappa) ((sqrt(kappa)-1)/(sqrt(kappa)+1))^k, so
+    |r_k| <= 1e-8 |b| after at most ceil(sqrt(kappa)/2 ln(2 sqrt(kappa)/1e-8))
+    iterations from x0 = 0."""
+    A = W.poisson_2d_p1(64, jitter=0.0, bc="all")
+    N = 62
+    lmin = 2 * (2 - 2 * np.cos(np.pi / (N + 1)))
+    lmax = 2 * (2 - 2 * np.cos(N * np.pi / (N + 1)))
+    kappa = lmax / lmin
+    assert abs(kappa - 1607.9) < 0.1
+    sk = np.sqrt(kappa)
+    bound = int(np.ceil(0.5 * sk * np.log(2 * sk / 1e-8)))
+    b = W.random_vector(A.n_rows, 0, W.BVEC)
+    x, st, it, rr = orc.pcg(A, b, precond=0, rtol=1e-8, maxit=5000)
+    assert st == orc.OK and it <= bound
+
+
+def test_jacobi_is_scaling_invariant(orc):
+    """Jacobi-PCG on D L D equals plain CG on L when diag(L) is constant:
+    same iteration count; a wrong preconditioner (d instead of 1/d, or
+    none) needs far more iterations on the badly scaled matrix."""
+    L, b = W.laplace_1d_p1(120)
+    g = np.random.default_rng(3)
+    d = 10.0 ** g.uniform(0, 3, L.n_rows)
+    rows = np.repeat(np.arange(L.n_rows), L.row_lengths())
+    S = CSR(L.n_rows, L.n_cols, L.rowptr, L.col, d[rows] * L.val * d[L.col])
+    _, st0, it0, _ = orc.pcg(L, b, precond=0, rtol=1e-10, maxit=5000)
+    x1, st1, it1, rr1 = orc.pcg(S, d * b, precond=1, rtol=1e-10,
+                                maxit=5000)
+    _, st2, it2, _ = orc.pcg(S, d * b, precond=0, rtol=1e-10, maxit=5000)
+    assert st0 == st1 == orc.OK
+    assert abs(it0 - it1) <= 1
+    assert it2 > 3 * it1 or st2 != orc.OK
+
+
+def test_cg_status_codes(orc):
+    # indefinite: breakdown
+    Ind = CSR(2, 2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32),
+              np.array([1.0, -1.0]))
+    _, st, it, _ = orc.pcg(Ind, np.array([1.0, 1.0]), precond=0)
+    assert st == orc.BREAKDOWN
+    # maxit reached
+    A = W.poisson_2d_p1(16, seed=(82, 0), bc="all")
+    b = W.random_vector(A.n_rows, 82, W.BVEC)
+    _, st, it, rr = orc.pcg(A, b, precond=1, maxit=3)
+    assert st == orc.NOT_CONVERGED and it == 3 and rr > 1e-8
+    # b = 0
+    x, st, it, rr = orc.pcg(A, np.zeros(A.n_rows), x0=np.ones(A.n_rows))
+    assert st == orc.OK and it == 0 and not x.any()
+    # zero diagonal with Jacobi
+    Z = CSR(2, 2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32),
+            np.array([1.0, 1.0]))
+    _, st, _, _ = orc.pcg(Z, np.array([1.0, 2.0]), precond=1)
+    assert st == orc.ARG
+
+
+def test_cg_warm_start_resume(orc):
+    A = W.tet_p1(6, "elastic", seed=(83, 0), bc="x0", permute=True)
+    b = W.random_vector(A.n_rows, 83, W.BVEC)
+    _, _, full, _ = orc.pcg(A, b, precond=1)
+    x1, st1, it1, _ = orc.pcg(A, b, precond=1, maxit=full // 2)
+    assert st1 == orc.NOT_CONVERGED
+    x2, st2, it2, rr2 = orc.pcg(A, b, x0=x1, precond=1)
+    assert st2 == orc.OK and rr2 <= 1e-8
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16"])
+def test_ir_cg_reaches_fp64_residual(orc, kind):
+    A = W.tet_p1(6, "elastic", seed=(84, 0), bc="x0", permute=True)
+    b = W.random_vector(A.n_rows, 84, W.BVEC)
+    if kind == "f32":
+        a = orc.round_f32(A.val)
+    else:
+        a = orc.bf16_bits_to_f32(orc.round_bf16(A.val))
+    x, st, outer, inner, rr = orc.ir_cg(A, a, b, precond=1, rtol=1e-8,
+                                        inner_rtol=1e-2)
+    assert st == orc.OK and rr <= 1e-8
+    assert outer >= 2          # one low-precision solve cannot reach 1e-8
+    D = A.to_dense()
+    xs = np.linalg.solve(D, b)
+    kappa = np.linalg.cond(D)
+    assert np.linalg.norm(x - xs) <= 2e-8 * kappa * np.linalg.norm(xs)
