@@ -1,0 +1,231 @@
+/*
+ * fespmv -- FP64 sparse matrix-vector products and conjugate-gradient solves
+ * for matrices assembled from unstructured finite element meshes, on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation is y = A x for a sparse A given in CSR form (paper: section
+ * "Description of Current GPU Methods", statement of the SpMV problem), and
+ * the Jacobi-preconditioned conjugate-gradient solve of A x = b built around
+ * it (paper: sections "Computational Cost of the Finite Element Method" and
+ * "Description of Current GPU Methods": the solver performs at least one
+ * SpMV per iteration).  The matrix is re-packed once into a row-grouped,
+ * column-interleaved layout (paper: section "Development of Novel GPU
+ * Algorithms"; the pattern is fixed and only values change between Newton
+ * steps, section "Cost of Reordering Matrix Values").
+ *
+ * Conventions for every entry point:
+ *  - Every call returns an fs_status (int32_t).  FS_OK is 0.  The library
+ *    never aborts and never throws across this interface; fs_last_error()
+ *    returns a thread-local description of the last non-OK status.
+ *  - Vector and CSR array pointers are DEVICE pointers on the device that
+ *    is current when the call is made (the device the handle was created
+ *    on).  They stay owned by the caller; the library never frees them and
+ *    keeps no reference to them after the call (blocking calls) or after
+ *    the stream reaches the call (asynchronous calls).
+ *  - Indices are 0-based int32.  nnz must be below 2^31.
+ *  - Asynchronous calls are ordered on the given stream (0 = the null
+ *    stream).  A device fault raised by an asynchronous call is reported as
+ *    FS_E_HIP by the next call that synchronises.
+ *  - One handle must not be used from two streams at the same time;
+ *    different handles are independent.
+ */
+#ifndef FESPMV_H
+#define FESPMV_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef int32_t fs_status;
+enum {
+    FS_OK = 0,
+    FS_E_ARG = 1,            /* NULL pointer, negative size, k out of range  */
+    FS_E_BAD_CSR = 2,        /* malformed row pointer, column out of range,
+                                duplicate column in a row                   */
+    FS_E_NOT_SQUARE = 3,     /* operation needs a square matrix             */
+    FS_E_OOM = 4,            /* device or host allocation failed            */
+    FS_E_BUDGET = 5,         /* request exceeds the configured memory budget */
+    FS_E_HIP = 6,            /* HIP runtime error (message has the details) */
+    FS_E_NOT_CONVERGED = 7,  /* maxit reached; x holds the last iterate     */
+    FS_E_BREAKDOWN = 8,      /* p^T A p <= 0 or a non-finite CG scalar      */
+    FS_E_UNSUPPORTED = 9     /* option combination not implemented          */
+};
+
+/* Thread-local message for the last non-OK status returned on this thread
+ * (empty string if none).  The pointer stays valid until the next call on
+ * the same thread. */
+const char *fs_last_error(void);
+
+/* ----------------------------------------------------------- the matrix */
+typedef struct fs_csr *fs_csr_t;
+
+enum {  /* fs_csr_opts.reorder */
+    FS_REORDER_AUTO = 0,  /* reverse Cuthill-McKee when it shortens the mean
+                             |i - j| of the non-zeros, else none           */
+    FS_REORDER_NONE = 1,  /* keep the caller's numbering (rows may still be
+                             sorted by length inside sort windows)         */
+    FS_REORDER_RCM = 2,   /* reverse Cuthill-McKee on the pattern of A+A^T */
+    FS_REORDER_USER = 3   /* use opts.perm                                 */
+};
+
+enum {  /* bit mask, fs_csr_opts.dtypes and csr_add_dtype() */
+    FS_DT_F64 = 1,
+    FS_DT_F32 = 2,        /* FP32 copy of the values, rounded to nearest  */
+    FS_DT_BF16 = 4        /* BF16 copy: FP64 -> FP32 -> BF16, each to
+                             nearest, ties to even                         */
+};
+
+typedef struct fs_csr_opts {
+    int32_t reorder;       /* FS_REORDER_*                                   */
+    const int32_t *perm;   /* HOST array of n_rows entries for
+                              FS_REORDER_USER: new row i is old row perm[i] */
+    int32_t sort_window;   /* rows are ordered longest-first (stable) inside
+                              consecutive windows of this many rows, after
+                              the reordering; 1 disables; 0 = default 256  */
+    int32_t threshold;     /* most slots one lane may own before the row is
+                              spread over more lanes; 0 = default 16       */
+    int32_t lanes_min;     /* lanes per row bounds, powers of two in 1..64; */
+    int32_t lanes_max;     /*   0 = defaults 1 and 64                       */
+    int32_t dtypes;        /* extra low-precision copies (FS_DT_F32/BF16)   */
+    int32_t reserved[8];   /* must be zero                                   */
+} fs_csr_opts;
+
+/* Fill *o with the defaults (AUTO reorder, window 256, threshold 16,
+ * lanes 1..64, FP64 only). */
+fs_status csr_opts_default(fs_csr_opts *o);
+
+/* Build the layout of an n_rows x n_cols CSR matrix.  rowptr (n_rows+1),
+ * colind (nnz) and vals (nnz) are device arrays; columns may be unsorted
+ * inside a row but must be unique and in [0, n_cols).  opts may be NULL
+ * (defaults).  The call reads the structure on the host, builds the row
+ * permutation, groups and slot map, and scatters the values on the device.
+ * It synchronises stream s before returning, after which the caller may
+ * free or reuse its arrays.  *out receives the handle.
+ * Errors: FS_E_ARG, FS_E_BAD_CSR, FS_E_OOM, FS_E_HIP, FS_E_UNSUPPORTED. */
+fs_status csr_create(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                     const int32_t *rowptr, const int32_t *colind,
+                     const double *vals, const fs_csr_opts *opts,
+                     hipStream_t s, fs_csr_t *out);
+
+/* New values for the same pattern (vals in the CSR order that csr_create
+ * saw), refreshing any low-precision copies.  Asynchronous on s. */
+fs_status csr_update_values(fs_csr_t A, const double *vals, hipStream_t s);
+
+/* Materialise a low-precision copy (FS_DT_F32 or FS_DT_BF16) of the values
+ * for mixed-precision solves.  Synchronises s. */
+fs_status csr_add_dtype(fs_csr_t A, int32_t dtype, hipStream_t s);
+
+typedef struct fs_csr_stats {
+    int32_t n_rows, n_cols;
+    int64_t nnz;
+    int64_t slots;            /* padded slots, >= nnz                       */
+    int32_t n_groups;         /* row groups (one wavefront each)            */
+    int32_t reorder;          /* reordering actually applied (FS_REORDER_*) */
+    double padding;           /* (slots - nnz) / slots                      */
+    int64_t bytes_algorithmic;/* 12 nnz + 8 n_cols + 8 n_rows: compulsory
+                                 traffic of one FP64 product                */
+    int64_t bytes_layout;     /* 12 slots + 16 n_groups + 8 n_cols + 8 n_rows */
+    int32_t groups_by_lanes[7];/* groups with 1,2,4,...,64 lanes per row    */
+    int32_t dtypes;           /* FS_DT_* copies held                        */
+    double mean_band_before;  /* mean |i - j| over non-zeros, input order  */
+    double mean_band_after;   /* same, layout order                         */
+    double t_build_ms;        /* wall time of csr_create                    */
+    int64_t device_bytes;     /* device memory held by the handle          */
+} fs_csr_stats;
+
+fs_status csr_info(fs_csr_t A, fs_csr_stats *st);
+
+/* Copy the layout's row permutation to a HOST array of n_rows entries:
+ * layout row i is row perm[i] of the caller's matrix. */
+fs_status csr_get_perm(fs_csr_t A, int32_t *perm_host);
+
+/* Host-only dry run of the layout builder on HOST arrays (no device memory
+ * is touched, no GPU needed): the same validation, reordering, grouping and
+ * slot assignment csr_create performs.  Outputs (each may be NULL):
+ * n_groups, slots; groups: 4 int32 per group {first element / 64, first
+ * layout row, rows, slots per lane | log2(lanes per row) << 24}; slot_col:
+ * layout column of every slot (-1 = padding); map: slot of every CSR
+ * position; perm: layout row i is caller row perm[i].  Call once with NULL
+ * arrays to learn the sizes. */
+fs_status csr_layout_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                          const int32_t *rowptr, const int32_t *colind,
+                          const fs_csr_opts *opts, int32_t *n_groups,
+                          int64_t *slots, int32_t *groups, int32_t *slot_col,
+                          int32_t *map, int32_t *perm);
+
+/* Free everything the handle owns (after synchronising the device).  NULL
+ * is a no-op. */
+fs_status csr_destroy(fs_csr_t A);
+
+/* --------------------------------------------------------------- products */
+/* y = A x in the caller's numbering (x has n_cols, y n_rows entries).  x and
+ * y must not alias.  Asynchronous on s. */
+fs_status spmv(fs_csr_t A, const double *x, double *y, hipStream_t s);
+
+/* y' = A' x' in the layout numbering, A' = P A P^T (square matrices only):
+ * x'(i) = x(perm[i]) and y'(i) = y(perm[i]) (paper: section "ELL-WARP with
+ * row reordering (K1r)" -- an iterative solver keeps its vectors in this
+ * numbering and never pays the final re-mapping).  Asynchronous on s. */
+fs_status spmv_perm(fs_csr_t A, const double *xp, double *yp, hipStream_t s);
+
+enum { FS_TO_LAYOUT = 0, FS_FROM_LAYOUT = 1 };
+/* out(i) = in(perm[i]) (FS_TO_LAYOUT) or out(perm[i]) = in(i)
+ * (FS_FROM_LAYOUT); n_rows entries; in and out must not alias. */
+fs_status csr_permute(fs_csr_t A, int32_t dir, const double *in, double *out,
+                      hipStream_t s);
+
+/* Y = A X for k right-hand sides, 1 <= k <= 16.  X is n_cols x k and Y is
+ * n_rows x k, row-major with row strides ldx >= k and ldy >= k (elements).
+ * Asynchronous on s. */
+fs_status spmm(fs_csr_t A, int32_t k, const double *X, int64_t ldx,
+               double *Y, int64_t ldy, hipStream_t s);
+
+/* --------------------------------------------------------------- solvers */
+enum { FS_PC_NONE = 0, FS_PC_JACOBI = 1 };
+enum { FS_PREC_F64 = 0, FS_PREC_IR_F32 = 1, FS_PREC_IR_BF16 = 2 };
+
+typedef struct fs_cg_opts {
+    double rtol;          /* stop when |b - A x|_2 <= rtol |b|_2 (true
+                             residual, checked in FP64); default 1e-8      */
+    int32_t maxit;        /* iteration limit (inner iterations for IR);
+                             0 = default 20000                              */
+    int32_t precond;      /* FS_PC_*; default JACOBI                         */
+    int32_t precision;    /* FS_PREC_*; default F64                          */
+    double inner_rtol;    /* IR: inner solve tolerance; 0 = default 1e-2    */
+    int32_t check_every;  /* iterations between host convergence checks
+                             (one captured graph); 0 = default 32           */
+    int32_t x0_zero;      /* 1: start from x = 0 and ignore x on input      */
+    int32_t use_graph;    /* 1: replay chunks as HIP graphs (default 1)    */
+    int32_t max_outer;    /* IR: refinement steps; 0 = default 50           */
+    int32_t reserved[6];  /* must be zero                                    */
+} fs_cg_opts;
+
+fs_status cg_opts_default(fs_cg_opts *o);
+
+typedef struct fs_cg_info {
+    int32_t status;       /* same value the call returned                   */
+    int32_t iters;        /* CG iterations (F64) / inner iterations (IR)    */
+    int32_t outer;        /* IR refinement steps (0 for F64)                */
+    int32_t replacements; /* residual replacements performed               */
+    double relres;        /* true relative residual |b - A x| / |b| (FP64) */
+    double ms;            /* wall time of the call                          */
+    double bytes;         /* algorithmic HBM bytes moved by the solve       */
+} fs_cg_info;
+
+/* Solve A x = b (A square, symmetric positive definite).  b and x are
+ * device vectors in the caller's numbering; x holds the initial guess on
+ * entry (unless opts->x0_zero) and the solution on return.  Blocking: the
+ * call synchronises stream s.  opts NULL = defaults; info may be NULL.
+ * Returns FS_OK when the true residual meets rtol, FS_E_NOT_CONVERGED
+ * (x = last iterate), FS_E_BREAKDOWN, or an argument/runtime error. */
+fs_status cg_solve(fs_csr_t A, const double *b, double *x,
+                   const fs_cg_opts *opts, fs_cg_info *info, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FESPMV_H */

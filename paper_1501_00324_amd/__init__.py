@@ -1,0 +1,349 @@
+"""Python binding of libfespmv (FP64 FEM SpMV and CG on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libfespmv.so``.  PyTorch supplies device memory and streams;
+the names mirror the C ABI in ``include/fespmv.h``.
+
+There is no CPU fallback: if the library cannot be built or loaded, or no
+GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+from . import _build
+
+FS_OK, FS_E_ARG, FS_E_BAD_CSR, FS_E_NOT_SQUARE, FS_E_OOM, FS_E_BUDGET, \
+    FS_E_HIP, FS_E_NOT_CONVERGED, FS_E_BREAKDOWN, FS_E_UNSUPPORTED = range(10)
+STATUS_NAMES = {0: "FS_OK", 1: "FS_E_ARG", 2: "FS_E_BAD_CSR",
+                3: "FS_E_NOT_SQUARE", 4: "FS_E_OOM", 5: "FS_E_BUDGET",
+                6: "FS_E_HIP", 7: "FS_E_NOT_CONVERGED", 8: "FS_E_BREAKDOWN",
+                9: "FS_E_UNSUPPORTED"}
+REORDER_AUTO, REORDER_NONE, REORDER_RCM, REORDER_USER = range(4)
+DT_F64, DT_F32, DT_BF16 = 1, 2, 4
+PC_NONE, PC_JACOBI = 0, 1
+PREC_F64, PREC_IR_F32, PREC_IR_BF16 = 0, 1, 2
+TO_LAYOUT, FROM_LAYOUT = 0, 1
+
+
+class FsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class CsrOpts(C.Structure):
+    _fields_ = [("reorder", C.c_int32), ("perm", C.c_void_p),
+                ("sort_window", C.c_int32), ("threshold", C.c_int32),
+                ("lanes_min", C.c_int32), ("lanes_max", C.c_int32),
+                ("dtypes", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+class CsrStats(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32),
+                ("nnz", C.c_int64), ("slots", C.c_int64),
+                ("n_groups", C.c_int32), ("reorder", C.c_int32),
+                ("padding", C.c_double), ("bytes_algorithmic", C.c_int64),
+                ("bytes_layout", C.c_int64),
+                ("groups_by_lanes", C.c_int32 * 7), ("dtypes", C.c_int32),
+                ("mean_band_before", C.c_double),
+                ("mean_band_after", C.c_double),
+                ("t_build_ms", C.c_double), ("device_bytes", C.c_int64)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name == "groups_by_lanes" else v
+        return d
+
+
+class CgOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32),
+                ("precond", C.c_int32), ("precision", C.c_int32),
+                ("inner_rtol", C.c_double), ("check_every", C.c_int32),
+                ("x0_zero", C.c_int32), ("use_graph", C.c_int32),
+                ("max_outer", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class CgInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32),
+                ("outer", C.c_int32), ("replacements", C.c_int32),
+                ("relres", C.c_double), ("ms", C.c_double),
+                ("bytes", C.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+# every symbol include/fespmv.h declares
+EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
+           "csr_layout_host",
+           "csr_update_values", "csr_add_dtype", "csr_info", "csr_get_perm",
+           "csr_destroy", "spmv", "spmv_perm", "csr_permute", "spmm",
+           "cg_opts_default", "cg_solve"]
+
+_lib = None
+
+
+def lib_path():
+    return _build.LIB
+
+
+def load(build_if_missing=True):
+    """Load libfespmv.so (building it with hipcc when absent or stale)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if build_if_missing and _build.needs_build():
+        _build.build()
+    if not os.path.exists(_build.LIB):
+        raise FsError(FS_E_HIP, "libfespmv.so is not built")
+    L = C.CDLL(_build.LIB)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    P = C.POINTER
+    L.fs_last_error.restype = C.c_char_p
+    L.fs_last_error.argtypes = []
+    sigs = {
+        "csr_opts_default": [P(CsrOpts)],
+        "csr_create": [i32, i32, i64, vp, vp, vp, P(CsrOpts), vp, P(vp)],
+        "csr_layout_host": [i32, i32, i64, vp, vp, P(CsrOpts), P(i32),
+                            P(i64), vp, vp, vp, vp],
+        "csr_update_values": [vp, vp, vp],
+        "csr_add_dtype": [vp, i32, vp],
+        "csr_info": [vp, P(CsrStats)],
+        "csr_get_perm": [vp, vp],
+        "csr_destroy": [vp],
+        "spmv": [vp, vp, vp, vp],
+        "spmv_perm": [vp, vp, vp, vp],
+        "csr_permute": [vp, i32, vp, vp, vp],
+        "spmm": [vp, i32, vp, i64, vp, i64, vp],
+        "cg_opts_default": [P(CgOpts)],
+        "cg_solve": [vp, vp, vp, P(CgOpts), P(CgInfo), vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int32
+    _lib = L
+    return L
+
+
+def last_error():
+    return load().fs_last_error().decode()
+
+
+def _check(status):
+    if status != FS_OK:
+        raise FsError(status, last_error())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t, dtype=None, n=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (checked)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise FsError(FS_E_ARG, "%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise FsError(FS_E_ARG, "%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise FsError(FS_E_ARG, "%s must be %s" % (name, dtype))
+    if n is not None and t.numel() != n:
+        raise FsError(FS_E_ARG, "%s has %d entries, expected %d"
+                      % (name, t.numel(), n))
+    return t.data_ptr() if t.numel() else None
+
+
+class Matrix:
+    """Owning wrapper of an fs_csr_t handle."""
+
+    def __init__(self, handle, n_rows, n_cols, nnz):
+        self.handle = handle
+        self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, nnz
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        if self.handle:
+            load().csr_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def _h(self):
+        if not self.handle:
+            raise FsError(FS_E_ARG, "matrix handle already destroyed")
+        return self.handle
+
+
+def csr_opts(**kw):
+    o = CsrOpts()
+    load().csr_opts_default(C.byref(o))
+    perm = kw.pop("perm", None)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    if perm is not None:
+        import numpy as np
+        arr = np.ascontiguousarray(perm, dtype=np.int32)
+        o._perm_keep = arr
+        o.perm = arr.ctypes.data
+        o.reorder = REORDER_USER
+    return o
+
+
+def csr_create(rowptr, col, val, n_rows=None, n_cols=None, stream=None,
+               **opts):
+    """Build the layout from device CSR tensors (int32, int32, float64)."""
+    import torch
+    L = load()
+    n_rows = rowptr.numel() - 1 if n_rows is None else n_rows
+    n_cols = n_rows if n_cols is None else n_cols
+    nnz = col.numel()
+    o = csr_opts(**opts)
+    h = C.c_void_p()
+    _check(L.csr_create(n_rows, n_cols, nnz,
+                        _ptr(rowptr, torch.int32, n_rows + 1, "rowptr"),
+                        _ptr(col, torch.int32, None, "col"),
+                        _ptr(val, torch.float64, nnz, "val"),
+                        C.byref(o), _stream(stream), C.byref(h)))
+    return Matrix(h.value, n_rows, n_cols, nnz)
+
+
+def csr_layout_host(rowptr, col, n_rows=None, n_cols=None, **opts):
+    """Host-only layout dry run on numpy arrays; returns a dict with
+    groups (n_groups x 4), slot_col, map and perm."""
+    import numpy as np
+    L = load()
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    n_rows = len(rowptr) - 1 if n_rows is None else n_rows
+    n_cols = n_rows if n_cols is None else n_cols
+    o = csr_opts(**opts)
+    ng = C.c_int32()
+    ns = C.c_int64()
+    _check(L.csr_layout_host(n_rows, n_cols, len(col), rowptr.ctypes.data,
+                             col.ctypes.data, C.byref(o), C.byref(ng),
+                             C.byref(ns), None, None, None, None))
+    groups = np.zeros((ng.value, 4), dtype=np.int32)
+    slot_col = np.zeros(ns.value, dtype=np.int32)
+    mp = np.zeros(len(col), dtype=np.int32)
+    perm = np.zeros(n_rows, dtype=np.int32)
+    _check(L.csr_layout_host(n_rows, n_cols, len(col), rowptr.ctypes.data,
+                             col.ctypes.data, C.byref(o), C.byref(ng),
+                             C.byref(ns), groups.ctypes.data,
+                             slot_col.ctypes.data, mp.ctypes.data,
+                             perm.ctypes.data))
+    return dict(groups=groups, slot_col=slot_col, map=mp, perm=perm,
+                slots=ns.value)
+
+
+def csr_update_values(A, val, stream=None):
+    import torch
+    _check(load().csr_update_values(A._h, _ptr(val, torch.float64, A.nnz,
+                                                 "val"), _stream(stream)))
+
+
+def csr_add_dtype(A, dtype, stream=None):
+    _check(load().csr_add_dtype(A._h, int(dtype), _stream(stream)))
+
+
+def csr_info(A):
+    st = CsrStats()
+    _check(load().csr_info(A._h, C.byref(st)))
+    return st.as_dict()
+
+
+def csr_get_perm(A):
+    import numpy as np
+    out = np.empty(A.n_rows, dtype=np.int32)
+    _check(load().csr_get_perm(A._h, out.ctypes.data))
+    return out
+
+
+def csr_destroy(A):
+    A.close()
+
+
+def spmv(A, x, y=None, stream=None):
+    import torch
+    if y is None:
+        y = torch.empty(A.n_rows, dtype=torch.float64, device=x.device)
+    _check(load().spmv(A._h, _ptr(x, torch.float64, A.n_cols, "x"),
+                       _ptr(y, torch.float64, A.n_rows, "y"),
+                       _stream(stream)))
+    return y
+
+
+def spmv_perm(A, xp, yp=None, stream=None):
+    import torch
+    if yp is None:
+        yp = torch.empty(A.n_rows, dtype=torch.float64, device=xp.device)
+    _check(load().spmv_perm(A._h, _ptr(xp, torch.float64, A.n_cols, "x"),
+                            _ptr(yp, torch.float64, A.n_rows, "y"),
+                            _stream(stream)))
+    return yp
+
+
+def csr_permute(A, direction, inp, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty_like(inp)
+    _check(load().csr_permute(A._h, int(direction),
+                              _ptr(inp, torch.float64, A.n_rows, "in"),
+                              _ptr(out, torch.float64, A.n_rows, "out"),
+                              _stream(stream)))
+    return out
+
+
+def spmm(A, X, Y=None, stream=None):
+    import torch
+    k = X.shape[1]
+    if Y is None:
+        Y = torch.empty((A.n_rows, k), dtype=torch.float64, device=X.device)
+    _check(load().spmm(A._h, k, _ptr(X, torch.float64, A.n_cols * k, "X"),
+                       X.stride(0), _ptr(Y, torch.float64, A.n_rows * k, "Y"),
+                       Y.stride(0), _stream(stream)))
+    return Y
+
+
+def cg_opts(**kw):
+    o = CgOpts()
+    load().cg_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def cg_solve(A, b, x=None, stream=None, check=True, **opts):
+    """Solve A x = b; returns (x, info dict).  With check=False a
+    not-converged or breakdown status is reported in info instead of
+    raised."""
+    import torch
+    if x is None:
+        x = torch.zeros(A.n_rows, dtype=torch.float64, device=b.device)
+        opts.setdefault("x0_zero", 1)
+    o = cg_opts(**opts)
+    info = CgInfo()
+    st = load().cg_solve(A._h, _ptr(b, torch.float64, A.n_rows, "b"),
+                         _ptr(x, torch.float64, A.n_rows, "x"), C.byref(o),
+                         C.byref(info), _stream(stream))
+    d = info.as_dict()
+    d["message"] = last_error() if st != FS_OK else ""
+    if st != FS_OK and (check or st not in (FS_E_NOT_CONVERGED,
+                                            FS_E_BREAKDOWN)):
+        raise FsError(st, d["message"])
+    return x, d

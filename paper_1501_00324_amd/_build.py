@@ -1,0 +1,65 @@
+"""Build libfespmv.so (gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libfespmv.so")
+SOURCES = ["api.cpp", "layout.cpp", "kernels.hip"]
+ARCH = os.environ.get("FESPMV_ARCH", "gfx950")
+
+FLAGS = [
+    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+    # packed FP32 instructions stay off (the compiler would otherwise form
+    # them from scalar float code)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function",
+]
+
+
+def sources():
+    return [os.path.join(CSRC, s) for s in SOURCES]
+
+
+def needs_build():
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    deps = sources() + [os.path.join(CSRC, "internal.h"),
+                        os.path.join(HERE, "..", "include", "fespmv.h")]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose=False):
+    objs = []
+    procs = []
+    for src in sources():
+        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
+        lang = [] if src.endswith(".hip") else ["-x", "hip"]
+        cmd = ["hipcc", *FLAGS, *lang, "-c", src, "-o", obj]
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                            stderr=subprocess.STDOUT)))
+        objs.append(obj)
+    for cmd, p in procs:
+        out, _ = p.communicate()
+        text = out.decode(errors="replace")
+        text = "\n".join(l for l in text.splitlines()
+                         if "packed-fp32-ops" not in l)
+        if p.returncode != 0:
+            raise RuntimeError("hipcc failed: %s\n%s" % (" ".join(cmd), text))
+        if verbose and text.strip():
+            print(text, file=sys.stderr)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["hipcc", "--offload-arch=" + ARCH, "-shared",
+                           "-fPIC", *objs, "-o", tmp])
+    os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,591 @@
+// The C ABI: handle lifetime, products and the CG driver.
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+namespace fs {
+
+namespace {
+thread_local std::string g_last_error;
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(
+               steady_clock::now().time_since_epoch()).count();
+}
+
+struct DeviceGuard {
+    int prev = -1, want;
+    explicit DeviceGuard(int d) : want(d)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != want)
+            (void)hipSetDevice(want);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+fs_status dalloc(T **p, int64_t count, int64_t &acct)
+{
+    *p = nullptr;
+    if (count <= 0) return FS_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p),
+                             size_t(count) * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_error(e == hipErrorOutOfMemory ? FS_E_OOM : FS_E_HIP,
+                         "hipMalloc(%lld bytes): %s",
+                         (long long)(count * int64_t(sizeof(T))),
+                         hipGetErrorString(e));
+    }
+    acct += count * int64_t(sizeof(T));
+    return FS_OK;
+}
+
+template <class T> void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_cg(CgWork &w)
+{
+    if (w.graph) (void)hipGraphExecDestroy(w.graph);
+    w.graph = nullptr;
+    dfree(w.x); dfree(w.r); dfree(w.p); dfree(w.q); dfree(w.b);
+    dfree(w.dinv); dfree(w.partials); dfree(w.sc);
+    if (w.sc_host) (void)hipHostFree(w.sc_host);
+    w.sc_host = nullptr;
+    if (w.done_ev) (void)hipEventDestroy(w.done_ev);
+    w.done_ev = nullptr;
+    if (w.stream) (void)hipStreamDestroy(w.stream);
+    w.stream = nullptr;
+    w.n = 0;
+}
+
+void free_handle(fs_csr *A)
+{
+    free_cg(A->cg);
+    dfree(A->d_groups); dfree(A->d_val); dfree(A->d_val_f32);
+    dfree(A->d_val_bf16); dfree(A->d_col); dfree(A->d_map);
+    dfree(A->d_perm); dfree(A->d_iperm); dfree(A->d_xtmp);
+}
+
+fs_status check_handle(const fs_csr *A)
+{
+    if (!A) return set_error(FS_E_ARG, "NULL matrix handle");
+    return FS_OK;
+}
+
+}  // namespace
+
+fs_status set_error(fs_status code, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace fs
+
+using namespace fs;
+
+extern "C" {
+
+const char *fs_last_error(void) { return g_last_error.c_str(); }
+
+fs_status csr_opts_default(fs_csr_opts *o)
+{
+    if (!o) return set_error(FS_E_ARG, "NULL opts");
+    std::memset(o, 0, sizeof *o);
+    o->reorder = FS_REORDER_AUTO;
+    o->sort_window = 256;
+    o->threshold = 16;
+    o->lanes_min = 1;
+    o->lanes_max = 64;
+    return FS_OK;
+}
+
+fs_status cg_opts_default(fs_cg_opts *o)
+{
+    if (!o) return set_error(FS_E_ARG, "NULL opts");
+    std::memset(o, 0, sizeof *o);
+    o->rtol = 1e-8;
+    o->maxit = 20000;
+    o->precond = FS_PC_JACOBI;
+    o->precision = FS_PREC_F64;
+    o->inner_rtol = 1e-2;
+    o->check_every = 32;
+    o->use_graph = 1;
+    o->max_outer = 50;
+    return FS_OK;
+}
+
+fs_status csr_create(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                     const int32_t *rowptr, const int32_t *colind,
+                     const double *vals, const fs_csr_opts *opts,
+                     hipStream_t s, fs_csr_t *out)
+{
+    const double t0 = now_ms();
+    if (!out) return set_error(FS_E_ARG, "NULL output handle pointer");
+    *out = nullptr;
+    if (n_rows < 0 || n_cols < 0 || nnz < 0)
+        return set_error(FS_E_ARG, "negative size (%d x %d, nnz %lld)",
+                         n_rows, n_cols, (long long)nnz);
+    if (nnz >= INT32_MAX)
+        return set_error(FS_E_UNSUPPORTED, "nnz must be below 2^31");
+    if (!rowptr || (nnz > 0 && (!colind || !vals)))
+        return set_error(FS_E_ARG, "NULL CSR array");
+    fs_csr_opts o;
+    csr_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.dtypes & ~(FS_DT_F64 | FS_DT_F32 | FS_DT_BF16))
+        return set_error(FS_E_ARG, "unknown dtype bits 0x%x", o.dtypes);
+
+    int dev = 0;
+    FS_HIP_TRY(hipGetDevice(&dev));
+    std::vector<int32_t> h_rp(static_cast<size_t>(n_rows) + 1);
+    std::vector<int32_t> h_col(static_cast<size_t>(nnz));
+    FS_HIP_TRY(hipMemcpyAsync(h_rp.data(), rowptr,
+                              sizeof(int32_t) * (size_t(n_rows) + 1),
+                              hipMemcpyDeviceToHost, s));
+    if (nnz > 0)
+        FS_HIP_TRY(hipMemcpyAsync(h_col.data(), colind,
+                                  sizeof(int32_t) * size_t(nnz),
+                                  hipMemcpyDeviceToHost, s));
+    FS_HIP_TRY(hipStreamSynchronize(s));
+
+    fs_csr *A = new (std::nothrow) fs_csr();
+    if (!A) return set_error(FS_E_OOM, "host allocation failed");
+    A->n_rows = n_rows;
+    A->n_cols = n_cols;
+    A->nnz = nnz;
+    A->device = dev;
+    fs_status st = build_layout(n_rows, n_cols, nnz, h_rp.data(),
+                                h_col.data(), o, A->host);
+    if (st != FS_OK) {
+        delete A;
+        return st;
+    }
+    HostLayout &L = A->host;
+    A->n_groups = int32_t(L.groups.size());
+    A->slots = L.slots;
+
+    auto fail = [&](fs_status code) {
+        (void)hipStreamSynchronize(s);
+        free_handle(A);
+        delete A;
+        return code;
+    };
+    int64_t &acct = A->device_bytes;
+    if ((st = dalloc(&A->d_groups, A->n_groups, acct)) ||
+        (st = dalloc(&A->d_val, A->slots, acct)) ||
+        (st = dalloc(&A->d_col, A->slots, acct)) ||
+        (st = dalloc(&A->d_map, nnz, acct)) ||
+        (st = dalloc(&A->d_perm, n_rows, acct)) ||
+        (st = dalloc(&A->d_iperm, n_rows, acct)) ||
+        (st = dalloc(&A->d_xtmp, n_cols, acct)))
+        return fail(st);
+    if (o.dtypes & FS_DT_F32)
+        if ((st = dalloc(&A->d_val_f32, A->slots, acct))) return fail(st);
+    if (o.dtypes & FS_DT_BF16)
+        if ((st = dalloc(&A->d_val_bf16, A->slots, acct))) return fail(st);
+
+    hipError_t e = hipSuccess;
+#define FS_CREATE_HIP(expr)                                                 \
+    if ((e = (expr)) != hipSuccess)                                         \
+        return fail(set_error(FS_E_HIP, "%s: %s", #expr, hipGetErrorString(e)))
+    if (A->n_groups)
+        FS_CREATE_HIP(hipMemcpyAsync(A->d_groups, L.groups.data(),
+                                     sizeof(Group) * L.groups.size(),
+                                     hipMemcpyHostToDevice, s));
+    if (A->slots) {
+        FS_CREATE_HIP(hipMemcpyAsync(A->d_col, L.slot_col.data(),
+                                     sizeof(int32_t) * size_t(A->slots),
+                                     hipMemcpyHostToDevice, s));
+        FS_CREATE_HIP(hipMemsetAsync(A->d_val, 0,
+                                     sizeof(double) * size_t(A->slots), s));
+        if (A->d_val_f32)
+            FS_CREATE_HIP(hipMemsetAsync(A->d_val_f32, 0,
+                                         sizeof(float) * size_t(A->slots), s));
+        if (A->d_val_bf16)
+            FS_CREATE_HIP(hipMemsetAsync(A->d_val_bf16, 0,
+                                         sizeof(uint16_t) * size_t(A->slots),
+                                         s));
+    }
+    if (nnz)
+        FS_CREATE_HIP(hipMemcpyAsync(A->d_map, L.map.data(),
+                                     sizeof(int32_t) * size_t(nnz),
+                                     hipMemcpyHostToDevice, s));
+    if (n_rows) {
+        FS_CREATE_HIP(hipMemcpyAsync(A->d_perm, L.perm.data(),
+                                     sizeof(int32_t) * size_t(n_rows),
+                                     hipMemcpyHostToDevice, s));
+        FS_CREATE_HIP(hipMemcpyAsync(A->d_iperm, L.iperm.data(),
+                                     sizeof(int32_t) * size_t(n_rows),
+                                     hipMemcpyHostToDevice, s));
+    }
+    FS_CREATE_HIP(launch_value_scatter(vals, A->d_map, nnz, A->d_val,
+                                       A->d_val_f32, A->d_val_bf16, s));
+    FS_CREATE_HIP(hipStreamSynchronize(s));
+#undef FS_CREATE_HIP
+    A->dtypes = FS_DT_F64 | (A->d_val_f32 ? FS_DT_F32 : 0) |
+                (A->d_val_bf16 ? FS_DT_BF16 : 0);
+    // the slot columns and map are on the device now; keep only what the
+    // info / permutation queries need on the host
+    std::vector<int32_t>().swap(L.slot_col);
+    std::vector<int32_t>().swap(L.map);
+    A->t_build_ms = now_ms() - t0;
+    *out = A;
+    return FS_OK;
+}
+
+fs_status csr_layout_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                          const int32_t *rowptr, const int32_t *colind,
+                          const fs_csr_opts *opts, int32_t *n_groups,
+                          int64_t *slots, int32_t *groups, int32_t *slot_col,
+                          int32_t *map, int32_t *perm)
+{
+    if (n_rows < 0 || n_cols < 0 || nnz < 0)
+        return set_error(FS_E_ARG, "negative size");
+    if (nnz >= INT32_MAX)
+        return set_error(FS_E_UNSUPPORTED, "nnz must be below 2^31");
+    if (!rowptr || (nnz > 0 && !colind))
+        return set_error(FS_E_ARG, "NULL CSR array");
+    fs_csr_opts o;
+    csr_opts_default(&o);
+    if (opts) o = *opts;
+    HostLayout L;
+    FS_TRY(build_layout(n_rows, n_cols, nnz, rowptr, colind, o, L));
+    if (n_groups) *n_groups = int32_t(L.groups.size());
+    if (slots) *slots = L.slots;
+    if (groups && !L.groups.empty())
+        std::memcpy(groups, L.groups.data(), sizeof(Group) * L.groups.size());
+    if (slot_col && L.slots)
+        std::memcpy(slot_col, L.slot_col.data(),
+                    sizeof(int32_t) * size_t(L.slots));
+    if (map && nnz) std::memcpy(map, L.map.data(), sizeof(int32_t) * size_t(nnz));
+    if (perm && n_rows)
+        std::memcpy(perm, L.perm.data(), sizeof(int32_t) * size_t(n_rows));
+    return FS_OK;
+}
+
+fs_status csr_update_values(fs_csr_t A, const double *vals, hipStream_t s)
+{
+    FS_TRY(check_handle(A));
+    if (!vals && A->nnz > 0) return set_error(FS_E_ARG, "NULL values");
+    DeviceGuard g(A->device);
+    FS_HIP_TRY(launch_value_scatter(vals, A->d_map, A->nnz, A->d_val,
+                                    A->d_val_f32, A->d_val_bf16, s));
+    return FS_OK;
+}
+
+fs_status csr_info(fs_csr_t A, fs_csr_stats *st)
+{
+    FS_TRY(check_handle(A));
+    if (!st) return set_error(FS_E_ARG, "NULL stats");
+    std::memset(st, 0, sizeof *st);
+    st->n_rows = A->n_rows;
+    st->n_cols = A->n_cols;
+    st->nnz = A->nnz;
+    st->slots = A->slots;
+    st->n_groups = A->n_groups;
+    st->reorder = A->host.reorder;
+    st->padding = A->slots ? double(A->slots - A->nnz) / double(A->slots) : 0.0;
+    st->bytes_algorithmic = 12 * A->nnz + 8 * int64_t(A->n_cols) +
+                            8 * int64_t(A->n_rows);
+    st->bytes_layout = 12 * A->slots + int64_t(sizeof(Group)) * A->n_groups +
+                       8 * int64_t(A->n_cols) + 8 * int64_t(A->n_rows);
+    for (int i = 0; i < 7; ++i) st->groups_by_lanes[i] = A->host.groups_by_lanes[i];
+    st->dtypes = A->dtypes;
+    st->mean_band_before = A->host.band_before;
+    st->mean_band_after = A->host.band_after;
+    st->t_build_ms = A->t_build_ms;
+    st->device_bytes = A->device_bytes;
+    return FS_OK;
+}
+
+fs_status csr_get_perm(fs_csr_t A, int32_t *perm_host)
+{
+    FS_TRY(check_handle(A));
+    if (!perm_host && A->n_rows > 0) return set_error(FS_E_ARG, "NULL perm");
+    if (A->n_rows)
+        std::memcpy(perm_host, A->host.perm.data(),
+                    sizeof(int32_t) * size_t(A->n_rows));
+    return FS_OK;
+}
+
+fs_status csr_destroy(fs_csr_t A)
+{
+    if (!A) return FS_OK;
+    DeviceGuard g(A->device);
+    (void)hipDeviceSynchronize();
+    free_handle(A);
+    delete A;
+    return FS_OK;
+}
+
+fs_status spmv(fs_csr_t A, const double *x, double *y, hipStream_t s)
+{
+    FS_TRY(check_handle(A));
+    if ((!x && A->n_cols) || (!y && A->n_rows))
+        return set_error(FS_E_ARG, "NULL vector");
+    if (x == y && x) return set_error(FS_E_ARG, "x and y must not alias");
+    DeviceGuard g(A->device);
+    const HostLayout &L = A->host;
+    if (L.identity) {
+        FS_HIP_TRY(launch_spmv_f64(A, x, y, nullptr, s));
+    } else if (L.symmetric_relabel) {
+        // x' = x(perm), then y(perm[row]) = (A' x')[row] in the epilogue
+        FS_HIP_TRY(launch_gather(A->n_cols, A->d_perm, x, A->d_xtmp, s));
+        FS_HIP_TRY(launch_spmv_f64(A, A->d_xtmp, y, A->d_perm, s));
+    } else {
+        FS_HIP_TRY(launch_spmv_f64(A, x, y, A->d_perm, s));
+    }
+    return FS_OK;
+}
+
+fs_status spmv_perm(fs_csr_t A, const double *xp, double *yp, hipStream_t s)
+{
+    FS_TRY(check_handle(A));
+    if (A->n_rows != A->n_cols)
+        return set_error(FS_E_NOT_SQUARE, "spmv_perm needs a square matrix");
+    if ((!xp || !yp) && A->n_rows) return set_error(FS_E_ARG, "NULL vector");
+    if (xp == yp && xp) return set_error(FS_E_ARG, "x and y must not alias");
+    DeviceGuard g(A->device);
+    FS_HIP_TRY(launch_spmv_f64(A, xp, yp, nullptr, s));
+    return FS_OK;
+}
+
+fs_status csr_permute(fs_csr_t A, int32_t dir, const double *in, double *out,
+                      hipStream_t s)
+{
+    FS_TRY(check_handle(A));
+    if ((!in || !out) && A->n_rows) return set_error(FS_E_ARG, "NULL vector");
+    if (in == out && in) return set_error(FS_E_ARG, "in and out must not alias");
+    DeviceGuard g(A->device);
+    if (dir == FS_TO_LAYOUT)
+        FS_HIP_TRY(launch_gather(A->n_rows, A->d_perm, in, out, s));
+    else if (dir == FS_FROM_LAYOUT)
+        FS_HIP_TRY(launch_scatter(A->n_rows, A->d_perm, in, out, s));
+    else
+        return set_error(FS_E_ARG, "unknown direction %d", dir);
+    return FS_OK;
+}
+
+fs_status spmm(fs_csr_t A, int32_t k, const double *X, int64_t ldx,
+               double *Y, int64_t ldy, hipStream_t s)
+{
+    (void)A; (void)k; (void)X; (void)ldx; (void)Y; (void)ldy; (void)s;
+    return set_error(FS_E_UNSUPPORTED, "spmm is not built yet");
+}
+
+fs_status csr_add_dtype(fs_csr_t A, int32_t dtype, hipStream_t s)
+{
+    (void)A; (void)dtype; (void)s;
+    return set_error(FS_E_UNSUPPORTED, "csr_add_dtype is not built yet");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- CG driver
+namespace fs {
+namespace {
+
+fs_status ensure_cg(fs_csr *A, int32_t precond)
+{
+    CgWork &w = A->cg;
+    const int32_t n = A->n_rows;
+    if (w.n != n || !w.sc) {
+        free_cg(w);
+        int64_t acct = 0;
+        FS_TRY(dalloc(&w.x, n, acct));
+        FS_TRY(dalloc(&w.r, n, acct));
+        FS_TRY(dalloc(&w.p, n, acct));
+        FS_TRY(dalloc(&w.q, n, acct));
+        FS_TRY(dalloc(&w.b, n, acct));
+        w.nparts = cg_partials_needed(A);
+        FS_TRY(dalloc(&w.partials, w.nparts, acct));
+        FS_TRY(dalloc(&w.sc, 1, acct));
+        FS_HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&w.sc_host),
+                                 sizeof(CgScalars), hipHostMallocDefault));
+        FS_HIP_TRY(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking));
+        FS_HIP_TRY(hipEventCreateWithFlags(&w.done_ev, hipEventDisableTiming));
+        A->device_bytes += acct;
+        w.n = n;
+    }
+    if (precond && !w.dinv) {
+        FS_TRY(dalloc(&w.dinv, n, A->device_bytes));
+    }
+    return FS_OK;
+}
+
+fs_status launch_iterations(fs_csr *A, int32_t pc, int32_t k, hipStream_t s)
+{
+    CgWork &w = A->cg;
+    for (int32_t i = 0; i < k; ++i) {
+        FS_HIP_TRY(launch_cg_spmv_dot(A, w, s));
+        FS_HIP_TRY(launch_cg_update(w, pc, s));
+        FS_HIP_TRY(launch_cg_pupdate(w, pc, s));
+    }
+    return FS_OK;
+}
+
+fs_status run_chunk(fs_csr *A, int32_t pc, int32_t k, bool use_graph)
+{
+    CgWork &w = A->cg;
+    hipStream_t s = w.stream;
+    if (!use_graph) return launch_iterations(A, pc, k, s);
+    if (!w.graph || w.graph_k != k || w.graph_pc != pc) {
+        if (w.graph) (void)hipGraphExecDestroy(w.graph);
+        w.graph = nullptr;
+        hipGraph_t graph = nullptr;
+        FS_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        fs_status st = launch_iterations(A, pc, k, s);
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (st != FS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess)
+            return set_error(FS_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&w.graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            w.graph = nullptr;
+            return set_error(FS_E_HIP, "graph instantiate: %s",
+                             hipGetErrorString(e));
+        }
+        w.graph_k = k;
+        w.graph_pc = pc;
+    }
+    FS_HIP_TRY(hipGraphLaunch(w.graph, s));
+    return FS_OK;
+}
+
+fs_status read_scalars(CgWork &w)
+{
+    FS_HIP_TRY(hipMemcpyAsync(w.sc_host, w.sc, sizeof(CgScalars),
+                              hipMemcpyDeviceToHost, w.stream));
+    FS_HIP_TRY(hipStreamSynchronize(w.stream));
+    return FS_OK;
+}
+
+fs_status cg_f64(fs_csr *A, const double *b, double *x, const fs_cg_opts &o,
+                 fs_cg_info &info, hipStream_t caller)
+{
+    CgWork &w = A->cg;
+    const int32_t n = A->n_rows, pc = o.precond;
+    FS_TRY(ensure_cg(A, pc));
+    hipStream_t s = w.stream;
+    // order after the caller's stream
+    FS_HIP_TRY(hipEventRecord(w.done_ev, caller));
+    FS_HIP_TRY(hipStreamWaitEvent(s, w.done_ev, 0));
+    const bool ident = A->host.identity;
+    if (ident) FS_HIP_TRY(hipMemcpyAsync(w.b, b, sizeof(double) * n,
+                                         hipMemcpyDeviceToDevice, s));
+    else FS_HIP_TRY(launch_gather(n, A->d_perm, b, w.b, s));
+    if (o.x0_zero) FS_HIP_TRY(hipMemsetAsync(w.x, 0, sizeof(double) * n, s));
+    else if (ident) FS_HIP_TRY(hipMemcpyAsync(w.x, x, sizeof(double) * n,
+                                              hipMemcpyDeviceToDevice, s));
+    else FS_HIP_TRY(launch_gather(n, A->d_perm, x, w.x, s));
+    FS_HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(CgScalars), s));
+    if (pc) FS_HIP_TRY(launch_diag_inv(A, w.dinv, w.sc, s));
+    FS_HIP_TRY(launch_cg_residual(A, w, pc, 0, o.rtol, o.maxit, o.x0_zero, s));
+    FS_TRY(read_scalars(w));
+    if (pc && w.sc_host->pad[0] > 0)
+        return set_error(FS_E_ARG, "Jacobi preconditioner: %d rows with a "
+                         "zero or non-finite diagonal", w.sc_host->pad[0]);
+    while (!w.sc_host->done) {
+        FS_TRY(run_chunk(A, pc, o.check_every, o.use_graph != 0));
+        FS_TRY(read_scalars(w));
+        if (w.sc_host->status == CG_RECURRENCE_MET) {
+            FS_HIP_TRY(launch_cg_residual(A, w, pc, 1, o.rtol, o.maxit, 0, s));
+            FS_TRY(read_scalars(w));
+            if (!w.sc_host->done)   // replaced residual: finish this iteration
+                FS_HIP_TRY(launch_cg_pupdate(w, pc, s));
+        }
+    }
+    const int32_t status = w.sc_host->status;
+    if (status != CG_CONVERGED) {
+        FS_HIP_TRY(launch_cg_residual(A, w, pc, 2, o.rtol, o.maxit, 0, s));
+        FS_TRY(read_scalars(w));
+    }
+    if (w.sc_host->bnorm2 == 0.0)
+        FS_HIP_TRY(hipMemsetAsync(w.x, 0, sizeof(double) * n, s));
+    if (ident) FS_HIP_TRY(hipMemcpyAsync(x, w.x, sizeof(double) * n,
+                                         hipMemcpyDeviceToDevice, s));
+    else FS_HIP_TRY(launch_scatter(n, A->d_perm, w.x, x, s));
+    FS_HIP_TRY(hipStreamSynchronize(s));
+    const CgScalars &h = *w.sc_host;
+    info.iters = h.iter;
+    info.replacements = h.replacements;
+    info.relres = h.bnorm2 > 0.0 ? std::sqrt(h.rr_true / h.bnorm2) : 0.0;
+    const double it_bytes = 12.0 * double(A->nnz) + (pc ? 104.0 : 88.0) * n;
+    const double spmv_bytes = 12.0 * double(A->nnz) + 16.0 * n;
+    info.bytes = h.iter * it_bytes +
+                 (2.0 + h.replacements + (status != CG_CONVERGED)) * spmv_bytes;
+    switch (status) {
+    case CG_CONVERGED: return FS_OK;
+    case CG_MAXIT:
+        return set_error(FS_E_NOT_CONVERGED,
+                         "CG: %d iterations, relative residual %.3e",
+                         h.iter, info.relres);
+    default:
+        return set_error(FS_E_BREAKDOWN,
+                         "CG breakdown after %d iterations (p.Ap = %.3e)",
+                         h.iter, h.gamma);
+    }
+}
+
+}  // namespace
+}  // namespace fs
+
+extern "C" fs_status cg_solve(fs_csr_t A, const double *b, double *x,
+                              const fs_cg_opts *opts, fs_cg_info *info,
+                              hipStream_t s)
+{
+    const double t0 = now_ms();
+    fs_cg_info local;
+    std::memset(&local, 0, sizeof local);
+    fs_status st = check_handle(A);
+    if (st == FS_OK && A->n_rows != A->n_cols)
+        st = set_error(FS_E_NOT_SQUARE, "cg_solve needs a square matrix");
+    if (st == FS_OK && A->n_rows > 0 && (!b || !x))
+        st = set_error(FS_E_ARG, "NULL vector");
+    fs_cg_opts o;
+    cg_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.rtol <= 0.0) o.rtol = 1e-8;
+    if (o.maxit <= 0) o.maxit = 20000;
+    if (o.check_every <= 0) o.check_every = 32;
+    if (o.inner_rtol <= 0.0) o.inner_rtol = 1e-2;
+    if (o.max_outer <= 0) o.max_outer = 50;
+    if (st == FS_OK && o.precond != FS_PC_NONE && o.precond != FS_PC_JACOBI)
+        st = set_error(FS_E_ARG, "unknown preconditioner %d", o.precond);
+    if (st == FS_OK && o.precision != FS_PREC_F64)
+        st = set_error(FS_E_UNSUPPORTED, "mixed precision is not built yet");
+    if (st == FS_OK && A->n_rows > 0) {
+        DeviceGuard g(A->device);
+        st = cg_f64(A, b, x, o, local, s);
+    }
+    local.status = st;
+    local.ms = now_ms() - t0;
+    if (info) *info = local;
+    return st;
+}

@@ -1,0 +1,331 @@
+// Host-side layout builder: CSR validation, locality reordering, row
+// grouping and the CSR-position -> slot map.
+//
+// The layout follows the row-grouped, column-interleaved idea of the paper
+// (section "Development of Novel GPU Algorithms": rows sorted by length,
+// grouped per warp, padded to the group's longest row, stored column-major;
+// several lanes per row when a row is long, ELL-WARP v2 (K2); columns
+// relabelled and sorted, K1r/K1rs).  Differences for gfx950: a group is one
+// 64-lane wavefront, rows are only sorted inside windows (the locality
+// order from reverse Cuthill-McKee is kept between windows because there is
+// no texture cache to hide a scrambled x), and each lane loads two adjacent
+// slots per access.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+namespace fs {
+namespace {
+
+// Pattern of A + A^T without the diagonal, rows sorted.  Only used for the
+// reordering, never for arithmetic.
+struct Graph {
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    int32_t n = 0;
+    int32_t deg(int32_t v) const { return int32_t(rp[v + 1] - rp[v]); }
+};
+
+Graph symmetric_graph(int32_t n, const int32_t *rowptr, const int32_t *col)
+{
+    // transpose pattern by counting sort: rows of T come out sorted
+    std::vector<int64_t> tp(size_t(n) + 1, 0);
+    int64_t nnz = rowptr[n];
+    for (int64_t k = 0; k < nnz; ++k) tp[size_t(col[k]) + 1]++;
+    for (int32_t i = 0; i < n; ++i) tp[i + 1] += tp[i];
+    std::vector<int32_t> ti(static_cast<size_t>(nnz));
+    {
+        std::vector<int64_t> pos(tp.begin(), tp.end() - 1);
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                ti[size_t(pos[col[k]]++)] = i;
+    }
+    Graph g;
+    g.n = n;
+    g.rp.assign(size_t(n) + 1, 0);
+    g.ci.reserve(size_t(nnz));
+    std::vector<int32_t> row;
+    for (int32_t i = 0; i < n; ++i) {
+        row.assign(col + rowptr[i], col + rowptr[i + 1]);
+        std::sort(row.begin(), row.end());
+        // merge row with column i of A (row i of T), dropping i itself
+        size_t a = 0, b = size_t(tp[i]), be = size_t(tp[i + 1]);
+        int32_t last = -1;
+        while (a < row.size() || b < be) {
+            int32_t v;
+            if (b >= be || (a < row.size() && row[a] <= ti[b])) v = row[a++];
+            else v = ti[b++];
+            if (v != last && v != i) g.ci.push_back(v);
+            last = v;
+        }
+        g.rp[i + 1] = int64_t(g.ci.size());
+    }
+    return g;
+}
+
+// Breadth-first levels from r over the component; returns eccentricity and
+// fills `last` with the last level.
+int32_t bfs_levels(const Graph &g, int32_t r, std::vector<int32_t> &stamp,
+                   int32_t tag, std::vector<int32_t> &queue,
+                   std::vector<int32_t> &last)
+{
+    queue.clear();
+    queue.push_back(r);
+    stamp[r] = tag;
+    size_t head = 0, level_start = 0;
+    int32_t ecc = 0;
+    while (true) {
+        size_t level_end = queue.size();
+        while (head < level_end) {
+            int32_t u = queue[head++];
+            for (int64_t k = g.rp[u]; k < g.rp[u + 1]; ++k) {
+                int32_t v = g.ci[size_t(k)];
+                if (stamp[v] != tag) {
+                    stamp[v] = tag;
+                    queue.push_back(v);
+                }
+            }
+        }
+        if (queue.size() == level_end) {
+            last.assign(queue.begin() + long(level_start),
+                        queue.begin() + long(level_end));
+            return ecc;
+        }
+        level_start = level_end;
+        ++ecc;
+    }
+}
+
+// Reverse Cuthill-McKee (Cuthill & McKee 1969; George & Liu's
+// pseudo-peripheral start).  order[i] = old index of new index i.
+std::vector<int32_t> rcm_order(const Graph &g)
+{
+    const int32_t n = g.n;
+    std::vector<int32_t> order;
+    order.reserve(size_t(n));
+    std::vector<char> visited(size_t(n), 0);
+    std::vector<int32_t> stamp(size_t(n), -1), queue, last, nb;
+    int32_t tag = 0;
+    for (int32_t s = 0; s < n; ++s) {
+        if (visited[s]) continue;
+        // pseudo-peripheral node of s's component
+        int32_t r = s;
+        int32_t ecc = bfs_levels(g, r, stamp, tag++, queue, last);
+        for (int it = 0; it < 8; ++it) {
+            int32_t best = last[0];
+            for (int32_t v : last)
+                if (g.deg(v) < g.deg(best)) best = v;
+            int32_t e2 = bfs_levels(g, best, stamp, tag++, queue, last);
+            if (e2 <= ecc) break;
+            r = best;
+            ecc = e2;
+        }
+        // Cuthill-McKee from r: neighbours in increasing degree
+        size_t head = order.size();
+        order.push_back(r);
+        visited[r] = 1;
+        while (head < order.size()) {
+            int32_t u = order[head++];
+            nb.clear();
+            for (int64_t k = g.rp[u]; k < g.rp[u + 1]; ++k) {
+                int32_t v = g.ci[size_t(k)];
+                if (!visited[v]) {
+                    visited[v] = 1;
+                    nb.push_back(v);
+                }
+            }
+            std::stable_sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) {
+                return g.deg(a) < g.deg(b);
+            });
+            order.insert(order.end(), nb.begin(), nb.end());
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
+double mean_band(int32_t n, const int32_t *rowptr, const int32_t *col,
+                 const int32_t *iperm)
+{
+    double s = 0.0;
+    int64_t nnz = rowptr[n];
+    if (nnz == 0) return 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t ri = iperm ? iperm[i] : i;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            int64_t c = iperm ? iperm[col[k]] : col[k];
+            s += double(ri > c ? ri - c : c - ri);
+        }
+    }
+    return s / double(nnz);
+}
+
+bool is_pow2(int32_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                       const int32_t *rowptr, const int32_t *col,
+                       const fs_csr_opts &o, HostLayout &L)
+{
+    // ---- validation (paper: CSR arrays of values, column indices and
+    // row offsets, section "Description of Current GPU Methods")
+    if (rowptr[0] != 0)
+        return set_error(FS_E_BAD_CSR, "rowptr[0] = %d, expected 0", rowptr[0]);
+    for (int32_t i = 0; i < n_rows; ++i)
+        if (rowptr[i + 1] < rowptr[i])
+            return set_error(FS_E_BAD_CSR, "rowptr decreases at row %d", i);
+    if (int64_t(rowptr[n_rows]) != nnz)
+        return set_error(FS_E_BAD_CSR, "rowptr[n] = %d but nnz = %lld",
+                         rowptr[n_rows], (long long)nnz);
+    for (int64_t k = 0; k < nnz; ++k)
+        if (col[k] < 0 || col[k] >= n_cols)
+            return set_error(FS_E_BAD_CSR, "column %d out of range at %lld",
+                             col[k], (long long)k);
+
+    const bool square = n_rows == n_cols;
+    int32_t sort_window = o.sort_window > 0 ? o.sort_window : 256;
+    int32_t threshold = o.threshold > 0 ? o.threshold : 16;
+    int32_t tmin = o.lanes_min > 0 ? o.lanes_min : 1;
+    int32_t tmax = o.lanes_max > 0 ? o.lanes_max : 64;
+    if (!is_pow2(tmin) || !is_pow2(tmax) || tmin > tmax || tmax > kWave)
+        return set_error(FS_E_ARG, "lanes_min/lanes_max must be powers of "
+                         "two with 1 <= min <= max <= 64");
+
+    // ---- locality permutation
+    L.perm.resize(size_t(n_rows));
+    std::iota(L.perm.begin(), L.perm.end(), 0);
+    L.reorder = FS_REORDER_NONE;
+    if (o.reorder == FS_REORDER_USER) {
+        if (!o.perm) return set_error(FS_E_ARG, "FS_REORDER_USER needs perm");
+        std::vector<char> seen(size_t(n_rows), 0);
+        for (int32_t i = 0; i < n_rows; ++i) {
+            int32_t v = o.perm[i];
+            if (v < 0 || v >= n_rows || seen[v])
+                return set_error(FS_E_ARG, "perm is not a permutation");
+            seen[v] = 1;
+            L.perm[i] = v;
+        }
+        L.reorder = FS_REORDER_USER;
+    } else if (o.reorder == FS_REORDER_RCM || o.reorder == FS_REORDER_AUTO) {
+        if (!square) {
+            if (o.reorder == FS_REORDER_RCM)
+                return set_error(FS_E_NOT_SQUARE,
+                                 "RCM reordering needs a square matrix");
+        } else if (n_rows > 0) {
+            Graph g = symmetric_graph(n_rows, rowptr, col);
+            std::vector<int32_t> ord = rcm_order(g);
+            if (o.reorder == FS_REORDER_RCM) {
+                L.perm = ord;
+                L.reorder = FS_REORDER_RCM;
+            } else {
+                std::vector<int32_t> inv(static_cast<size_t>(n_rows));
+                for (int32_t i = 0; i < n_rows; ++i) inv[ord[i]] = i;
+                double b0 = mean_band(n_rows, rowptr, col, nullptr);
+                double b1 = mean_band(n_rows, rowptr, col, inv.data());
+                if (b1 < 0.8 * b0) {
+                    L.perm = ord;
+                    L.reorder = FS_REORDER_RCM;
+                }
+            }
+        }
+    } else if (o.reorder != FS_REORDER_NONE) {
+        return set_error(FS_E_ARG, "unknown reorder option %d", o.reorder);
+    }
+
+    // ---- longest-first inside windows (stable, keeps locality order)
+    if (sort_window > 1) {
+        for (int64_t w0 = 0; w0 < n_rows; w0 += sort_window) {
+            int64_t w1 = std::min<int64_t>(n_rows, w0 + sort_window);
+            std::stable_sort(L.perm.begin() + w0, L.perm.begin() + w1,
+                             [&](int32_t a, int32_t b) {
+                                 return rowptr[a + 1] - rowptr[a] >
+                                        rowptr[b + 1] - rowptr[b];
+                             });
+        }
+    }
+    L.iperm.assign(size_t(n_rows), 0);
+    L.identity = true;
+    for (int32_t i = 0; i < n_rows; ++i) {
+        L.iperm[L.perm[i]] = i;
+        if (L.perm[i] != i) L.identity = false;
+    }
+    L.symmetric_relabel = square;
+    L.band_before = square ? mean_band(n_rows, rowptr, col, nullptr) : 0.0;
+    L.band_after = square ? mean_band(n_rows, rowptr, col, L.iperm.data())
+                          : 0.0;
+
+    // ---- row groups: one wavefront, T lanes per row, 64/T rows
+    auto len = [&](int32_t layout_row) {
+        int32_t r = L.perm[layout_row];
+        return rowptr[r + 1] - rowptr[r];
+    };
+    L.groups.clear();
+    std::fill(std::begin(L.groups_by_lanes), std::end(L.groups_by_lanes), 0);
+    int64_t slots = 0;
+    for (int32_t i = 0; i < n_rows;) {
+        int32_t T = tmin, rows = 0, w = 0;
+        while (true) {
+            rows = std::min<int32_t>(kWave / T, n_rows - i);
+            int32_t maxlen = 0;
+            for (int32_t j = 0; j < rows; ++j) maxlen = std::max(maxlen, len(i + j));
+            w = (maxlen + T - 1) / T;
+            if (w <= threshold || T >= tmax) break;
+            T *= 2;
+        }
+        int32_t width = (w + kVec - 1) / kVec * kVec;
+        int32_t lt = 0;
+        while ((1 << lt) < T) ++lt;
+        if (slots / kWave >= INT32_MAX)
+            return set_error(FS_E_UNSUPPORTED, "layout too large");
+        L.groups.push_back(Group{int32_t(slots / kWave), i, rows,
+                                 width | (lt << 24)});
+        L.groups_by_lanes[lt]++;
+        slots += int64_t(width) * kWave;
+        i += rows;
+    }
+    if (slots >= INT32_MAX)
+        return set_error(FS_E_UNSUPPORTED,
+                         "more than 2^31 padded slots (%lld)",
+                         (long long)slots);
+    L.slots = slots;
+
+    // ---- slot columns and the CSR-position -> slot map
+    L.slot_col.assign(size_t(slots), -1);
+    L.map.assign(size_t(nnz), -1);
+    std::vector<std::pair<int32_t, int32_t>> ent;  // (layout col, local k)
+    for (const Group &g : L.groups) {
+        const int32_t lt = g.width_lt >> 24, T = 1 << lt;
+        const int64_t base = int64_t(g.base64) * kWave;
+        for (int32_t rr = 0; rr < g.nrows; ++rr) {
+            const int32_t orow = L.perm[g.row0 + rr];
+            const int32_t k0 = rowptr[orow], k1 = rowptr[orow + 1];
+            ent.clear();
+            for (int32_t k = k0; k < k1; ++k) {
+                int32_t c = L.symmetric_relabel ? L.iperm[col[k]] : col[k];
+                ent.emplace_back(c, k - k0);
+            }
+            std::sort(ent.begin(), ent.end());
+            for (size_t e = 1; e < ent.size(); ++e)
+                if (ent[e].first == ent[e - 1].first)
+                    return set_error(FS_E_BAD_CSR,
+                                     "duplicate column %d in row %d",
+                                     col[k0 + ent[e].second], orow);
+            for (size_t e = 0; e < ent.size(); ++e) {
+                const int32_t lane = rr * T + int32_t(e) % T;
+                const int32_t s = int32_t(e) / T;
+                const int64_t idx = base + int64_t(s / kVec) * kWave * kVec +
+                                    int64_t(lane) * kVec + s % kVec;
+                L.slot_col[size_t(idx)] = ent[e].first;
+                L.map[size_t(k0 + ent[e].second)] = int32_t(idx);
+            }
+        }
+    }
+    return FS_OK;
+}
+
+}  // namespace fs

@@ -1,0 +1,146 @@
+"""GPU parity of the FP64 (Jacobi-)CG solve against the CPU oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads.meshes import CSR
+from tests.gpu_util import note, dev, host, make
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_1501_00324_amd as fs
+    fs.load(build_if_missing=False)
+    return fs
+
+
+def kappa(A):
+    """Spectral condition number (dense for small, Lanczos otherwise)."""
+    if A.n_rows <= 2500:
+        ev = np.linalg.eigvalsh(A.to_dense())
+        return ev[-1] / ev[0]
+    import scipy.sparse.linalg as sla
+    S = A.to_scipy()
+    lmax = sla.eigsh(S, k=1, which="LA", return_eigenvectors=False)[0]
+    lmin = sla.eigsh(S, k=1, sigma=0, which="LM",
+                     return_eigenvectors=False)[0]
+    return lmax / lmin
+
+
+def true_relres(orc, A, x, b):
+    r = b - orc.spmv(A, x)
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+def solve_and_check(fs, orc, A, precond, what, rtol=1e-8, **kw):
+    note("cg %s n=%d nnz=%d pc=%d %s" % (what, A.n_rows, A.nnz, precond, kw))
+    M = make(A)
+    b = W.random_vector(A.n_rows, 55, W.BVEC, A.n_rows % 97)
+    x, info = fs.cg_solve(M, dev(b), precond=precond, rtol=rtol, **kw)
+    xg = host(x)
+    assert info["status"] == fs.FS_OK, info
+    # the library's own FP64 true residual and the oracle's recomputation
+    assert info["relres"] <= rtol
+    assert true_relres(orc, A, xg, b) <= rtol * 1.001
+    return M, b, xg, info
+
+
+SPD = [
+    ("cfg0", W.config0_poisson2d),
+    ("p2d_perm", lambda: W.poisson_2d_p1(20, seed=(56, 0), bc="all",
+                                         permute=True)),
+    ("ela6", lambda: W.tet_p1(6, "elastic", seed=(56, 1), bc="x0",
+                              permute=True)),
+    ("lap8", lambda: W.tet_p1(8, "laplace", seed=(56, 2), bc="all")),
+    ("q1ela", lambda: W.hex_q1(5, "elastic", seed=(56, 3), bc="x0")),
+    ("p2lap", lambda: W.tet_p2(3, "laplace", seed=(56, 4), bc="all")),
+]
+
+
+@pytest.mark.parametrize("name,gen", SPD, ids=[s[0] for s in SPD])
+@pytest.mark.parametrize("precond", [0, 1])
+def test_cg_parity_small(fs, orc, name, gen, precond):
+    A = gen()
+    M, b, xg, info = solve_and_check(fs, orc, A, precond, name)
+    xo, st, it, rr = orc.pcg(A, b, precond=precond, rtol=1e-8)
+    assert st == orc.OK
+    k = kappa(A)
+    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    assert err <= 2 * 1e-8 * k, (err, k)
+    # counts are reported, not pinned; they should be close
+    assert abs(info["iters"] - it) <= max(3, 0.05 * it), (info["iters"], it)
+
+
+def test_cg_graph_chunking_is_bitwise_neutral(fs, orc):
+    A = W.config0_poisson2d()
+    note("cg chunking")
+    M = make(A)
+    b = dev(W.random_vector(A.n_rows, 57, W.BVEC))
+    ref, ri = fs.cg_solve(M, b, precond=1, use_graph=0, check_every=1)
+    for ce, g in [(1, 1), (7, 1), (32, 1), (64, 0), (500, 1)]:
+        x, info = fs.cg_solve(M, b, precond=1, use_graph=g, check_every=ce)
+        assert info["iters"] == ri["iters"]
+        assert np.array_equal(host(x), host(ref))
+
+
+def test_cg_config1_jacobi(fs, orc):
+    """Config 1: 3-D elasticity, random numbering, Jacobi-PCG to 1e-8."""
+    A = W.config1_elasticity3d()
+    M, b, xg, info = solve_and_check(fs, orc, A, 1, "cfg1")
+    assert info["iters"] > 100
+
+
+def test_cg_status_codes(fs, orc):
+    import torch
+    note("cg status codes")
+    Ind = CSR(2, 2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32),
+              np.array([1.0, -1.0]))
+    M = make(Ind)
+    x, info = fs.cg_solve(M, dev(np.array([1.0, 1.0])), precond=0,
+                          check=False)
+    assert info["status"] == fs.FS_E_BREAKDOWN
+    A = W.poisson_2d_p1(16, seed=(58, 0), bc="all")
+    M = make(A)
+    b = W.random_vector(A.n_rows, 58, W.BVEC)
+    x, info = fs.cg_solve(M, dev(b), precond=1, maxit=3, check=False)
+    assert info["status"] == fs.FS_E_NOT_CONVERGED and info["iters"] == 3
+    assert abs(info["relres"] - true_relres(orc, A, host(x), b)) < 1e-10
+    xo, _, _, _ = orc.pcg(A, b, precond=1, maxit=3)
+    assert np.allclose(host(x), xo, rtol=1e-9, atol=1e-12)
+    x0 = dev(np.ones(A.n_rows))
+    x, info = fs.cg_solve(M, dev(np.zeros(A.n_rows)), x=x0, precond=1)
+    assert info["iters"] == 0 and not host(x).any()
+    Z = CSR(2, 2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32),
+            np.array([1.0, 1.0]))
+    M = make(Z)
+    with pytest.raises(fs.FsError) as e:
+        fs.cg_solve(M, dev(np.array([1.0, 2.0])), precond=1)
+    assert e.value.status == fs.FS_E_ARG
+    R = CSR(2, 3, np.array([0, 1, 2], np.int32), np.array([0, 2], np.int32),
+            np.array([1.0, 1.0]))
+    M = make(R)
+    with pytest.raises(fs.FsError) as e:
+        fs.cg_solve(M, dev(np.array([1.0, 2.0])))
+    assert e.value.status == fs.FS_E_NOT_SQUARE
+    del torch
+
+
+def test_cg_warm_start_and_determinism(fs, orc):
+    A = W.tet_p1(8, "elastic", seed=(59, 0), bc="x0", permute=True)
+    note("cg warm start")
+    M = make(A)
+    b = W.random_vector(A.n_rows, 59, W.BVEC)
+    x, full = fs.cg_solve(M, dev(b), precond=1)
+    x2, again = fs.cg_solve(M, dev(b), precond=1)
+    assert np.array_equal(host(x), host(x2))
+    half = full["iters"] // 2
+    xh, ih = fs.cg_solve(M, dev(b), precond=1, maxit=half, check=False)
+    assert ih["status"] == fs.FS_E_NOT_CONVERGED
+    xr, ir = fs.cg_solve(M, dev(b), x=xh.clone(), precond=1)
+    assert ir["status"] == fs.FS_OK
+    assert true_relres(orc, A, host(xr), b) <= 1.001e-8
