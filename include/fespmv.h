@@ -91,7 +91,9 @@ typedef struct fs_csr_opts {
     int32_t lanes_min;     /* lanes per row bounds, powers of two in 1..64; */
     int32_t lanes_max;     /*   0 = defaults 1 and 64                       */
     int32_t dtypes;        /* extra low-precision copies (FS_DT_F32/BF16)   */
-    int32_t reserved[8];   /* must be zero                                   */
+    int32_t vec;           /* slots each lane loads at once: 1 or 2; 0 =
+                              auto (2 unless it adds > 3% padded slots)    */
+    int32_t reserved[7];   /* must be zero                                   */
 } fs_csr_opts;
 
 /* Fill *o with the defaults (AUTO reorder, window 256, threshold 16,
@@ -131,6 +133,7 @@ typedef struct fs_csr_stats {
     int64_t bytes_layout;     /* 12 slots + 16 n_groups + 8 n_cols + 8 n_rows */
     int32_t groups_by_lanes[7];/* groups with 1,2,4,...,64 lanes per row    */
     int32_t dtypes;           /* FS_DT_* copies held                        */
+    int32_t vec;              /* slots per lane per load (1 or 2)           */
     double mean_band_before;  /* mean |i - j| over non-zeros, input order  */
     double mean_band_after;   /* same, layout order                         */
     double t_build_ms;        /* wall time of csr_create                    */
@@ -146,16 +149,17 @@ fs_status csr_get_perm(fs_csr_t A, int32_t *perm_host);
 /* Host-only dry run of the layout builder on HOST arrays (no device memory
  * is touched, no GPU needed): the same validation, reordering, grouping and
  * slot assignment csr_create performs.  Outputs (each may be NULL):
- * n_groups, slots; groups: 4 int32 per group {first element / 64, first
- * layout row, rows, slots per lane | log2(lanes per row) << 24}; slot_col:
+ * n_groups, slots, vec (slots per lane per load); groups: 4 int32 per
+ * group {first element / 64, first layout row, rows, slots per lane |
+ * log2(lanes per row) << 24}; slot_col:
  * layout column of every slot (-1 = padding); map: slot of every CSR
  * position; perm: layout row i is caller row perm[i].  Call once with NULL
  * arrays to learn the sizes. */
 fs_status csr_layout_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
                           const int32_t *rowptr, const int32_t *colind,
                           const fs_csr_opts *opts, int32_t *n_groups,
-                          int64_t *slots, int32_t *groups, int32_t *slot_col,
-                          int32_t *map, int32_t *perm);
+                          int64_t *slots, int32_t *vec, int32_t *groups,
+                          int32_t *slot_col, int32_t *map, int32_t *perm);
 
 /* Free everything the handle owns (after synchronising the device).  NULL
  * is a no-op. */

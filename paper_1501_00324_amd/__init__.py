@@ -37,7 +37,8 @@ class CsrOpts(C.Structure):
     _fields_ = [("reorder", C.c_int32), ("perm", C.c_void_p),
                 ("sort_window", C.c_int32), ("threshold", C.c_int32),
                 ("lanes_min", C.c_int32), ("lanes_max", C.c_int32),
-                ("dtypes", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("dtypes", C.c_int32), ("vec", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
 
 
 class CsrStats(C.Structure):
@@ -47,7 +48,7 @@ class CsrStats(C.Structure):
                 ("padding", C.c_double), ("bytes_algorithmic", C.c_int64),
                 ("bytes_layout", C.c_int64),
                 ("groups_by_lanes", C.c_int32 * 7), ("dtypes", C.c_int32),
-                ("mean_band_before", C.c_double),
+                ("vec", C.c_int32), ("mean_band_before", C.c_double),
                 ("mean_band_after", C.c_double),
                 ("t_build_ms", C.c_double), ("device_bytes", C.c_int64)]
 
@@ -109,7 +110,7 @@ def load(build_if_missing=True):
         "csr_opts_default": [P(CsrOpts)],
         "csr_create": [i32, i32, i64, vp, vp, vp, P(CsrOpts), vp, P(vp)],
         "csr_layout_host": [i32, i32, i64, vp, vp, P(CsrOpts), P(i32),
-                            P(i64), vp, vp, vp, vp],
+                            P(i64), P(i32), vp, vp, vp, vp],
         "csr_update_values": [vp, vp, vp],
         "csr_add_dtype": [vp, i32, vp],
         "csr_info": [vp, P(CsrStats)],
@@ -235,20 +236,22 @@ def csr_layout_host(rowptr, col, n_rows=None, n_cols=None, **opts):
     o = csr_opts(**opts)
     ng = C.c_int32()
     ns = C.c_int64()
+    nv = C.c_int32()
     _check(L.csr_layout_host(n_rows, n_cols, len(col), rowptr.ctypes.data,
                              col.ctypes.data, C.byref(o), C.byref(ng),
-                             C.byref(ns), None, None, None, None))
+                             C.byref(ns), C.byref(nv), None, None, None,
+                             None))
     groups = np.zeros((ng.value, 4), dtype=np.int32)
     slot_col = np.zeros(ns.value, dtype=np.int32)
     mp = np.zeros(len(col), dtype=np.int32)
     perm = np.zeros(n_rows, dtype=np.int32)
     _check(L.csr_layout_host(n_rows, n_cols, len(col), rowptr.ctypes.data,
                              col.ctypes.data, C.byref(o), C.byref(ng),
-                             C.byref(ns), groups.ctypes.data,
+                             C.byref(ns), C.byref(nv), groups.ctypes.data,
                              slot_col.ctypes.data, mp.ctypes.data,
                              perm.ctypes.data))
     return dict(groups=groups, slot_col=slot_col, map=mp, perm=perm,
-                slots=ns.value)
+                slots=ns.value, vec=nv.value)
 
 
 def csr_update_values(A, val, stream=None):

@@ -258,8 +258,8 @@ fs_status csr_create(int32_t n_rows, int32_t n_cols, int64_t nnz,
 fs_status csr_layout_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
                           const int32_t *rowptr, const int32_t *colind,
                           const fs_csr_opts *opts, int32_t *n_groups,
-                          int64_t *slots, int32_t *groups, int32_t *slot_col,
-                          int32_t *map, int32_t *perm)
+                          int64_t *slots, int32_t *vec, int32_t *groups,
+                          int32_t *slot_col, int32_t *map, int32_t *perm)
 {
     if (n_rows < 0 || n_cols < 0 || nnz < 0)
         return set_error(FS_E_ARG, "negative size");
@@ -274,6 +274,7 @@ fs_status csr_layout_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
     FS_TRY(build_layout(n_rows, n_cols, nnz, rowptr, colind, o, L));
     if (n_groups) *n_groups = int32_t(L.groups.size());
     if (slots) *slots = L.slots;
+    if (vec) *vec = L.vec;
     if (groups && !L.groups.empty())
         std::memcpy(groups, L.groups.data(), sizeof(Group) * L.groups.size());
     if (slot_col && L.slots)
@@ -313,6 +314,7 @@ fs_status csr_info(fs_csr_t A, fs_csr_stats *st)
                        8 * int64_t(A->n_cols) + 8 * int64_t(A->n_rows);
     for (int i = 0; i < 7; ++i) st->groups_by_lanes[i] = A->host.groups_by_lanes[i];
     st->dtypes = A->dtypes;
+    st->vec = A->host.vec;
     st->mean_band_before = A->host.band_before;
     st->mean_band_after = A->host.band_after;
     st->t_build_ms = A->t_build_ms;

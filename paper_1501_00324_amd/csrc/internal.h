@@ -35,10 +35,10 @@ void clear_error();
 // 64 / T consecutive layout rows, T lanes per row (T a power of two); entry
 // e of a row (columns ascending) goes to lane (row_in_group * T + e % T),
 // slot e / T of that lane.  Slots are interleaved so that one wave-wide
-// load of V consecutive slots per lane is one contiguous 64*V element
-// block:  element index = base + (s / V) * 64 * V + lane * V + s % V.
+// load of V consecutive slots per lane (V = 1 or 2, per matrix) is one
+// contiguous 64*V element block:
+//     element index = base + (s / V) * 64 * V + lane * V + s % V.
 constexpr int kWave = 64;
-constexpr int kVec = 2;            // slots loaded per lane per access
 constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 
 struct Group {                     // 16 bytes, read once per wave
@@ -55,6 +55,7 @@ struct HostLayout {
     std::vector<int32_t> slot_col; // layout column per slot, -1 = padding
     std::vector<int32_t> map;      // CSR position k -> slot index
     int64_t slots = 0;
+    int32_t vec = 2;                 // slots per lane per load (1 or 2)
     int32_t reorder = FS_REORDER_NONE;
     int32_t groups_by_lanes[7] = {0, 0, 0, 0, 0, 0, 0};
     double band_before = 0.0, band_after = 0.0;

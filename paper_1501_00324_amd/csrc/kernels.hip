@@ -50,26 +50,68 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum of the lane partials of one group row slice: lanes [slot loop].
+template <int V> struct Slots;
+template <> struct Slots<1> { typedef double D; typedef int I; };
+template <> struct Slots<2> { typedef dv2 D; typedef iv2 I; };
+
+// Padded slots (column -1) read x[0] (always in bounds: a matrix with
+// slots has at least one column) and the select drops the product, so an
+// Inf/NaN there never reaches the sum.
+__device__ __forceinline__ void slot_fma(int c, double a, const double *x,
+                                         double &acc)
+{
+    const double xv = x[c < 0 ? 0 : c];
+    acc = fma(a, c >= 0 ? xv : 0.0, acc);
+}
+
+// This lane's share of its row: sum over its slots of a * x[col].  The
+// matrix stream is loaded in batches of 8 slots (all column and value
+// loads of a batch issued before any gather) so that each wavefront keeps
+// ~12 KiB of the stream plus 512 gathers in flight.
+template <int V>
 __device__ __forceinline__ double group_lane_sum(const Group &g, int lane,
                                                  const double *__restrict__ val,
                                                  const int *__restrict__ col,
                                                  const double *__restrict__ x)
 {
+    typedef typename Slots<V>::D D;
+    typedef typename Slots<V>::I I;
+    constexpr int U = 8 / V;
     const int width = g.width_lt & 0xffffff;
     const long base = long(g.base64) * kWave;
-    const dv2 *pv = reinterpret_cast<const dv2 *>(val + base) + lane;
-    const iv2 *pc = reinterpret_cast<const iv2 *>(col + base) + lane;
+    const D *pv = reinterpret_cast<const D *>(val + base) + lane;
+    const I *pc = reinterpret_cast<const I *>(col + base) + lane;
+    const int nch = width / V;
     double acc0 = 0.0, acc1 = 0.0;
-    const int nch = width >> 1;
-#pragma unroll 4
-    for (int j = 0; j < nch; ++j) {
-        const iv2 c = __builtin_nontemporal_load(pc + j * kWave);
-        const dv2 a = __builtin_nontemporal_load(pv + j * kWave);
-        const double x0 = c.x >= 0 ? x[c.x] : 0.0;
-        const double x1 = c.y >= 0 ? x[c.y] : 0.0;
-        acc0 = fma(a.x, x0, acc0);
-        acc1 = fma(a.y, x1, acc1);
+    int j = 0;
+    for (; j + U <= nch; j += U) {
+        I c[U];
+        D a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            c[u] = __builtin_nontemporal_load(pc + (j + u) * kWave);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            a[u] = __builtin_nontemporal_load(pv + (j + u) * kWave);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if constexpr (V == 1) {
+                slot_fma(c[u], a[u], x, (u & 1) ? acc1 : acc0);
+            } else {
+                slot_fma(c[u].x, a[u].x, x, acc0);
+                slot_fma(c[u].y, a[u].y, x, acc1);
+            }
+        }
+    }
+    for (; j < nch; ++j) {
+        const I c = __builtin_nontemporal_load(pc + j * kWave);
+        const D a = __builtin_nontemporal_load(pv + j * kWave);
+        if constexpr (V == 1) {
+            slot_fma(c, a, x, acc0);
+        } else {
+            slot_fma(c.x, a.x, x, acc0);
+            slot_fma(c.y, a.y, x, acc1);
+        }
     }
     return acc0 + acc1;
 }
@@ -91,6 +133,9 @@ __device__ __forceinline__ Group load_group(const Group *groups, int g)
 }
 
 // ---------------------------------------------------------------- SpMV
+// SCATTER: write y(yperm[row]) (caller numbering, the final re-mapping of
+// the paper's K1), else y(row) in layout numbering (K1r).
+template <int V, bool SCATTER>
 __global__ __launch_bounds__(kBlock) void k_spmv_f64(
     const Group *__restrict__ groups, int ngroups,
     const double *__restrict__ val, const int *__restrict__ col,
@@ -104,11 +149,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_f64(
     const int lane = threadIdx.x & (kWave - 1);
     const Group gd = load_group(groups, g);
     const int lt = gd.width_lt >> 24;
-    double acc = row_reduce(group_lane_sum(gd, lane, val, col, x), lt);
+    double acc = row_reduce(group_lane_sum<V>(gd, lane, val, col, x), lt);
     const int r = lane >> lt;
     if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
         const int row = gd.row0 + r;
-        y[yperm ? yperm[row] : row] = acc;
+        y[SCATTER ? yperm[row] : row] = acc;
     }
 }
 
@@ -143,15 +188,16 @@ __device__ bool two_stage_sum(double (&v)[NV], double *partials, int nblk,
     }
     __syncthreads();
     if (!last) return false;
+    // acquire: every other block's partial is visible after this fence;
+    // plain loads so the whole column of partials is in flight at once
     __threadfence();
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         s[k] = 0.0;
-        for (int i = threadIdx.x; i < nblk; i += kBlock)
-            s[k] += __hip_atomic_load(&partials[k * nblk + i],
-                                      __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
+        const double *pk = partials + k * nblk;
+#pragma unroll 8
+        for (int i = threadIdx.x; i < nblk; i += kBlock) s[k] += pk[i];
     }
     __syncthreads();
 #pragma unroll
@@ -173,6 +219,7 @@ __device__ bool two_stage_sum(double (&v)[NV], double *partials, int nblk,
 // ------------------------------------------------------------------- CG
 // q = A p and gamma = p.q; the last block sets alpha = rho / gamma or flags
 // a breakdown (gamma <= 0 or non-finite).
+template <int V>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(
     const Group *__restrict__ groups, int ngroups,
     const double *__restrict__ val, const int *__restrict__ col,
@@ -188,7 +235,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(
     if (g < ngroups) {
         const Group gd = load_group(groups, g);
         const int lt = gd.width_lt >> 24;
-        const double acc = row_reduce(group_lane_sum(gd, lane, val, col, p), lt);
+        const double acc =
+            row_reduce(group_lane_sum<V>(gd, lane, val, col, p), lt);
         const int r = lane >> lt;
         if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
             const int row = gd.row0 + r;
@@ -277,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(
 // mode 1: convergence check -- stop when the true residual meets the
 //         tolerance, else keep it (residual replacement) and set beta/rho;
 // mode 2: measurement only (rr_true).
-template <bool X_ZERO>
+template <int V, bool X_ZERO>
 __global__ __launch_bounds__(kBlock) void k_cg_residual(
     const Group *__restrict__ groups, int ngroups,
     const double *__restrict__ val, const int *__restrict__ col,
@@ -295,7 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_residual(
         const Group gd = load_group(groups, g);
         const int lt = gd.width_lt >> 24;
         double acc = 0.0;
-        if (!X_ZERO) acc = row_reduce(group_lane_sum(gd, lane, val, col, x), lt);
+        if (!X_ZERO)
+            acc = row_reduce(group_lane_sum<V>(gd, lane, val, col, x), lt);
         const int rr = lane >> lt;
         if ((lane & ((1 << lt) - 1)) == 0 && rr < gd.nrows) {
             const int row = gd.row0 + rr;
@@ -355,6 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_residual(
 
 // Jacobi: dinv[row] = 1 / A(row,row) in layout numbering; counts rows whose
 // diagonal is zero or non-finite in sc->pad[0].
+template <int V>
 __global__ __launch_bounds__(kBlock) void k_diag_inv(
     const Group *__restrict__ groups, int ngroups,
     const double *__restrict__ val, const int *__restrict__ col,
@@ -370,8 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_inv(
     const long base = long(gd.base64) * kWave;
     double d = 0.0;
     for (int s = 0; s < width; ++s) {
-        const long idx = base + long(s / kVec) * kWave * kVec + lane * kVec +
-                         s % kVec;
+        const long idx = base + long(s / V) * kWave * V + lane * V + s % V;
         if (col[idx] == row) d += val[idx];
     }
     d = row_reduce(d, lt);
@@ -470,13 +519,37 @@ hipError_t launch_scatter(int32_t n, const int32_t *perm, const double *in,
     return hipGetLastError();
 }
 
+// Instantiate F<V> for the matrix's slot vector width.
+#define FS_LAUNCH_V(A, KERNEL, grid, ...)                                     \
+    do {                                                                    \
+        if ((A)->host.vec == 1)                                             \
+            hipLaunchKernelGGL(KERNEL<1>, grid, dim3(kBlock), 0, __VA_ARGS__); \
+        else                                                                \
+            hipLaunchKernelGGL(KERNEL<2>, grid, dim3(kBlock), 0, __VA_ARGS__); \
+    } while (0)
+
+template <int V> struct SpmvScatter {
+    template <bool S> static void go(const fs_csr *A, const double *x,
+                                     double *y, const int32_t *yperm,
+                                     hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_spmv_f64<V, S>), dim3(spmv_blocks(A->n_groups)),
+                           dim3(kBlock), 0, s, A->d_groups, A->n_groups,
+                           A->d_val, A->d_col, x, y, yperm);
+    }
+};
+
 hipError_t launch_spmv_f64(const fs_csr *A, const double *x, double *y,
                            const int32_t *yperm, hipStream_t s)
 {
     if (A->n_groups == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv_f64, dim3(spmv_blocks(A->n_groups)),
-                       dim3(kBlock), 0, s, A->d_groups, A->n_groups,
-                       A->d_val, A->d_col, x, y, yperm);
+    if (A->host.vec == 1) {
+        if (yperm) SpmvScatter<1>::go<true>(A, x, y, yperm, s);
+        else SpmvScatter<1>::go<false>(A, x, y, yperm, s);
+    } else {
+        if (yperm) SpmvScatter<2>::go<true>(A, x, y, yperm, s);
+        else SpmvScatter<2>::go<false>(A, x, y, yperm, s);
+    }
     return hipGetLastError();
 }
 
@@ -489,9 +562,9 @@ int32_t cg_partials_needed(const fs_csr *A)
 
 hipError_t launch_cg_spmv_dot(const fs_csr *A, CgWork &w, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_spmv_dot, dim3(spmv_blocks(A->n_groups)),
-                       dim3(kBlock), 0, s, A->d_groups, A->n_groups,
-                       A->d_val, A->d_col, w.p, w.q, w.sc, w.partials);
+    FS_LAUNCH_V(A, k_cg_spmv_dot, dim3(spmv_blocks(A->n_groups)), s,
+                A->d_groups, A->n_groups, A->d_val, A->d_col, w.p, w.q, w.sc,
+                w.partials);
     return hipGetLastError();
 }
 
@@ -510,22 +583,32 @@ hipError_t launch_cg_pupdate(CgWork &w, int32_t precond, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int V> struct Residual {
+    template <bool XZ> static void go(const fs_csr *A, CgWork &w,
+                                      const double *dinv, int32_t mode,
+                                      double rtol, int32_t maxit,
+                                      hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_cg_residual<V, XZ>),
+                           dim3(spmv_blocks(A->n_groups)), dim3(kBlock), 0, s,
+                           A->d_groups, A->n_groups, A->d_val, A->d_col, w.x,
+                           w.b, w.r, w.p, dinv, w.sc, w.partials, mode, rtol,
+                           maxit);
+    }
+};
+
 hipError_t launch_cg_residual(const fs_csr *A, CgWork &w, int32_t precond,
                               int32_t mode, double rtol, int32_t maxit,
                               int32_t x_is_zero, hipStream_t s)
 {
-    const dim3 grid(spmv_blocks(A->n_groups)), block(kBlock);
     const double *dinv = precond ? w.dinv : nullptr;
-    if (x_is_zero)
-        hipLaunchKernelGGL(k_cg_residual<true>, grid, block, 0, s,
-                           A->d_groups, A->n_groups, A->d_val, A->d_col, w.x,
-                           w.b, w.r, w.p, dinv, w.sc, w.partials, mode, rtol,
-                           maxit);
-    else
-        hipLaunchKernelGGL(k_cg_residual<false>, grid, block, 0, s,
-                           A->d_groups, A->n_groups, A->d_val, A->d_col, w.x,
-                           w.b, w.r, w.p, dinv, w.sc, w.partials, mode, rtol,
-                           maxit);
+    if (A->host.vec == 1) {
+        if (x_is_zero) Residual<1>::go<true>(A, w, dinv, mode, rtol, maxit, s);
+        else Residual<1>::go<false>(A, w, dinv, mode, rtol, maxit, s);
+    } else {
+        if (x_is_zero) Residual<2>::go<true>(A, w, dinv, mode, rtol, maxit, s);
+        else Residual<2>::go<false>(A, w, dinv, mode, rtol, maxit, s);
+    }
     return hipGetLastError();
 }
 
@@ -533,9 +616,8 @@ hipError_t launch_diag_inv(const fs_csr *A, double *dinv, CgScalars *sc,
                            hipStream_t s)
 {
     if (A->n_groups == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_diag_inv, dim3(spmv_blocks(A->n_groups)),
-                       dim3(kBlock), 0, s, A->d_groups, A->n_groups,
-                       A->d_val, A->d_col, dinv, sc);
+    FS_LAUNCH_V(A, k_diag_inv, dim3(spmv_blocks(A->n_groups)), s,
+                A->d_groups, A->n_groups, A->d_val, A->d_col, dinv, sc);
     return hipGetLastError();
 }
 

@@ -195,6 +195,8 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
     if (!is_pow2(tmin) || !is_pow2(tmax) || tmin > tmax || tmax > kWave)
         return set_error(FS_E_ARG, "lanes_min/lanes_max must be powers of "
                          "two with 1 <= min <= max <= 64");
+    if (o.vec < 0 || o.vec > 2)
+        return set_error(FS_E_ARG, "vec must be 0 (auto), 1 or 2");
 
     // ---- locality permutation
     L.perm.resize(size_t(n_rows));
@@ -264,9 +266,9 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
         int32_t r = L.perm[layout_row];
         return rowptr[r + 1] - rowptr[r];
     };
-    L.groups.clear();
-    std::fill(std::begin(L.groups_by_lanes), std::end(L.groups_by_lanes), 0);
-    int64_t slots = 0;
+    struct Raw { int32_t row0, rows, w, lt; };
+    std::vector<Raw> raw;
+    int64_t slots1 = 0, slots2 = 0;
     for (int32_t i = 0; i < n_rows;) {
         int32_t T = tmin, rows = 0, w = 0;
         while (true) {
@@ -277,16 +279,29 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
             if (w <= threshold || T >= tmax) break;
             T *= 2;
         }
-        int32_t width = (w + kVec - 1) / kVec * kVec;
         int32_t lt = 0;
         while ((1 << lt) < T) ++lt;
+        raw.push_back(Raw{i, rows, w, lt});
+        slots1 += int64_t(w) * kWave;
+        slots2 += int64_t((w + 1) / 2 * 2) * kWave;
+        i += rows;
+    }
+    // two slots per load halves the load instructions; one slot per load
+    // avoids rounding each lane's slot count up to even.  Auto keeps the
+    // wide loads unless they cost more than 3% extra padded slots.
+    L.vec = o.vec ? o.vec : (double(slots2) <= 1.03 * double(slots1) ? 2 : 1);
+    const int32_t V = L.vec;
+    L.groups.clear();
+    std::fill(std::begin(L.groups_by_lanes), std::end(L.groups_by_lanes), 0);
+    int64_t slots = 0;
+    for (const Raw &r : raw) {
+        const int32_t width = (r.w + V - 1) / V * V;
         if (slots / kWave >= INT32_MAX)
             return set_error(FS_E_UNSUPPORTED, "layout too large");
-        L.groups.push_back(Group{int32_t(slots / kWave), i, rows,
-                                 width | (lt << 24)});
-        L.groups_by_lanes[lt]++;
+        L.groups.push_back(Group{int32_t(slots / kWave), r.row0, r.rows,
+                                 width | (r.lt << 24)});
+        L.groups_by_lanes[r.lt]++;
         slots += int64_t(width) * kWave;
-        i += rows;
     }
     if (slots >= INT32_MAX)
         return set_error(FS_E_UNSUPPORTED,
@@ -318,8 +333,8 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
             for (size_t e = 0; e < ent.size(); ++e) {
                 const int32_t lane = rr * T + int32_t(e) % T;
                 const int32_t s = int32_t(e) / T;
-                const int64_t idx = base + int64_t(s / kVec) * kWave * kVec +
-                                    int64_t(lane) * kVec + s % kVec;
+                const int64_t idx = base + int64_t(s / V) * kWave * V +
+                                    int64_t(lane) * V + s % V;
                 L.slot_col[size_t(idx)] = ent[e].first;
                 L.map[size_t(k0 + ent[e].second)] = int32_t(idx);
             }

@@ -59,14 +59,15 @@ def emulate(lay, x, n_rows):
     code: checks the layout, not the kernel)."""
     y = np.zeros(n_rows)
     sc = lay["slot_col"]
+    V = lay["vec"]
     for base64, row0, nrows, wlt in lay["groups"]:
         width, lt = wlt & 0xFFFFFF, wlt >> 24
         T = 1 << lt
         base = int(base64) * 64
         lanes = np.arange(64)
         s = np.arange(width)
-        idx = base + (s[:, None] // 2) * 128 + lanes[None, :] * 2 + \
-            (s[:, None] % 2)
+        idx = base + (s[:, None] // V) * 64 * V + lanes[None, :] * V + \
+            (s[:, None] % V)
         cols = sc[idx]
         vals = lay["val"][idx]
         prod = np.where(cols >= 0, vals * x[np.maximum(cols, 0)], 0.0)
@@ -98,7 +99,7 @@ def check_layout(A, lay, square=True):
         width, lt = wlt & 0xFFFFFF, wlt >> 24
         T = 1 << lt
         assert row0 == row and 1 <= nrows <= 64 // T
-        assert base64 * 64 == slot and width % 2 == 0
+        assert base64 * 64 == slot and width % lay["vec"] == 0
         lens = rl[perm[row0:row0 + nrows]]
         assert width * T >= lens.max()
         row += nrows
@@ -126,6 +127,10 @@ CASES = [
      dict(threshold=4)),
     ("q1_rcm_w1", lambda: W.hex_q1(5, "elastic", seed=(60, 2), permute=True),
      dict(reorder=2, sort_window=1)),
+    ("ela_v1", lambda: W.tet_p1(6, "elastic", seed=(60, 3), bc="x0",
+                                permute=True), dict(vec=1)),
+    ("p2_v2_t2", lambda: W.tet_p2(3, "elastic", seed=(60, 4)),
+     dict(vec=2, lanes_min=2, lanes_max=2)),
 ]
 
 
@@ -226,7 +231,8 @@ def test_host_layout_worked_example():
     lane = r - row0
     width = wlt & 0xFFFFFF
     s = np.arange(5)
-    idx = base64 * 64 + (s // 2) * 128 + lane * 2 + s % 2
+    V = lay["vec"]
+    idx = base64 * 64 + (s // V) * 64 * V + lane * V + s % V
     assert list(lay["slot_col"][idx] + 1) == g["c_dprime"]
     assert list(lay["val"][idx]) == g["A_dprime"]
     assert width >= 5

@@ -47,6 +47,9 @@ LAYOUTS = [
     dict(reorder=2, sort_window=1),
     dict(sort_window=1024, threshold=4),
     dict(threshold=64),
+    dict(vec=1),
+    dict(vec=1, lanes_min=4, lanes_max=4),
+    dict(vec=2, lanes_min=1, lanes_max=1, sort_window=1),
 ]
 
 
@@ -55,7 +58,7 @@ def test_config0_all_layouts(fs, orc, li):
     run_spmv(fs, orc, W.config0_poisson2d(), LAYOUTS[li], li, "cfg0")
 
 
-@pytest.mark.parametrize("li", [0, 1, 3, 5, 8])
+@pytest.mark.parametrize("li", [0, 1, 3, 5, 8, 12, 13, 14])
 def test_elasticity_layouts(fs, orc, li):
     A = W.tet_p1(12, "elastic", seed=(51, 0), bc="x0", permute=True)
     run_spmv(fs, orc, A, LAYOUTS[li], li, "ela12")
@@ -70,7 +73,7 @@ def test_sweep_small(fs, orc, i, permuted):
 
 @pytest.mark.parametrize("nr,nc", [(1, 1), (63, 63), (65, 65), (1000, 1000),
                                    (4099, 4099), (300, 1200), (1500, 40)])
-@pytest.mark.parametrize("li", [0, 1, 4])
+@pytest.mark.parametrize("li", [0, 1, 4, 12])
 def test_ragged_rows(fs, orc, nr, nc, li):
     A = ragged(nr, nc, seed=nr * 7 + nc)
     run_spmv(fs, orc, A, LAYOUTS[li], nr, "ragged%dx%d" % (nr, nc))
