@@ -87,16 +87,16 @@ typedef struct fs_csr_opts {
                               consecutive windows of this many rows, after
                               the reordering; 1 disables; 0 = default 256  */
     int32_t threshold;     /* most slots one lane may own before the row is
-                              spread over more lanes; 0 = default 16       */
+                              spread over more lanes; 0 = default 48       */
     int32_t lanes_min;     /* lanes per row bounds, powers of two in 1..64; */
     int32_t lanes_max;     /*   0 = defaults 1 and 64                       */
     int32_t dtypes;        /* extra low-precision copies (FS_DT_F32/BF16)   */
     int32_t vec;           /* slots each lane loads at once: 1 or 2; 0 =
-                              auto (2 unless it adds > 3% padded slots)    */
+                              auto (2 unless it adds > 6% padded slots)    */
     int32_t reserved[7];   /* must be zero                                   */
 } fs_csr_opts;
 
-/* Fill *o with the defaults (AUTO reorder, window 256, threshold 16,
+/* Fill *o with the defaults (AUTO reorder, window 256, threshold 48,
  * lanes 1..64, FP64 only). */
 fs_status csr_opts_default(fs_csr_opts *o);
 
@@ -188,6 +188,14 @@ fs_status csr_permute(fs_csr_t A, int32_t dir, const double *in, double *out,
 fs_status spmm(fs_csr_t A, int32_t k, const double *X, int64_t ldx,
                double *Y, int64_t ldy, hipStream_t s);
 
+/* Low-precision product in the layout numbering: y' = A'_lo x' with the FP32
+ * or BF16 copy of the values (csr_add_dtype first), float x' and y', float
+ * accumulation.  The inner operation of mixed-precision refinement; BF16
+ * values are widened to float exactly.  Square matrices only.
+ * Asynchronous on s. */
+fs_status spmv_lowp(fs_csr_t A, int32_t dtype, const float *xp, float *yp,
+                    hipStream_t s);
+
 /* --------------------------------------------------------------- solvers */
 enum { FS_PC_NONE = 0, FS_PC_JACOBI = 1 };
 enum { FS_PREC_F64 = 0, FS_PREC_IR_F32 = 1, FS_PREC_IR_BF16 = 2 };
@@ -228,6 +236,17 @@ typedef struct fs_cg_info {
  * (x = last iterate), FS_E_BREAKDOWN, or an argument/runtime error. */
 fs_status cg_solve(fs_csr_t A, const double *b, double *x,
                    const fs_cg_opts *opts, fs_cg_info *info, hipStream_t s);
+
+/* k independent solves A X[:, c] = B[:, c], 1 <= k <= 16, advanced
+ * together: one multi-column product per iteration (the k columns of a row
+ * of X are contiguous, so one gathered row serves all k).  B and X are
+ * n x k row-major device blocks with row strides ldb, ldx >= k.  Each
+ * column's iterates are exactly those of a cg_solve of that column alone
+ * (columns stop independently).  info (may be NULL) receives k entries.
+ * Blocking; returns the worst column status. */
+fs_status cg_solve_multi(fs_csr_t A, int32_t k, const double *B, int64_t ldb,
+                         double *X, int64_t ldx, const fs_cg_opts *opts,
+                         fs_cg_info *info, hipStream_t s);
 
 #ifdef __cplusplus
 }

@@ -83,7 +83,7 @@ EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "csr_layout_host",
            "csr_update_values", "csr_add_dtype", "csr_info", "csr_get_perm",
            "csr_destroy", "spmv", "spmv_perm", "csr_permute", "spmm",
-           "cg_opts_default", "cg_solve"]
+           "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_multi"]
 
 _lib = None
 
@@ -120,8 +120,11 @@ def load(build_if_missing=True):
         "spmv_perm": [vp, vp, vp, vp],
         "csr_permute": [vp, i32, vp, vp, vp],
         "spmm": [vp, i32, vp, i64, vp, i64, vp],
+        "spmv_lowp": [vp, i32, vp, vp, vp],
         "cg_opts_default": [P(CgOpts)],
         "cg_solve": [vp, vp, vp, P(CgOpts), P(CgInfo), vp],
+        "cg_solve_multi": [vp, i32, vp, i64, vp, i64, P(CgOpts), P(CgInfo),
+                           vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -323,6 +326,19 @@ def spmm(A, X, Y=None, stream=None):
     return Y
 
 
+def spmv_lowp(A, dtype, xp, yp=None, stream=None):
+    """y' = A'_lo x' in layout numbering with float vectors (FP32 or BF16
+    values, float accumulation)."""
+    import torch
+    if yp is None:
+        yp = torch.empty(A.n_rows, dtype=torch.float32, device=xp.device)
+    _check(load().spmv_lowp(A._h, int(dtype),
+                            _ptr(xp, torch.float32, A.n_cols, "x"),
+                            _ptr(yp, torch.float32, A.n_rows, "y"),
+                            _stream(stream)))
+    return yp
+
+
 def cg_opts(**kw):
     o = CgOpts()
     load().cg_opts_default(C.byref(o))
@@ -350,3 +366,28 @@ def cg_solve(A, b, x=None, stream=None, check=True, **opts):
                                             FS_E_BREAKDOWN)):
         raise FsError(st, d["message"])
     return x, d
+
+
+def cg_solve_multi(A, B, X=None, stream=None, check=True, **opts):
+    """Solve A X[:, c] = B[:, c] for the k <= 16 columns of the n x k block
+    B together; returns (X, list of k info dicts)."""
+    import torch
+    n, k = B.shape
+    if X is None:
+        X = torch.zeros((n, k), dtype=torch.float64, device=B.device)
+        opts.setdefault("x0_zero", 1)
+    o = cg_opts(**opts)
+    infos = (CgInfo * k)()
+    st = load().cg_solve_multi(A._h, k, _ptr(B, torch.float64, n * k, "B"),
+                               B.stride(0),
+                               _ptr(X, torch.float64, n * k, "X"),
+                               X.stride(0), C.byref(o), infos,
+                               _stream(stream))
+    out = [i.as_dict() for i in infos]
+    msg = last_error() if st != FS_OK else ""
+    for d in out:
+        d["message"] = msg
+    if st != FS_OK and (check or st not in (FS_E_NOT_CONVERGED,
+                                            FS_E_BREAKDOWN)):
+        raise FsError(st, msg)
+    return X, out

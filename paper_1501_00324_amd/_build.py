@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfespmv.so")
-SOURCES = ["api.cpp", "layout.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "layout.cpp", "solver.cpp", "kernels.hip", "engine.hip"]
 ARCH = os.environ.get("FESPMV_ARCH", "gfx950")
 
 FLAGS = [
@@ -28,8 +28,8 @@ def needs_build():
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    deps = sources() + [os.path.join(CSRC, "internal.h"),
-                        os.path.join(HERE, "..", "include", "fespmv.h")]
+    deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + \
+        [os.path.join(HERE, "..", "include", "fespmv.h")]
     return any(os.path.getmtime(d) > t for d in deps)
 
 

@@ -57,27 +57,12 @@ template <class T> void dfree(T *&p)
     p = nullptr;
 }
 
-void free_cg(CgWork &w)
-{
-    if (w.graph) (void)hipGraphExecDestroy(w.graph);
-    w.graph = nullptr;
-    dfree(w.x); dfree(w.r); dfree(w.p); dfree(w.q); dfree(w.b);
-    dfree(w.dinv); dfree(w.partials); dfree(w.sc);
-    if (w.sc_host) (void)hipHostFree(w.sc_host);
-    w.sc_host = nullptr;
-    if (w.done_ev) (void)hipEventDestroy(w.done_ev);
-    w.done_ev = nullptr;
-    if (w.stream) (void)hipStreamDestroy(w.stream);
-    w.stream = nullptr;
-    w.n = 0;
-}
-
 void free_handle(fs_csr *A)
 {
-    free_cg(A->cg);
+    free_solver_state(A);
     dfree(A->d_groups); dfree(A->d_val); dfree(A->d_val_f32);
     dfree(A->d_val_bf16); dfree(A->d_col); dfree(A->d_map);
-    dfree(A->d_perm); dfree(A->d_iperm); dfree(A->d_xtmp);
+    dfree(A->d_perm); dfree(A->d_iperm); dfree(A->d_xtmp); dfree(A->d_Xtmp);
 }
 
 fs_status check_handle(const fs_csr *A)
@@ -115,7 +100,7 @@ fs_status csr_opts_default(fs_csr_opts *o)
     std::memset(o, 0, sizeof *o);
     o->reorder = FS_REORDER_AUTO;
     o->sort_window = 256;
-    o->threshold = 16;
+    o->threshold = 48;
     o->lanes_min = 1;
     o->lanes_max = 64;
     return FS_OK;
@@ -393,201 +378,71 @@ fs_status csr_permute(fs_csr_t A, int32_t dir, const double *in, double *out,
 fs_status spmm(fs_csr_t A, int32_t k, const double *X, int64_t ldx,
                double *Y, int64_t ldy, hipStream_t s)
 {
-    (void)A; (void)k; (void)X; (void)ldx; (void)Y; (void)ldy; (void)s;
-    return set_error(FS_E_UNSUPPORTED, "spmm is not built yet");
+    FS_TRY(check_handle(A));
+    if (k < 1 || k > 16) return set_error(FS_E_ARG, "k = %d, must be in [1, 16]", k);
+    if (ldx < k || ldy < k) return set_error(FS_E_ARG, "leading dimension below k");
+    if ((!X && A->n_cols) || (!Y && A->n_rows))
+        return set_error(FS_E_ARG, "NULL block");
+    if (X == Y && X) return set_error(FS_E_ARG, "X and Y must not alias");
+    DeviceGuard g(A->device);
+    const HostLayout &L = A->host;
+    if (L.identity) {
+        FS_HIP_TRY(launch_spmm_f64(A, k, X, ldx, Y, ldy, nullptr, s));
+    } else if (L.symmetric_relabel) {
+        // X' = X(perm, :) in a k-wide buffer, then Y(perm[row], :) = (A' X')
+        const int64_t need = int64_t(A->n_cols) * k;
+        if (need > A->xtmp_cap) {
+            FS_HIP_TRY(hipStreamSynchronize(s));
+            dfree(A->d_Xtmp);
+            A->xtmp_cap = 0;
+            FS_TRY(dalloc(&A->d_Xtmp, int64_t(A->n_cols) * 16, A->device_bytes));
+            A->xtmp_cap = int64_t(A->n_cols) * 16;
+        }
+        FS_HIP_TRY(permute_rows(A->n_cols, k, A->d_perm, X, ldx, A->d_Xtmp, k,
+                                true, s));
+        FS_HIP_TRY(launch_spmm_f64(A, k, A->d_Xtmp, k, Y, ldy, A->d_perm, s));
+    } else {
+        FS_HIP_TRY(launch_spmm_f64(A, k, X, ldx, Y, ldy, A->d_perm, s));
+    }
+    return FS_OK;
+}
+
+fs_status spmv_lowp(fs_csr_t A, int32_t dtype, const float *xp, float *yp,
+                    hipStream_t s)
+{
+    FS_TRY(check_handle(A));
+    if (A->n_rows != A->n_cols)
+        return set_error(FS_E_NOT_SQUARE, "spmv_lowp needs a square matrix");
+    if (dtype != FS_DT_F32 && dtype != FS_DT_BF16)
+        return set_error(FS_E_ARG, "dtype must be FS_DT_F32 or FS_DT_BF16");
+    if (!(A->dtypes & dtype))
+        return set_error(FS_E_ARG, "no %s copy: call csr_add_dtype first",
+                         dtype == FS_DT_F32 ? "FP32" : "BF16");
+    if ((!xp || !yp) && A->n_rows) return set_error(FS_E_ARG, "NULL vector");
+    if (xp == yp && xp) return set_error(FS_E_ARG, "x and y must not alias");
+    DeviceGuard g(A->device);
+    FS_HIP_TRY(launch_spmv_lowp(A, dtype, xp, yp, s));
+    return FS_OK;
 }
 
 fs_status csr_add_dtype(fs_csr_t A, int32_t dtype, hipStream_t s)
 {
-    (void)A; (void)dtype; (void)s;
-    return set_error(FS_E_UNSUPPORTED, "csr_add_dtype is not built yet");
+    FS_TRY(check_handle(A));
+    if (dtype != FS_DT_F32 && dtype != FS_DT_BF16)
+        return set_error(FS_E_ARG, "dtype must be FS_DT_F32 or FS_DT_BF16");
+    if (A->dtypes & dtype) return FS_OK;
+    DeviceGuard g(A->device);
+    if (dtype == FS_DT_F32)
+        FS_TRY(dalloc(&A->d_val_f32, A->slots, A->device_bytes));
+    else
+        FS_TRY(dalloc(&A->d_val_bf16, A->slots, A->device_bytes));
+    FS_HIP_TRY(cast_slots(A->slots, A->d_val,
+                          dtype == FS_DT_F32 ? A->d_val_f32 : nullptr,
+                          dtype == FS_DT_BF16 ? A->d_val_bf16 : nullptr, s));
+    FS_HIP_TRY(hipStreamSynchronize(s));
+    A->dtypes |= dtype;
+    return FS_OK;
 }
 
 }  // extern "C"
 
-// ------------------------------------------------------------- CG driver
-namespace fs {
-namespace {
-
-fs_status ensure_cg(fs_csr *A, int32_t precond)
-{
-    CgWork &w = A->cg;
-    const int32_t n = A->n_rows;
-    if (w.n != n || !w.sc) {
-        free_cg(w);
-        int64_t acct = 0;
-        FS_TRY(dalloc(&w.x, n, acct));
-        FS_TRY(dalloc(&w.r, n, acct));
-        FS_TRY(dalloc(&w.p, n, acct));
-        FS_TRY(dalloc(&w.q, n, acct));
-        FS_TRY(dalloc(&w.b, n, acct));
-        w.nparts = cg_partials_needed(A);
-        FS_TRY(dalloc(&w.partials, w.nparts, acct));
-        FS_TRY(dalloc(&w.sc, 1, acct));
-        FS_HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&w.sc_host),
-                                 sizeof(CgScalars), hipHostMallocDefault));
-        FS_HIP_TRY(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking));
-        FS_HIP_TRY(hipEventCreateWithFlags(&w.done_ev, hipEventDisableTiming));
-        A->device_bytes += acct;
-        w.n = n;
-    }
-    if (precond && !w.dinv) {
-        FS_TRY(dalloc(&w.dinv, n, A->device_bytes));
-    }
-    return FS_OK;
-}
-
-fs_status launch_iterations(fs_csr *A, int32_t pc, int32_t k, hipStream_t s)
-{
-    CgWork &w = A->cg;
-    for (int32_t i = 0; i < k; ++i) {
-        FS_HIP_TRY(launch_cg_spmv_dot(A, w, s));
-        FS_HIP_TRY(launch_cg_update(w, pc, s));
-        FS_HIP_TRY(launch_cg_pupdate(w, pc, s));
-    }
-    return FS_OK;
-}
-
-fs_status run_chunk(fs_csr *A, int32_t pc, int32_t k, bool use_graph)
-{
-    CgWork &w = A->cg;
-    hipStream_t s = w.stream;
-    if (!use_graph) return launch_iterations(A, pc, k, s);
-    if (!w.graph || w.graph_k != k || w.graph_pc != pc) {
-        if (w.graph) (void)hipGraphExecDestroy(w.graph);
-        w.graph = nullptr;
-        hipGraph_t graph = nullptr;
-        FS_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        fs_status st = launch_iterations(A, pc, k, s);
-        hipError_t e = hipStreamEndCapture(s, &graph);
-        if (st != FS_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return st;
-        }
-        if (e != hipSuccess)
-            return set_error(FS_E_HIP, "graph capture: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&w.graph, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            w.graph = nullptr;
-            return set_error(FS_E_HIP, "graph instantiate: %s",
-                             hipGetErrorString(e));
-        }
-        w.graph_k = k;
-        w.graph_pc = pc;
-    }
-    FS_HIP_TRY(hipGraphLaunch(w.graph, s));
-    return FS_OK;
-}
-
-fs_status read_scalars(CgWork &w)
-{
-    FS_HIP_TRY(hipMemcpyAsync(w.sc_host, w.sc, sizeof(CgScalars),
-                              hipMemcpyDeviceToHost, w.stream));
-    FS_HIP_TRY(hipStreamSynchronize(w.stream));
-    return FS_OK;
-}
-
-fs_status cg_f64(fs_csr *A, const double *b, double *x, const fs_cg_opts &o,
-                 fs_cg_info &info, hipStream_t caller)
-{
-    CgWork &w = A->cg;
-    const int32_t n = A->n_rows, pc = o.precond;
-    FS_TRY(ensure_cg(A, pc));
-    hipStream_t s = w.stream;
-    // order after the caller's stream
-    FS_HIP_TRY(hipEventRecord(w.done_ev, caller));
-    FS_HIP_TRY(hipStreamWaitEvent(s, w.done_ev, 0));
-    const bool ident = A->host.identity;
-    if (ident) FS_HIP_TRY(hipMemcpyAsync(w.b, b, sizeof(double) * n,
-                                         hipMemcpyDeviceToDevice, s));
-    else FS_HIP_TRY(launch_gather(n, A->d_perm, b, w.b, s));
-    if (o.x0_zero) FS_HIP_TRY(hipMemsetAsync(w.x, 0, sizeof(double) * n, s));
-    else if (ident) FS_HIP_TRY(hipMemcpyAsync(w.x, x, sizeof(double) * n,
-                                              hipMemcpyDeviceToDevice, s));
-    else FS_HIP_TRY(launch_gather(n, A->d_perm, x, w.x, s));
-    FS_HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(CgScalars), s));
-    if (pc) FS_HIP_TRY(launch_diag_inv(A, w.dinv, w.sc, s));
-    FS_HIP_TRY(launch_cg_residual(A, w, pc, 0, o.rtol, o.maxit, o.x0_zero, s));
-    FS_TRY(read_scalars(w));
-    if (pc && w.sc_host->pad[0] > 0)
-        return set_error(FS_E_ARG, "Jacobi preconditioner: %d rows with a "
-                         "zero or non-finite diagonal", w.sc_host->pad[0]);
-    while (!w.sc_host->done) {
-        FS_TRY(run_chunk(A, pc, o.check_every, o.use_graph != 0));
-        FS_TRY(read_scalars(w));
-        if (w.sc_host->status == CG_RECURRENCE_MET) {
-            FS_HIP_TRY(launch_cg_residual(A, w, pc, 1, o.rtol, o.maxit, 0, s));
-            FS_TRY(read_scalars(w));
-            if (!w.sc_host->done)   // replaced residual: finish this iteration
-                FS_HIP_TRY(launch_cg_pupdate(w, pc, s));
-        }
-    }
-    const int32_t status = w.sc_host->status;
-    if (status != CG_CONVERGED) {
-        FS_HIP_TRY(launch_cg_residual(A, w, pc, 2, o.rtol, o.maxit, 0, s));
-        FS_TRY(read_scalars(w));
-    }
-    if (w.sc_host->bnorm2 == 0.0)
-        FS_HIP_TRY(hipMemsetAsync(w.x, 0, sizeof(double) * n, s));
-    if (ident) FS_HIP_TRY(hipMemcpyAsync(x, w.x, sizeof(double) * n,
-                                         hipMemcpyDeviceToDevice, s));
-    else FS_HIP_TRY(launch_scatter(n, A->d_perm, w.x, x, s));
-    FS_HIP_TRY(hipStreamSynchronize(s));
-    const CgScalars &h = *w.sc_host;
-    info.iters = h.iter;
-    info.replacements = h.replacements;
-    info.relres = h.bnorm2 > 0.0 ? std::sqrt(h.rr_true / h.bnorm2) : 0.0;
-    const double it_bytes = 12.0 * double(A->nnz) + (pc ? 104.0 : 88.0) * n;
-    const double spmv_bytes = 12.0 * double(A->nnz) + 16.0 * n;
-    info.bytes = h.iter * it_bytes +
-                 (2.0 + h.replacements + (status != CG_CONVERGED)) * spmv_bytes;
-    switch (status) {
-    case CG_CONVERGED: return FS_OK;
-    case CG_MAXIT:
-        return set_error(FS_E_NOT_CONVERGED,
-                         "CG: %d iterations, relative residual %.3e",
-                         h.iter, info.relres);
-    default:
-        return set_error(FS_E_BREAKDOWN,
-                         "CG breakdown after %d iterations (p.Ap = %.3e)",
-                         h.iter, h.gamma);
-    }
-}
-
-}  // namespace
-}  // namespace fs
-
-extern "C" fs_status cg_solve(fs_csr_t A, const double *b, double *x,
-                              const fs_cg_opts *opts, fs_cg_info *info,
-                              hipStream_t s)
-{
-    const double t0 = now_ms();
-    fs_cg_info local;
-    std::memset(&local, 0, sizeof local);
-    fs_status st = check_handle(A);
-    if (st == FS_OK && A->n_rows != A->n_cols)
-        st = set_error(FS_E_NOT_SQUARE, "cg_solve needs a square matrix");
-    if (st == FS_OK && A->n_rows > 0 && (!b || !x))
-        st = set_error(FS_E_ARG, "NULL vector");
-    fs_cg_opts o;
-    cg_opts_default(&o);
-    if (opts) o = *opts;
-    if (o.rtol <= 0.0) o.rtol = 1e-8;
-    if (o.maxit <= 0) o.maxit = 20000;
-    if (o.check_every <= 0) o.check_every = 32;
-    if (o.inner_rtol <= 0.0) o.inner_rtol = 1e-2;
-    if (o.max_outer <= 0) o.max_outer = 50;
-    if (st == FS_OK && o.precond != FS_PC_NONE && o.precond != FS_PC_JACOBI)
-        st = set_error(FS_E_ARG, "unknown preconditioner %d", o.precond);
-    if (st == FS_OK && o.precision != FS_PREC_F64)
-        st = set_error(FS_E_UNSUPPORTED, "mixed precision is not built yet");
-    if (st == FS_OK && A->n_rows > 0) {
-        DeviceGuard g(A->device);
-        st = cg_f64(A, b, x, o, local, s);
-    }
-    local.status = st;
-    local.ms = now_ms() - t0;
-    if (info) *info = local;
-    return st;
-}

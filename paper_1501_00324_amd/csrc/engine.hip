@@ -1,0 +1,852 @@
+// Batched, multi-right-hand-side conjugate-gradient engine.
+//
+// One launch advances every running right-hand side of every system in a
+// batch: systems own contiguous block ranges of the grid (a block -> system
+// map), so a batch of many small systems costs the same three launches per
+// iteration as one large system, and each system's arithmetic -- including
+// its reduction trees, which depend only on its own size -- is identical
+// whether it runs alone or in a batch.  A single solve is a batch of one
+// system with one column.
+//
+// Per iteration (textbook preconditioned CG, the solver the paper runs
+// around its SpMV; M = diag(A) or I):
+//   k_spmm_dot   : Q = A P, per-block partials of p_c . q_c
+//   k_fin_dot    : gamma_c, alpha_c = rho_c / gamma_c (breakdown check)
+//   k_update     : x += alpha p, r -= alpha q, z = M^-1 r; partials of r.z
+//                  and r.r
+//   k_fin_update : stop a column when |r| <= rtol |b| (confirmed by the host
+//                  against the true residual), else beta and rho
+//   k_pupdate    : p = z + beta p
+// Reductions are two kernels: per-block partials in a fixed order, then one
+// block per (system, column) sums them in index order.  No atomics and no
+// fences: kernel boundaries order everything, and the sums depend only on
+// the system's own grid.
+// Vectors are n x k row-major.  Sums over a row's slots follow one fixed
+// order per column (even slots, odd slots, then the lanes of the row), so a
+// column's result does not depend on how many columns share the launch.
+// The vector type ST is double for FP64 solves and float for the inner
+// solve of mixed-precision refinement; values VT are double, float or bf16;
+// every dot product is accumulated in double.
+#include <type_traits>
+
+#include "device.h"
+
+namespace fs {
+namespace {
+
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+
+constexpr int kMaxSpmvBlocks = 2048;
+
+template <typename VT, int V> struct Pack;
+template <> struct Pack<double, 1> { typedef double T; };
+template <> struct Pack<double, 2> { typedef dv2 T; };
+template <> struct Pack<float, 1> { typedef float T; };
+template <> struct Pack<float, 2> { typedef fv2 T; };
+template <> struct Pack<uint16_t, 1> { typedef uint16_t T; };
+template <> struct Pack<uint16_t, 2> { typedef us2 T; };
+
+template <typename ST> __device__ __forceinline__ ST widen(double v) { return ST(v); }
+template <typename ST> __device__ __forceinline__ ST widen(float v) { return ST(v); }
+template <typename ST> __device__ __forceinline__ ST widen(uint16_t h)
+{
+    return ST(__uint_as_float(uint32_t(h) << 16));
+}
+
+template <typename VT, typename ST, int V>
+__device__ __forceinline__ void unpack(typename Pack<VT, V>::T a, ST (&o)[V])
+{
+    if constexpr (V == 1) {
+        o[0] = widen<ST>(a);
+    } else {
+        o[0] = widen<ST>(a.x);
+        o[1] = widen<ST>(a.y);
+    }
+}
+
+template <int V> __device__ __forceinline__ void unpack_col(
+    typename Slots<V>::I c, int (&o)[V])
+{
+    if constexpr (V == 1) {
+        o[0] = c;
+    } else {
+        o[0] = c.x;
+        o[1] = c.y;
+    }
+}
+
+// acc{0,1}[c] += a * X[col, c] over this lane's slots, even slots into
+// acc0, odd slots into acc1.  Padded slots (col -1) read row 0 of X and
+// drop the product through a select.
+template <typename VT, typename ST, int V, int KM>
+__device__ __forceinline__ void lane_sums(const Group &g, int lane,
+                                          const VT *__restrict__ val,
+                                          const int *__restrict__ col,
+                                          const ST *__restrict__ X, int k,
+                                          long ldx, ST (&acc0)[KM],
+                                          ST (&acc1)[KM])
+{
+    typedef typename Pack<VT, V>::T PV;
+    typedef typename Slots<V>::I PI;
+    constexpr int U0 = KM == 1 ? 8 : (KM == 2 ? 4 : 2);
+    constexpr int U = U0 / V > 0 ? U0 / V : 1;
+    const int width = g.width_lt & 0xffffff;
+    const long base = long(g.base64) * kWave;
+    const PV *pv = reinterpret_cast<const PV *>(val + base) + lane;
+    const PI *pc = reinterpret_cast<const PI *>(col + base) + lane;
+    const int nch = width / V;
+    auto slot = [&](int c, ST a, bool odd) {
+        const ST *xr = X + long(c < 0 ? 0 : c) * ldx;
+#pragma unroll
+        for (int q = 0; q < KM; ++q) {
+            if (KM == 1 || q < k) {
+                const ST xv = xr[q];
+                ST &acc = odd ? acc1[q] : acc0[q];
+                acc = fma(a, c >= 0 ? xv : ST(0), acc);
+            }
+        }
+    };
+    int j = 0;
+    for (; j + U <= nch; j += U) {
+        PI c[U];
+        PV a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            c[u] = __builtin_nontemporal_load(pc + (j + u) * kWave);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            a[u] = __builtin_nontemporal_load(pv + (j + u) * kWave);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int cc[V];
+            ST aa[V];
+            unpack_col<V>(c[u], cc);
+            unpack<VT, ST, V>(a[u], aa);
+#pragma unroll
+            for (int t = 0; t < V; ++t)
+                slot(cc[t], aa[t], ((j + u) * V + t) & 1);
+        }
+    }
+    for (; j < nch; ++j) {
+        int cc[V];
+        ST aa[V];
+        unpack_col<V>(__builtin_nontemporal_load(pc + j * kWave), cc);
+        unpack<VT, ST, V>(__builtin_nontemporal_load(pv + j * kWave), aa);
+#pragma unroll
+        for (int t = 0; t < V; ++t) slot(cc[t], aa[t], (j * V + t) & 1);
+    }
+}
+
+__device__ __forceinline__ bool any_running(const SysDesc &S)
+{
+    for (int c = 0; c < S.k; ++c)
+        if (S.cs[c].status == CG_RUNNING) return true;
+    return false;
+}
+
+// Fold NV per-thread values over the block (wave butterflies, then the
+// waves in order) and store them as this block's partials.
+template <int NV>
+__device__ __forceinline__ void store_partials(double (&v)[NV], int nact,
+                                               double *partials, int nblk,
+                                               int b)
+{
+    __shared__ double sh[NV][kWavesPerBlock];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        if (j >= nact) continue;
+        const double s = wave_sum(v[j]);
+        if (lane == 0) sh[j][w] = s;
+    }
+    __syncthreads();
+    if (int(threadIdx.x) < nact) {
+        double s = 0.0;
+        for (int i = 0; i < kWavesPerBlock; ++i) s += sh[threadIdx.x][i];
+        partials[long(threadIdx.x) * nblk + b] = s;
+    }
+}
+
+// Sum of partials[j * nblk + 0 .. nblk-1] for j < NJ, in index order
+// (thread t takes t, t + 256, ...; then the block folds).  Valid in thread 0.
+template <int NJ>
+__device__ __forceinline__ void sum_partials(const double *partials, int nblk,
+                                             int j0, double (&out)[NJ])
+{
+    __shared__ double sh[NJ][kWavesPerBlock];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const double *pj = partials + long(j0 + j) * nblk;
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nblk; i += kBlock) s += pj[i];
+        s = wave_sum(s);
+        if (lane == 0) sh[j][w] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        double t = 0.0;
+        for (int i = 0; i < kWavesPerBlock; ++i) t += sh[j][i];
+        out[j] = t;
+    }
+}
+
+// Q = A P for every column, gamma_c = p_c . q_c; the system's last block
+// sets alpha_c = rho_c / gamma_c or flags a breakdown.
+template <typename VT, typename ST, int V, int KM>
+__global__ __launch_bounds__(kBlock) void k_spmm_dot(
+    const SysDesc *__restrict__ sys, const int *__restrict__ smap)
+{
+    const int gb = xcd_remap(blockIdx.x, gridDim.x);
+    const SysDesc &S = sys[smap[gb]];
+    if (!any_running(S)) return;
+    const int lb = gb - S.sb0, nb = S.snb, k = S.k;
+    const VT *val = static_cast<const VT *>(S.val);
+    const ST *P = static_cast<const ST *>(S.p);
+    ST *Q = static_cast<ST *>(S.q);
+    const int g0 = int(long(lb) * S.ngroups / nb);
+    const int g1 = int(long(lb + 1) * S.ngroups / nb);
+    const int lane = threadIdx.x & (kWave - 1);
+    double dot[KM];
+#pragma unroll
+    for (int c = 0; c < KM; ++c) dot[c] = 0.0;
+    for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
+        const Group gd = load_group(S.groups, __builtin_amdgcn_readfirstlane(g));
+        ST a0[KM], a1[KM];
+#pragma unroll
+        for (int c = 0; c < KM; ++c) a0[c] = a1[c] = ST(0);
+        lane_sums<VT, ST, V, KM>(gd, lane, val, S.col, P, k, k, a0, a1);
+        const int lt = gd.width_lt >> 24, r = lane >> lt;
+        const bool owner = (lane & ((1 << lt) - 1)) == 0 && r < gd.nrows;
+        const long row = gd.row0 + r;
+#pragma unroll
+        for (int c = 0; c < KM; ++c) {
+            if (KM > 1 && c >= k) continue;
+            const ST v = row_reduce(a0[c] + a1[c], lt);
+            if (owner) {
+                Q[row * k + c] = v;
+                dot[c] += double(P[row * k + c]) * double(v);
+            }
+        }
+    }
+    store_partials<KM>(dot, KM == 1 ? 1 : k, S.partials, nb, lb);
+}
+
+// One block per (system, column): gamma = p.q, alpha = rho / gamma.
+__global__ __launch_bounds__(kBlock) void k_fin_dot(
+    const SysDesc *__restrict__ sys, const int2 *__restrict__ cmap)
+{
+    const int2 sc = cmap[blockIdx.x];
+    const SysDesc &S = sys[sc.x];
+    ColState &cs = S.cs[sc.y];
+    if (cs.status != CG_RUNNING) return;
+    double t[1];
+    sum_partials<1>(S.partials, S.snb, sc.y, t);
+    if (threadIdx.x == 0) {
+        cs.gamma = t[0];
+        if (!(t[0] > 0.0) || !isfinite(t[0])) cs.status = CG_BREAKDOWN;
+        else cs.alpha = cs.rho / t[0];
+    }
+}
+
+template <typename ST, int KM>
+__global__ __launch_bounds__(kBlock) void k_update(
+    const SysDesc *__restrict__ sys, const int *__restrict__ vmap)
+{
+    const SysDesc &S = sys[vmap[blockIdx.x]];
+    const int lb = blockIdx.x - S.vb0, nb = S.vnb, k = S.k, n = S.n;
+    ST *X = static_cast<ST *>(S.x);
+    ST *R = static_cast<ST *>(S.r);
+    const ST *P = static_cast<const ST *>(S.p);
+    const ST *Q = static_cast<const ST *>(S.q);
+    const ST *D = static_cast<const ST *>(S.dinv);
+    bool run[KM];
+    ST alpha[KM];
+    bool anyr = false;
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+        run[c] = c < k && S.cs[c].status == CG_RUNNING;
+        alpha[c] = run[c] ? ST(S.cs[c].alpha) : ST(0);
+        anyr |= run[c];
+    }
+    if (!anyr) return;
+    double v[2 * KM];
+#pragma unroll
+    for (int c = 0; c < 2 * KM; ++c) v[c] = 0.0;
+    for (int i = lb * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
+        const ST di = D ? D[i] : ST(1);
+#pragma unroll
+        for (int c = 0; c < KM; ++c) {
+            if (!run[c]) continue;
+            const long e = long(i) * k + c;
+            const ST ri = R[e] - alpha[c] * Q[e];
+            X[e] += alpha[c] * P[e];
+            R[e] = ri;
+            const ST zi = D ? di * ri : ri;
+            v[2 * c] += double(ri) * double(zi);
+            v[2 * c + 1] += double(ri) * double(ri);
+        }
+    }
+    store_partials<2 * KM>(v, 2 * (KM == 1 ? 1 : k), S.partials, nb, lb);
+}
+
+// One block per (system, column): count the iteration; stop when the
+// recurrence residual meets the tolerance, else beta = rz / rho.
+__global__ __launch_bounds__(kBlock) void k_fin_update(
+    const SysDesc *__restrict__ sys, const int2 *__restrict__ cmap)
+{
+    const int2 sc = cmap[blockIdx.x];
+    const SysDesc &S = sys[sc.x];
+    ColState &cs = S.cs[sc.y];
+    if (cs.status != CG_RUNNING) return;
+    double t[2];
+    sum_partials<2>(S.partials, S.vnb, 2 * sc.y, t);
+    if (threadIdx.x != 0) return;
+    const double rz = t[0], rr = t[1];
+    cs.iter += 1;
+    cs.rr = rr;
+    if (rr <= cs.tol2) {
+        cs.status = CG_RECURRENCE_MET;
+        return;
+    }
+    const double beta = rz / cs.rho;
+    if (!isfinite(beta) || !isfinite(rr)) {
+        cs.status = CG_BREAKDOWN;
+        return;
+    }
+    cs.beta = beta;
+    cs.rho = rz;
+    if (cs.iter >= cs.maxit) cs.status = CG_MAXIT;
+}
+
+// p = z + beta p for running columns (PENDING = false) or for the columns
+// whose residual was just replaced (PENDING = true).
+template <typename ST, int KM, bool PENDING>
+__global__ __launch_bounds__(kBlock) void k_pupdate(
+    const SysDesc *__restrict__ sys, const int *__restrict__ vmap)
+{
+    const SysDesc &S = sys[vmap[blockIdx.x]];
+    const int lb = blockIdx.x - S.vb0, nb = S.vnb, k = S.k, n = S.n;
+    ST *P = static_cast<ST *>(S.p);
+    const ST *R = static_cast<const ST *>(S.r);
+    const ST *D = static_cast<const ST *>(S.dinv);
+    bool upd[KM];
+    ST beta[KM];
+    bool anyu = false;
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+        upd[c] = c < k && (PENDING ? S.cs[c].pending != 0
+                                   : S.cs[c].status == CG_RUNNING);
+        beta[c] = upd[c] ? ST(S.cs[c].beta) : ST(0);
+        anyu |= upd[c];
+    }
+    if (!anyu) return;
+    for (int i = lb * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
+        const ST di = D ? D[i] : ST(1);
+#pragma unroll
+        for (int c = 0; c < KM; ++c) {
+            if (!upd[c]) continue;
+            const long e = long(i) * k + c;
+            const ST zi = D ? di * R[e] : R[e];
+            P[e] = zi + beta[c] * P[e];
+        }
+    }
+}
+
+// r = b - A x (x = 0: r = b) for every column, z = M^-1 r, with r.r, r.z
+// and b.b.  MODE 0 starts a solve (writes r and p = z, sets the column
+// state); MODE 1 checks the columns whose recurrence residual met the
+// tolerance against the true residual (writes r only for them; residual
+// replacement when the true residual is too large); MODE 2 only measures.
+template <typename VT, typename ST, int V, int KM, bool XZ, int MODE>
+__global__ __launch_bounds__(kBlock) void k_residual(
+    const SysDesc *__restrict__ sys, const int *__restrict__ smap)
+{
+    const int gb = xcd_remap(blockIdx.x, gridDim.x);
+    const SysDesc &S = sys[smap[gb]];
+    const int lb = gb - S.sb0, nb = S.snb, k = S.k;
+    const VT *val = static_cast<const VT *>(S.val);
+    const ST *X = static_cast<const ST *>(S.x);
+    const ST *B = static_cast<const ST *>(S.b);
+    const ST *D = static_cast<const ST *>(S.dinv);
+    ST *R = static_cast<ST *>(S.r);
+    ST *P = static_cast<ST *>(S.p);
+    bool wr[KM];
+#pragma unroll
+    for (int c = 0; c < KM; ++c)
+        wr[c] = c < k && (MODE == 0 ||
+                          (MODE == 1 && S.cs[c].status == CG_RECURRENCE_MET));
+    const int g0 = int(long(lb) * S.ngroups / nb);
+    const int g1 = int(long(lb + 1) * S.ngroups / nb);
+    const int lane = threadIdx.x & (kWave - 1);
+    double v[3 * KM];
+#pragma unroll
+    for (int c = 0; c < 3 * KM; ++c) v[c] = 0.0;
+    for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
+        const Group gd = load_group(S.groups, __builtin_amdgcn_readfirstlane(g));
+        ST a0[KM], a1[KM];
+#pragma unroll
+        for (int c = 0; c < KM; ++c) a0[c] = a1[c] = ST(0);
+        if (!XZ)
+            lane_sums<VT, ST, V, KM>(gd, lane, val, S.col, X, k, k, a0, a1);
+        const int lt = gd.width_lt >> 24, r = lane >> lt;
+        const bool owner = (lane & ((1 << lt) - 1)) == 0 && r < gd.nrows;
+        const long row = gd.row0 + r;
+        const ST di = (owner && D) ? D[row] : ST(1);
+#pragma unroll
+        for (int c = 0; c < KM; ++c) {
+            if (KM > 1 && c >= k) continue;
+            const ST ax = XZ ? ST(0) : row_reduce(a0[c] + a1[c], lt);
+            if (owner) {
+                const ST bi = B[row * k + c];
+                const ST ri = bi - ax;
+                const ST zi = D ? di * ri : ri;
+                if (wr[c]) R[row * k + c] = ri;
+                if (MODE == 0) P[row * k + c] = zi;
+                v[3 * c] += double(ri) * double(ri);
+                v[3 * c + 1] += double(ri) * double(zi);
+                v[3 * c + 2] += double(bi) * double(bi);
+            }
+        }
+    }
+    store_partials<3 * KM>(v, 3 * (KM == 1 ? 1 : k), S.partials, nb, lb);
+}
+
+// One block per (system, column) after k_residual.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_fin_residual(
+    const SysDesc *__restrict__ sys, const int2 *__restrict__ cmap)
+{
+    const int2 sc = cmap[blockIdx.x];
+    const SysDesc &S = sys[sc.x];
+    ColState &cs = S.cs[sc.y];
+    if (MODE == 1 && cs.status != CG_RECURRENCE_MET) {
+        if (threadIdx.x == 0) cs.pending = 0;
+        return;
+    }
+    double t[3];
+    sum_partials<3>(S.partials, S.snb, 3 * sc.y, t);
+    if (threadIdx.x != 0) return;
+    const double rr = t[0], rz = t[1], bb = t[2];
+    cs.rr_true = rr;
+    if (MODE == 0) {
+        cs.bnorm2 = bb;
+        cs.tol2 = S.rtol * S.rtol * bb;
+        cs.rho = rz;
+        cs.rr = rr;
+        cs.iter = 0;
+        cs.maxit = S.maxit;
+        cs.replacements = 0;
+        cs.pending = 0;
+        cs.alpha = cs.beta = cs.gamma = 0.0;
+        if (bb == 0.0 || rr <= cs.tol2) cs.status = CG_CONVERGED;
+        else if (!isfinite(rr) || !isfinite(rz)) cs.status = CG_BREAKDOWN;
+        else cs.status = CG_RUNNING;
+    } else if (MODE == 1) {
+        cs.pending = 0;
+        if (rr <= cs.tol2) {
+            cs.status = CG_CONVERGED;
+            return;
+        }
+        cs.replacements += 1;
+        cs.rr = rr;
+        const double beta = rz / cs.rho;
+        if (!isfinite(beta)) {
+            cs.status = CG_BREAKDOWN;
+            return;
+        }
+        cs.beta = beta;
+        cs.rho = rz;
+        if (cs.iter >= cs.maxit) {
+            cs.status = CG_MAXIT;
+        } else {
+            cs.status = CG_RUNNING;
+            cs.pending = 1;
+        }
+    }
+}
+
+// dinv = 1 / diag(A) in the launch's vector type; zero or non-finite
+// diagonals are counted in ctr->bad_diag.
+template <typename VT, typename ST, int V>
+__global__ __launch_bounds__(kBlock) void k_diag(
+    const SysDesc *__restrict__ sys, const int *__restrict__ smap)
+{
+    const int gb = blockIdx.x;
+    const SysDesc &S = sys[smap[gb]];
+    if (!S.dinv) return;                  // system without preconditioner
+    const int lb = gb - S.sb0, nb = S.snb;
+    const VT *val = static_cast<const VT *>(S.val);
+    ST *D = const_cast<ST *>(static_cast<const ST *>(S.dinv));
+    const int g0 = int(long(lb) * S.ngroups / nb);
+    const int g1 = int(long(lb + 1) * S.ngroups / nb);
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
+        const Group gd = load_group(S.groups, __builtin_amdgcn_readfirstlane(g));
+        const int lt = gd.width_lt >> 24, width = gd.width_lt & 0xffffff;
+        const int r = lane >> lt;
+        const int row = gd.row0 + r;
+        const long base = long(gd.base64) * kWave;
+        double d = 0.0;
+        for (int s = 0; s < width; ++s) {
+            const long idx = base + long(s / V) * kWave * V + lane * V + s % V;
+            if (S.col[idx] == row) d += double(widen<ST>(val[idx]));
+        }
+        d = row_reduce(d, lt);
+        if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
+            if (d == 0.0 || !isfinite(d)) atomicAdd(S.bad_diag, 1);
+            D[row] = ST(1.0 / d);
+        }
+    }
+}
+
+// ------------------------------------------------------------- products
+// Y[row or yperm[row], :] = (A X)[row, :] for k <= KM columns; one group per
+// wavefront, XCD-aware block order.  With KM = 1 and a float / bf16 value
+// array this is the low-precision product (float vectors and sums).
+template <typename VT, typename ST, int V, int KM, bool SCATTER>
+__global__ __launch_bounds__(kBlock) void k_spmm(
+    const Group *__restrict__ groups, int ngroups, const VT *__restrict__ val,
+    const int *__restrict__ col, const ST *__restrict__ X, long ldx,
+    ST *__restrict__ Y, long ldy, int k, const int *__restrict__ yperm)
+{
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = __builtin_amdgcn_readfirstlane(
+        b * kWavesPerBlock + int(threadIdx.x >> 6));
+    if (g >= ngroups) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const Group gd = load_group(groups, g);
+    ST a0[KM], a1[KM];
+#pragma unroll
+    for (int c = 0; c < KM; ++c) a0[c] = a1[c] = ST(0);
+    lane_sums<VT, ST, V, KM>(gd, lane, val, col, X, k, ldx, a0, a1);
+    const int lt = gd.width_lt >> 24, r = lane >> lt;
+    const bool owner = (lane & ((1 << lt) - 1)) == 0 && r < gd.nrows;
+    const int row = gd.row0 + r;
+    const long yr = SCATTER ? (owner ? long(yperm[row]) : 0) : long(row);
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+        if (KM > 1 && c >= k) continue;
+        const ST v = row_reduce(a0[c] + a1[c], lt);
+        if (owner) Y[yr * ldy + c] = v;
+    }
+}
+
+// ------------------------------------------------------------ dispatch
+template <int KM> struct KmTag { static constexpr int value = KM; };
+
+template <class F> void with_km(int km, F &&f)
+{
+    switch (km) {
+    case 1: f(KmTag<1>()); break;
+    case 2: f(KmTag<2>()); break;
+    case 4: f(KmTag<4>()); break;
+    case 8: f(KmTag<8>()); break;
+    default: f(KmTag<16>()); break;
+    }
+}
+
+template <typename VT, typename ST> struct TypeTag {
+    typedef VT V;
+    typedef ST S;
+};
+
+template <class F> void with_types(int vt, int st, F &&f)
+{
+    if (st == ST_F64) f(TypeTag<double, double>());
+    else if (vt == VT_F32) f(TypeTag<float, float>());
+    else f(TypeTag<uint16_t, float>());
+}
+
+}  // namespace
+
+int32_t engine_spmv_blocks(int32_t ngroups)
+{
+    int32_t b = (ngroups + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (b > kMaxSpmvBlocks) b = kMaxSpmvBlocks;
+    return b < 1 ? 1 : b;
+}
+
+int32_t engine_vec_blocks(int32_t n) { return vec_blocks(n); }
+
+hipError_t engine_iteration(const EngineLaunch &L, hipStream_t s)
+{
+    with_types(L.vt, L.st, [&](auto tt) {
+        typedef typename decltype(tt)::V VT;
+        typedef typename decltype(tt)::S ST;
+        with_km(L.km, [&](auto kt) {
+            constexpr int KM = decltype(kt)::value;
+            if (L.vec == 1)
+                hipLaunchKernelGGL((k_spmm_dot<VT, ST, 1, KM>), dim3(L.sblocks),
+                                   dim3(kBlock), 0, s, L.sys, L.smap);
+            else
+                hipLaunchKernelGGL((k_spmm_dot<VT, ST, 2, KM>), dim3(L.sblocks),
+                                   dim3(kBlock), 0, s, L.sys, L.smap);
+            hipLaunchKernelGGL(k_fin_dot, dim3(L.ncols), dim3(kBlock), 0, s,
+                               L.sys, L.cmap);
+            hipLaunchKernelGGL((k_update<ST, KM>), dim3(L.vblocks),
+                               dim3(kBlock), 0, s, L.sys, L.vmap);
+            hipLaunchKernelGGL(k_fin_update, dim3(L.ncols), dim3(kBlock), 0, s,
+                               L.sys, L.cmap);
+            hipLaunchKernelGGL((k_pupdate<ST, KM, false>), dim3(L.vblocks),
+                               dim3(kBlock), 0, s, L.sys, L.vmap);
+        });
+    });
+    return hipGetLastError();
+}
+
+template <typename VT, typename ST, int V, int KM, bool XZ>
+static void residual_mode(const EngineLaunch &L, int mode, hipStream_t s)
+{
+    const dim3 g(L.sblocks), b(kBlock), f(L.ncols);
+    if (mode == 0) {
+        hipLaunchKernelGGL((k_residual<VT, ST, V, KM, XZ, 0>), g, b, 0, s,
+                           L.sys, L.smap);
+        hipLaunchKernelGGL(k_fin_residual<0>, f, b, 0, s, L.sys, L.cmap);
+    } else if (mode == 1) {
+        hipLaunchKernelGGL((k_residual<VT, ST, V, KM, XZ, 1>), g, b, 0, s,
+                           L.sys, L.smap);
+        hipLaunchKernelGGL(k_fin_residual<1>, f, b, 0, s, L.sys, L.cmap);
+    } else {
+        hipLaunchKernelGGL((k_residual<VT, ST, V, KM, XZ, 2>), g, b, 0, s,
+                           L.sys, L.smap);
+        hipLaunchKernelGGL(k_fin_residual<2>, f, b, 0, s, L.sys, L.cmap);
+    }
+}
+
+hipError_t engine_residual(const EngineLaunch &L, int32_t mode, bool x_zero,
+                           hipStream_t s)
+{
+    with_types(L.vt, L.st, [&](auto tt) {
+        typedef typename decltype(tt)::V VT;
+        typedef typename decltype(tt)::S ST;
+        with_km(L.km, [&](auto kt) {
+            constexpr int KM = decltype(kt)::value;
+            if (L.vec == 1) {
+                if (x_zero) residual_mode<VT, ST, 1, KM, true>(L, mode, s);
+                else residual_mode<VT, ST, 1, KM, false>(L, mode, s);
+            } else {
+                if (x_zero) residual_mode<VT, ST, 2, KM, true>(L, mode, s);
+                else residual_mode<VT, ST, 2, KM, false>(L, mode, s);
+            }
+        });
+    });
+    return hipGetLastError();
+}
+
+hipError_t engine_pupdate_pending(const EngineLaunch &L, hipStream_t s)
+{
+    with_types(L.vt, L.st, [&](auto tt) {
+        typedef typename decltype(tt)::S ST;
+        with_km(L.km, [&](auto kt) {
+            constexpr int KM = decltype(kt)::value;
+            hipLaunchKernelGGL((k_pupdate<ST, KM, true>), dim3(L.vblocks),
+                               dim3(kBlock), 0, s, L.sys, L.vmap);
+        });
+    });
+    return hipGetLastError();
+}
+
+hipError_t engine_diag_inv(const EngineLaunch &L, hipStream_t s)
+{
+    with_types(L.vt, L.st, [&](auto tt) {
+        typedef typename decltype(tt)::V VT;
+        typedef typename decltype(tt)::S ST;
+        if (L.vec == 1)
+            hipLaunchKernelGGL((k_diag<VT, ST, 1>), dim3(L.sblocks),
+                               dim3(kBlock), 0, s, L.sys, L.smap);
+        else
+            hipLaunchKernelGGL((k_diag<VT, ST, 2>), dim3(L.sblocks),
+                               dim3(kBlock), 0, s, L.sys, L.smap);
+    });
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- auxiliary kernels
+namespace {
+
+// staging[b] = state of column cmap[b].y of system cmap[b].x
+__global__ void k_gather_states(const SysDesc *__restrict__ sys,
+                                const int2 *__restrict__ cmap, int ncols,
+                                ColState *__restrict__ staging)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= ncols) return;
+    const int2 sc = cmap[b];
+    staging[b] = sys[sc.x].cs[sc.y];
+}
+
+// Row permutation of an n x k block: TO_LAYOUT dst[i, :] = src[perm[i], :],
+// else dst[perm[i], :] = src[i, :].  ld of the caller side is ldc, of the
+// layout side k.
+template <bool TO_LAYOUT>
+__global__ __launch_bounds__(kBlock) void k_permute_rows(
+    int n, int k, const int *__restrict__ perm, const double *__restrict__ src,
+    long lds, double *__restrict__ dst, long ldd)
+{
+    const long total = long(n) * k;
+    for (long e = long(blockIdx.x) * kBlock + threadIdx.x; e < total;
+         e += long(gridDim.x) * kBlock) {
+        const int i = int(e / k), c = int(e % k);
+        const long pi = perm ? perm[i] : i;
+        if (TO_LAYOUT) dst[i * ldd + c] = src[pi * lds + c];
+        else dst[pi * ldd + c] = src[i * lds + c];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f32(long n,
+                                                   const double *__restrict__ a,
+                                                   float *__restrict__ b)
+{
+    for (long e = long(blockIdx.x) * kBlock + threadIdx.x; e < n;
+         e += long(gridDim.x) * kBlock)
+        b[e] = float(a[e]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_add_f32(long n,
+                                                    const float *__restrict__ d,
+                                                    double *__restrict__ x)
+{
+    for (long e = long(blockIdx.x) * kBlock + threadIdx.x; e < n;
+         e += long(gridDim.x) * kBlock)
+        x[e] += double(d[e]);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return uint16_t((u >> 16) | 0x0040u);        // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                   // nearest, ties even
+    return uint16_t(u >> 16);
+}
+
+// Low-precision copies of the slot values (padding stays 0).
+__global__ __launch_bounds__(kBlock) void k_cast_slots(
+    long n, const double *__restrict__ v, float *__restrict__ f32,
+    uint16_t *__restrict__ bf16)
+{
+    for (long e = long(blockIdx.x) * kBlock + threadIdx.x; e < n;
+         e += long(gridDim.x) * kBlock) {
+        const float f = float(v[e]);
+        if (f32) f32[e] = f;
+        if (bf16) bf16[e] = f32_to_bf16_bits(f);
+    }
+}
+
+int flat_blocks(long n)
+{
+    long b = (n + kBlock - 1) / kBlock;
+    if (b > 8192) b = 8192;
+    return b < 1 ? 1 : int(b);
+}
+
+}  // namespace
+
+hipError_t engine_gather_states(const EngineLaunch &L, ColState *staging,
+                                hipStream_t s)
+{
+    if (L.ncols == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_states, dim3((L.ncols + 63) / 64), dim3(64), 0,
+                       s, L.sys, L.cmap, L.ncols, staging);
+    return hipGetLastError();
+}
+
+hipError_t permute_rows(int32_t n, int32_t k, const int32_t *perm,
+                        const double *src, int64_t lds, double *dst,
+                        int64_t ldd, bool to_layout, hipStream_t s)
+{
+    const long total = long(n) * k;
+    if (total == 0) return hipSuccess;
+    if (to_layout)
+        hipLaunchKernelGGL(k_permute_rows<true>, dim3(flat_blocks(total)),
+                           dim3(kBlock), 0, s, n, k, perm, src, long(lds), dst,
+                           long(ldd));
+    else
+        hipLaunchKernelGGL(k_permute_rows<false>, dim3(flat_blocks(total)),
+                           dim3(kBlock), 0, s, n, k, perm, src, long(lds), dst,
+                           long(ldd));
+    return hipGetLastError();
+}
+
+hipError_t to_f32(int64_t n, const double *a, float *b, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32, dim3(flat_blocks(n)), dim3(kBlock), 0, s,
+                       long(n), a, b);
+    return hipGetLastError();
+}
+
+hipError_t add_f32(int64_t n, const float *d, double *x, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_f32, dim3(flat_blocks(n)), dim3(kBlock), 0, s,
+                       long(n), d, x);
+    return hipGetLastError();
+}
+
+hipError_t cast_slots(int64_t n, const double *v, float *f32, uint16_t *bf16,
+                      hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast_slots, dim3(flat_blocks(n)), dim3(kBlock), 0, s,
+                       long(n), v, f32, bf16);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_spmm_f64(const fs_csr *A, int32_t k, const double *X,
+                           int64_t ldx, double *Y, int64_t ldy,
+                           const int32_t *yperm, hipStream_t s)
+{
+    if (A->n_groups == 0) return hipSuccess;
+    const dim3 grid((A->n_groups + kWavesPerBlock - 1) / kWavesPerBlock);
+    const int km = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+    with_km(km, [&](auto kt) {
+        constexpr int KM = decltype(kt)::value;
+        auto go = [&](auto vtag, auto stag) {
+            constexpr int V = decltype(vtag)::value;
+            constexpr bool SC = decltype(stag)::value;
+            hipLaunchKernelGGL((k_spmm<double, double, V, KM, SC>), grid,
+                               dim3(kBlock), 0, s, A->d_groups, A->n_groups,
+                               A->d_val, A->d_col, X, long(ldx), Y, long(ldy),
+                               k, yperm);
+        };
+        if (A->host.vec == 1) {
+            if (yperm) go(KmTag<1>(), std::true_type());
+            else go(KmTag<1>(), std::false_type());
+        } else {
+            if (yperm) go(KmTag<2>(), std::true_type());
+            else go(KmTag<2>(), std::false_type());
+        }
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_lowp(const fs_csr *A, int32_t dtype, const float *x,
+                            float *y, hipStream_t s)
+{
+    if (A->n_groups == 0) return hipSuccess;
+    const dim3 grid((A->n_groups + kWavesPerBlock - 1) / kWavesPerBlock);
+    auto go = [&](auto vt, auto vtag) {
+        typedef typename decltype(vt)::V VT;
+        constexpr int V = decltype(vtag)::value;
+        const VT *val = dtype == FS_DT_F32
+                            ? reinterpret_cast<const VT *>(A->d_val_f32)
+                            : reinterpret_cast<const VT *>(A->d_val_bf16);
+        hipLaunchKernelGGL((k_spmm<VT, float, V, 1, false>), grid,
+                           dim3(kBlock), 0, s, A->d_groups, A->n_groups, val,
+                           A->d_col, x, 1L, y, 1L, 1, nullptr);
+    };
+    if (dtype == FS_DT_F32) {
+        if (A->host.vec == 1) go(TypeTag<float, float>(), KmTag<1>());
+        else go(TypeTag<float, float>(), KmTag<2>());
+    } else {
+        if (A->host.vec == 1) go(TypeTag<uint16_t, float>(), KmTag<1>());
+        else go(TypeTag<uint16_t, float>(), KmTag<2>());
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fs

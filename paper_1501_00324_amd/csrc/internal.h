@@ -67,34 +67,118 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
                        const int32_t *rowptr, const int32_t *col,
                        const fs_csr_opts &o, HostLayout &L);
 
-// ------------------------------------------------------------ CG scalars
-struct CgScalars {
-    double rho, gamma, alpha, beta;
-    double rr;          // |r|^2 of the recurrence residual
-    double rr_true;     // |b - A x|^2 from the last true-residual check
-    double bnorm2, tol2;
-    int32_t iter, done, status, maxit;
-    uint32_t counter;   // last-block-done ticket, reset by the last block
-    int32_t replacements;
-    int32_t pad[2];
-};
+// ------------------------------------------------- batched CG engine state
+// Status of one right-hand side.
 enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_RECURRENCE_MET = 2,
        CG_BREAKDOWN = 3, CG_MAXIT = 4 };
 
-// Per-handle Krylov workspace (layout numbering), allocated on first solve.
-struct CgWork {
-    int32_t n = 0;
-    double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr,
-           *b = nullptr, *dinv = nullptr, *partials = nullptr;
-    CgScalars *sc = nullptr;       // device
-    CgScalars *sc_host = nullptr;  // pinned host mirror
-    int32_t nparts = 0;
-    hipStream_t stream = nullptr;  // solves run here, ordered after the
-                                   // caller's stream by an event
-    hipEvent_t done_ev = nullptr;
-    hipGraphExec_t graph = nullptr;
-    int32_t graph_k = 0, graph_pc = -1;
+struct ColState {                // one right-hand side, device resident
+    double rho, gamma, alpha, beta;
+    double rr;                   // |r|^2 of the recurrence residual
+    double rr_true;              // |b - A x|^2 at the last true check
+    double bnorm2, tol2;
+    int32_t iter, status, pending, maxit;
+    int32_t replacements, pad[3];
 };
+
+// One linear system of a batched launch, in layout numbering.  Vectors are
+// n x k, row-major (leading dimension k), of the launch's vector type.
+struct SysDesc {
+    const Group *groups;
+    const void *val;             // slot values: double, float or bf16 bits
+    const int32_t *col;
+    int32_t n, ngroups, k, maxit;
+    int32_t sb0, snb;            // blocks in the group-shaped grid
+    int32_t vb0, vnb;            // blocks in the row-shaped grid
+    void *x, *r, *p, *q;
+    const void *b, *dinv;        // dinv NULL: no preconditioner
+    ColState *cs;                // k entries
+    int32_t *bad_diag;           // rows with a zero / non-finite diagonal
+    double *partials;            // 3 * k * max(snb, vnb) entries
+    double rtol;
+};
+
+// Value / vector type classes of a launch.
+enum { VT_F64 = 0, VT_F32 = 1, VT_BF16 = 2 };
+enum { ST_F64 = 0, ST_F32 = 1 };
+
+struct EngineLaunch {            // one batched launch shape
+    int32_t vt, st, vec, km;     // value type, vector type, slots/load, max k
+    const SysDesc *sys;          // device array of systems
+    const int32_t *smap;         // group-shaped grid block -> system
+    const int32_t *vmap;         // row-shaped grid block -> system
+    const int2 *cmap;            // finalize block -> (system, column)
+    int32_t sblocks, vblocks, ncols;  // grid sizes
+};
+
+int32_t engine_spmv_blocks(int32_t ngroups);
+int32_t engine_vec_blocks(int32_t n);
+// One CG iteration for every running right-hand side of every system:
+// Q = A P with p.q, then x/r update with r.z and r.r, then the p update.
+hipError_t engine_iteration(const EngineLaunch &L, hipStream_t s);
+// mode 0 (start: r = b - A x, p = z, sets the per-column state), 1 (true
+// residual check with replacement), 2 (measure |b - A x| only).
+hipError_t engine_residual(const EngineLaunch &L, int32_t mode,
+                           bool x_zero, hipStream_t s);
+// p = z + beta p for the columns whose residual was just replaced.
+hipError_t engine_pupdate_pending(const EngineLaunch &L, hipStream_t s);
+// dinv = 1 / diag(A) (vector type of the launch); counts bad diagonals.
+hipError_t engine_diag_inv(const EngineLaunch &L, hipStream_t s);
+// staging[i] = the ColState of finalize column i (cmap order).
+hipError_t engine_gather_states(const EngineLaunch &L, ColState *staging,
+                                hipStream_t s);
+// n x k row blocks between caller (stride ld*) and layout order; perm NULL
+// is the identity.
+hipError_t permute_rows(int32_t n, int32_t k, const int32_t *perm,
+                        const double *src, int64_t lds, double *dst,
+                        int64_t ldd, bool to_layout, hipStream_t s);
+hipError_t to_f32(int64_t n, const double *a, float *b, hipStream_t s);
+hipError_t add_f32(int64_t n, const float *d, double *x, hipStream_t s);
+hipError_t cast_slots(int64_t n, const double *v, float *f32, uint16_t *bf16,
+                      hipStream_t s);
+
+// ------------------------------------------------------------ host engine
+// Device state of one system (matrix + k right-hand sides) in one vector
+// precision, in layout numbering.
+struct CgSys {
+    struct ::fs_csr *A = nullptr;
+    int32_t k = 0, vt = VT_F64, st = ST_F64, precond = 1;
+    int32_t n = 0, snb = 0, vnb = 0;
+    void *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr,
+         *b = nullptr, *dinv = nullptr;
+    ColState *cs = nullptr;
+    int32_t *bad = nullptr;
+    double *partials = nullptr;
+    double rtol = 1e-8;
+    int32_t maxit = 20000;
+    int64_t bytes = 0;
+};
+
+// A set of systems launched together (same value/vector types and slot
+// vector width).  Device copies of the descriptors and block maps.
+struct Batch {
+    std::vector<CgSys *> members;
+    int32_t vt = VT_F64, st = ST_F64, vec = 2, km = 1;
+    SysDesc *d_sys = nullptr;
+    int32_t *d_smap = nullptr, *d_vmap = nullptr;
+    int2 *d_cmap = nullptr;
+    ColState *d_stage = nullptr, *h_stage = nullptr;
+    int32_t cap_sys = 0, cap_s = 0, cap_v = 0, cap_c = 0;
+    EngineLaunch L{};
+    hipGraphExec_t graph = nullptr;
+    int32_t graph_iters = 0;
+    std::vector<int2> cols;           // (member, column) per finalize block
+};
+
+fs_status sys_alloc(CgSys &S, struct ::fs_csr *A, int32_t k, int32_t vt,
+                    int32_t st, int32_t precond);
+void sys_free(CgSys &S);
+fs_status batch_build(Batch &B, hipStream_t s);   // upload descs and maps
+void batch_free(Batch &B);
+fs_status batch_iterations(Batch &B, int32_t iters, bool use_graph,
+                           hipStream_t s);
+fs_status batch_read_states(Batch &B, hipStream_t s);  // -> h_stage
+void free_solver_state(struct ::fs_csr *A);
 
 }  // namespace fs
 
@@ -114,10 +198,17 @@ struct fs_csr {
     int32_t *d_perm = nullptr;
     int32_t *d_iperm = nullptr;
     double *d_xtmp = nullptr;      // gathered x for caller-numbering spmv
+    double *d_Xtmp = nullptr;      // gathered X for caller-numbering spmm
+    int64_t xtmp_cap = 0;
     int32_t dtypes = FS_DT_F64;
     double t_build_ms = 0.0;
     int64_t device_bytes = 0;
-    fs::CgWork cg;
+    // solver state, created on the first solve and kept for reuse
+    hipStream_t stream = nullptr;  // solves run here, ordered after the
+    hipEvent_t ev = nullptr;       // caller's stream by an event
+    fs::CgSys *sys_f64 = nullptr;  // one right-hand side, FP64
+    fs::CgSys *sys_lo = nullptr;   // inner system of mixed precision
+    fs::Batch *batch_f64 = nullptr, *batch_lo = nullptr;
 };
 
 namespace fs {
@@ -133,20 +224,12 @@ hipError_t launch_scatter(int32_t n, const int32_t *perm, const double *in,
 // y[row or yperm[row]] = (A x)[row] over all groups.
 hipError_t launch_spmv_f64(const fs_csr *A, const double *x, double *y,
                            const int32_t *yperm, hipStream_t s);
-
-// CG (layout numbering)
-int32_t cg_partials_needed(const fs_csr *A);
-hipError_t launch_cg_spmv_dot(const fs_csr *A, CgWork &w, hipStream_t s);
-hipError_t launch_cg_update(CgWork &w, int32_t precond, hipStream_t s);
-hipError_t launch_cg_pupdate(CgWork &w, int32_t precond, hipStream_t s);
-// r = b - A x, with partial sums for |r|^2 and r.z; mode 0: initial residual
-// (sets rho, rr, bnorm2, tol2 and p = z); mode 1: convergence check with
-// residual replacement; mode 2: measurement only (rr_true).
-hipError_t launch_cg_residual(const fs_csr *A, CgWork &w, int32_t precond,
-                              int32_t mode, double rtol, int32_t maxit,
-                              int32_t x_is_zero, hipStream_t s);
-// dinv = 1 / diag(A) in layout numbering; rows with a zero or non-finite
-// diagonal are counted in sc->pad[0].
-hipError_t launch_diag_inv(const fs_csr *A, double *dinv, CgScalars *sc,
-                           hipStream_t s);
+// Y[row or yperm[row], :] = (A X)[row, :] for k <= 16 columns.
+hipError_t launch_spmm_f64(const fs_csr *A, int32_t k, const double *X,
+                           int64_t ldx, double *Y, int64_t ldy,
+                           const int32_t *yperm, hipStream_t s);
+// Low-precision product in layout numbering: y = A_lo x (float vectors,
+// float accumulation), A_lo the FP32 or BF16 copy.
+hipError_t launch_spmv_lowp(const fs_csr *A, int32_t dtype, const float *x,
+                            float *y, hipStream_t s);
 }  // namespace fs

@@ -189,7 +189,7 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
 
     const bool square = n_rows == n_cols;
     int32_t sort_window = o.sort_window > 0 ? o.sort_window : 256;
-    int32_t threshold = o.threshold > 0 ? o.threshold : 16;
+    int32_t threshold = o.threshold > 0 ? o.threshold : 48;
     int32_t tmin = o.lanes_min > 0 ? o.lanes_min : 1;
     int32_t tmax = o.lanes_max > 0 ? o.lanes_max : 64;
     if (!is_pow2(tmin) || !is_pow2(tmax) || tmin > tmax || tmax > kWave)
@@ -288,8 +288,8 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
     }
     // two slots per load halves the load instructions; one slot per load
     // avoids rounding each lane's slot count up to even.  Auto keeps the
-    // wide loads unless they cost more than 3% extra padded slots.
-    L.vec = o.vec ? o.vec : (double(slots2) <= 1.03 * double(slots1) ? 2 : 1);
+    // wide loads unless they cost more than 6% extra padded slots.
+    L.vec = o.vec ? o.vec : (double(slots2) <= 1.06 * double(slots1) ? 2 : 1);
     const int32_t V = L.vec;
     L.groups.clear();
     std::fill(std::begin(L.groups_by_lanes), std::end(L.groups_by_lanes), 0);

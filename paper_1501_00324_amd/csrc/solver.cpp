@@ -1,0 +1,649 @@
+// Host side of the CG engine: device state per system, batches of systems
+// launched together, the solve loop (chunks of iterations replayed as HIP
+// graphs, one small device-to-host read of the column states per chunk,
+// true-residual confirmation with residual replacement), mixed-precision
+// iterative refinement, and the cg_solve* entry points.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace fs {
+namespace {
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(
+               steady_clock::now().time_since_epoch()).count();
+}
+
+int32_t km_for(int32_t k)
+{
+    return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+}
+
+size_t st_size(int32_t st) { return st == ST_F64 ? 8 : 4; }
+
+fs_status dmalloc(void **p, size_t bytes, int64_t &acct)
+{
+    *p = nullptr;
+    if (!bytes) return FS_OK;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_error(e == hipErrorOutOfMemory ? FS_E_OOM : FS_E_HIP,
+                         "hipMalloc(%zu bytes): %s", bytes,
+                         hipGetErrorString(e));
+    }
+    acct += int64_t(bytes);
+    return FS_OK;
+}
+
+template <class T> void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+const void *values_of(const fs_csr *A, int32_t vt)
+{
+    return vt == VT_F64 ? static_cast<const void *>(A->d_val)
+         : vt == VT_F32 ? static_cast<const void *>(A->d_val_f32)
+                        : static_cast<const void *>(A->d_val_bf16);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- systems
+void sys_free(CgSys &S)
+{
+    dfree(S.x); dfree(S.r); dfree(S.p); dfree(S.q); dfree(S.b);
+    dfree(S.dinv); dfree(S.cs); dfree(S.bad); dfree(S.partials);
+    S.bytes = 0;
+    S.k = 0;
+}
+
+fs_status sys_alloc(CgSys &S, fs_csr *A, int32_t k, int32_t vt, int32_t st,
+                    int32_t precond)
+{
+    sys_free(S);
+    S.A = A;
+    S.k = k;
+    S.vt = vt;
+    S.st = st;
+    S.precond = precond;
+    S.n = A->n_rows;
+    S.snb = engine_spmv_blocks(A->n_groups);
+    S.vnb = engine_vec_blocks(S.n);
+    const size_t nk = size_t(S.n) * size_t(k) * st_size(st);
+    fs_status r = FS_OK;
+    if ((r = dmalloc(&S.x, nk, S.bytes)) || (r = dmalloc(&S.r, nk, S.bytes)) ||
+        (r = dmalloc(&S.p, nk, S.bytes)) || (r = dmalloc(&S.q, nk, S.bytes)) ||
+        (r = dmalloc(&S.b, nk, S.bytes)) ||
+        (precond &&
+         (r = dmalloc(&S.dinv, size_t(S.n) * st_size(st), S.bytes))) ||
+        (r = dmalloc(reinterpret_cast<void **>(&S.cs),
+                     sizeof(ColState) * size_t(k), S.bytes)) ||
+        (r = dmalloc(reinterpret_cast<void **>(&S.bad), sizeof(int32_t),
+                     S.bytes)) ||
+        (r = dmalloc(reinterpret_cast<void **>(&S.partials),
+                     sizeof(double) * 3 * size_t(k) *
+                         size_t(std::max(S.snb, S.vnb)),
+                     S.bytes))) {
+        sys_free(S);
+        return r;
+    }
+    return FS_OK;
+}
+
+// --------------------------------------------------------------- batches
+void batch_free(Batch &B)
+{
+    if (B.graph) (void)hipGraphExecDestroy(B.graph);
+    B.graph = nullptr;
+    dfree(B.d_sys); dfree(B.d_smap); dfree(B.d_vmap); dfree(B.d_cmap);
+    dfree(B.d_stage);
+    if (B.h_stage) (void)hipHostFree(B.h_stage);
+    B.h_stage = nullptr;
+    B.cap_sys = B.cap_s = B.cap_v = B.cap_c = 0;
+}
+
+namespace {
+template <class T>
+fs_status ensure_cap(T *&p, int32_t &cap, int32_t want)
+{
+    if (want <= cap) return FS_OK;
+    dfree(p);
+    int64_t dummy = 0;
+    int32_t c = std::max(want, 2 * cap);
+    FS_TRY(dmalloc(reinterpret_cast<void **>(&p), sizeof(T) * size_t(c),
+                   dummy));
+    cap = c;
+    return FS_OK;
+}
+}  // namespace
+
+fs_status batch_build(Batch &B, hipStream_t s)
+{
+    const int32_t m = int32_t(B.members.size());
+    std::vector<SysDesc> descs(static_cast<size_t>(m));
+    std::vector<int32_t> smap, vmap;
+    B.cols.clear();
+    int32_t kmax = 1, sb = 0, vb = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        CgSys &S = *B.members[size_t(i)];
+        const fs_csr *A = S.A;
+        SysDesc &d = descs[size_t(i)];
+        std::memset(&d, 0, sizeof d);
+        d.groups = A->d_groups;
+        d.val = values_of(A, S.vt);
+        d.col = A->d_col;
+        d.n = S.n;
+        d.ngroups = A->n_groups;
+        d.k = S.k;
+        d.maxit = S.maxit;
+        d.sb0 = sb;
+        d.snb = S.snb;
+        d.vb0 = vb;
+        d.vnb = S.vnb;
+        d.x = S.x; d.r = S.r; d.p = S.p; d.q = S.q;
+        d.b = S.b;
+        d.dinv = S.precond ? S.dinv : nullptr;
+        d.cs = S.cs;
+        d.bad_diag = S.bad;
+        d.partials = S.partials;
+        d.rtol = S.rtol;
+        smap.insert(smap.end(), size_t(S.snb), i);
+        vmap.insert(vmap.end(), size_t(S.vnb), i);
+        for (int32_t c = 0; c < S.k; ++c) B.cols.push_back(int2{i, c});
+        sb += S.snb;
+        vb += S.vnb;
+        kmax = std::max(kmax, S.k);
+    }
+    const int32_t nc = int32_t(B.cols.size());
+    FS_TRY(ensure_cap(B.d_sys, B.cap_sys, m));
+    FS_TRY(ensure_cap(B.d_smap, B.cap_s, sb));
+    FS_TRY(ensure_cap(B.d_vmap, B.cap_v, vb));
+    if (nc > B.cap_c) {
+        const int32_t cap = std::max(nc, 2 * B.cap_c);
+        int64_t dummy = 0;
+        dfree(B.d_cmap);
+        dfree(B.d_stage);
+        if (B.h_stage) (void)hipHostFree(B.h_stage);
+        B.h_stage = nullptr;
+        B.cap_c = 0;
+        FS_TRY(dmalloc(reinterpret_cast<void **>(&B.d_cmap),
+                       sizeof(int2) * size_t(cap), dummy));
+        FS_TRY(dmalloc(reinterpret_cast<void **>(&B.d_stage),
+                       sizeof(ColState) * size_t(cap), dummy));
+        FS_HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&B.h_stage),
+                                 sizeof(ColState) * size_t(cap),
+                                 hipHostMallocDefault));
+        B.cap_c = cap;
+    }
+    // blocking copies: the host vectors are temporaries
+    FS_HIP_TRY(hipStreamSynchronize(s));
+    if (m) FS_HIP_TRY(hipMemcpy(B.d_sys, descs.data(), sizeof(SysDesc) * m,
+                                hipMemcpyHostToDevice));
+    if (sb) FS_HIP_TRY(hipMemcpy(B.d_smap, smap.data(), sizeof(int32_t) * sb,
+                                 hipMemcpyHostToDevice));
+    if (vb) FS_HIP_TRY(hipMemcpy(B.d_vmap, vmap.data(), sizeof(int32_t) * vb,
+                                 hipMemcpyHostToDevice));
+    if (nc) FS_HIP_TRY(hipMemcpy(B.d_cmap, B.cols.data(), sizeof(int2) * nc,
+                                 hipMemcpyHostToDevice));
+    B.km = km_for(kmax);
+    B.L.vt = B.vt;
+    B.L.st = B.st;
+    B.L.vec = B.vec;
+    B.L.km = B.km;
+    B.L.sys = B.d_sys;
+    B.L.smap = B.d_smap;
+    B.L.vmap = B.d_vmap;
+    B.L.cmap = B.d_cmap;
+    B.L.sblocks = sb;
+    B.L.vblocks = vb;
+    B.L.ncols = nc;
+    if (B.graph) (void)hipGraphExecDestroy(B.graph);
+    B.graph = nullptr;
+    B.graph_iters = 0;
+    return FS_OK;
+}
+
+fs_status batch_iterations(Batch &B, int32_t iters, bool use_graph,
+                           hipStream_t s)
+{
+    if (B.L.ncols == 0) return FS_OK;
+    if (!use_graph || !s) {
+        for (int32_t i = 0; i < iters; ++i)
+            FS_HIP_TRY(engine_iteration(B.L, s));
+        return FS_OK;
+    }
+    if (!B.graph || B.graph_iters != iters) {
+        if (B.graph) (void)hipGraphExecDestroy(B.graph);
+        B.graph = nullptr;
+        hipGraph_t g = nullptr;
+        FS_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int32_t i = 0; i < iters && e == hipSuccess; ++i)
+            e = engine_iteration(B.L, s);
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return set_error(FS_E_HIP, "graph capture: %s",
+                             hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            B.graph = nullptr;
+            return set_error(FS_E_HIP, "graph instantiate: %s",
+                             hipGetErrorString(e));
+        }
+        B.graph_iters = iters;
+    }
+    FS_HIP_TRY(hipGraphLaunch(B.graph, s));
+    return FS_OK;
+}
+
+fs_status batch_read_states(Batch &B, hipStream_t s)
+{
+    if (B.L.ncols == 0) return FS_OK;
+    FS_HIP_TRY(engine_gather_states(B.L, B.d_stage, s));
+    FS_HIP_TRY(hipMemcpyAsync(B.h_stage, B.d_stage,
+                              sizeof(ColState) * size_t(B.L.ncols),
+                              hipMemcpyDeviceToHost, s));
+    FS_HIP_TRY(hipStreamSynchronize(s));
+    return FS_OK;
+}
+
+namespace {
+
+bool any_status(const Batch &B, int32_t st)
+{
+    for (int32_t i = 0; i < B.L.ncols; ++i)
+        if (B.h_stage[i].status == st) return true;
+    return false;
+}
+
+// Run every member of B from its current x to convergence (or failure).
+// Members' b and x are set, rtol / maxit / precond are in the members.
+fs_status run_batch(Batch &B, int32_t check_every, bool use_graph,
+                    bool x_zero, hipStream_t s)
+{
+    FS_TRY(batch_build(B, s));
+    bool pc = false;
+    for (CgSys *S : B.members) pc |= S->precond != 0;
+    if (pc) {
+        for (CgSys *S : B.members)
+            FS_HIP_TRY(hipMemsetAsync(S->bad, 0, sizeof(int32_t), s));
+        FS_HIP_TRY(engine_diag_inv(B.L, s));
+        for (CgSys *S : B.members) {
+            if (!S->precond) continue;
+            int32_t bad = 0;
+            FS_HIP_TRY(hipMemcpyAsync(&bad, S->bad, sizeof bad,
+                                      hipMemcpyDeviceToHost, s));
+            FS_HIP_TRY(hipStreamSynchronize(s));
+            if (bad)
+                return set_error(FS_E_ARG,
+                                 "Jacobi preconditioner: %d rows with a zero "
+                                 "or non-finite diagonal", bad);
+        }
+    }
+    FS_HIP_TRY(engine_residual(B.L, 0, x_zero, s));
+    FS_TRY(batch_read_states(B, s));
+    while (any_status(B, CG_RUNNING)) {
+        FS_TRY(batch_iterations(B, check_every, use_graph, s));
+        FS_TRY(batch_read_states(B, s));
+        if (any_status(B, CG_RECURRENCE_MET)) {
+            FS_HIP_TRY(engine_residual(B.L, 1, false, s));
+            FS_TRY(batch_read_states(B, s));
+            bool pending = false;
+            for (int32_t i = 0; i < B.L.ncols; ++i)
+                pending |= B.h_stage[i].pending != 0;
+            if (pending) FS_HIP_TRY(engine_pupdate_pending(B.L, s));
+        }
+    }
+    bool all_conv = true;
+    for (int32_t i = 0; i < B.L.ncols; ++i)
+        all_conv &= B.h_stage[i].status == CG_CONVERGED;
+    if (!all_conv) {
+        FS_HIP_TRY(engine_residual(B.L, 2, false, s));
+        FS_TRY(batch_read_states(B, s));
+    }
+    return FS_OK;
+}
+
+fs_status status_of(const ColState &c)
+{
+    switch (c.status) {
+    case CG_CONVERGED: return FS_OK;
+    case CG_MAXIT: return FS_E_NOT_CONVERGED;
+    default: return FS_E_BREAKDOWN;
+    }
+}
+
+void fill_info(const ColState &c, fs_cg_info &info)
+{
+    info.status = status_of(c);
+    info.iters = c.iter;
+    info.replacements = c.replacements;
+    info.relres = c.bnorm2 > 0.0 ? std::sqrt(c.rr_true / c.bnorm2) : 0.0;
+}
+
+// worst status over columns, for the return code
+fs_status worst(fs_status a, fs_status b)
+{
+    auto rank = [](fs_status v) {
+        return v == FS_OK ? 0 : v == FS_E_NOT_CONVERGED ? 1 : 2;
+    };
+    return rank(b) > rank(a) ? b : a;
+}
+
+fs_status normalise_opts(const fs_cg_opts *in, fs_cg_opts &o)
+{
+    cg_opts_default(&o);
+    if (in) o = *in;
+    if (o.rtol <= 0.0) o.rtol = 1e-8;
+    if (o.maxit <= 0) o.maxit = 20000;
+    if (o.check_every <= 0) o.check_every = 32;
+    if (o.inner_rtol <= 0.0) o.inner_rtol = 1e-2;
+    if (o.max_outer <= 0) o.max_outer = 50;
+    if (o.precond != FS_PC_NONE && o.precond != FS_PC_JACOBI)
+        return set_error(FS_E_ARG, "unknown preconditioner %d", o.precond);
+    if (o.precision < FS_PREC_F64 || o.precision > FS_PREC_IR_BF16)
+        return set_error(FS_E_ARG, "unknown precision %d", o.precision);
+    return FS_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1, want;
+    explicit DeviceGuard(int d) : want(d)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != want)
+            (void)hipSetDevice(want);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
+    }
+};
+
+fs_status ensure_stream(fs_csr *A)
+{
+    if (!A->stream)
+        FS_HIP_TRY(hipStreamCreateWithFlags(&A->stream, hipStreamNonBlocking));
+    if (!A->ev)
+        FS_HIP_TRY(hipEventCreateWithFlags(&A->ev, hipEventDisableTiming));
+    return FS_OK;
+}
+
+fs_status ensure_sys(CgSys *&S, fs_csr *A, int32_t k, int32_t vt, int32_t st,
+                     int32_t pc)
+{
+    if (!S) S = new CgSys();
+    if (S->k != k || S->vt != vt || S->st != st || (pc && !S->dinv) ||
+        S->n != A->n_rows)
+        FS_TRY(sys_alloc(*S, A, k, vt, st, pc));
+    S->precond = pc;
+    return FS_OK;
+}
+
+// caller block (n x k, row stride ld) -> layout block of S (ld = k)
+fs_status load_block(const fs_csr *A, int32_t k, const double *src,
+                     int64_t ld, void *dst, hipStream_t s)
+{
+    return permute_rows(A->n_rows, k, A->host.identity ? nullptr : A->d_perm,
+                        src, ld, static_cast<double *>(dst), k, true, s) ==
+                   hipSuccess
+               ? FS_OK
+               : set_error(FS_E_HIP, "permute_rows: %s",
+                           hipGetErrorString(hipGetLastError()));
+}
+
+fs_status store_block(const fs_csr *A, int32_t k, const void *src,
+                      double *dst, int64_t ld, hipStream_t s)
+{
+    return permute_rows(A->n_rows, k, A->host.identity ? nullptr : A->d_perm,
+                        static_cast<const double *>(src), k, dst, ld, false,
+                        s) == hipSuccess
+               ? FS_OK
+               : set_error(FS_E_HIP, "permute_rows: %s",
+                           hipGetErrorString(hipGetLastError()));
+}
+
+// FP64 CG on one handle with k right-hand sides (caller blocks B, X).
+fs_status solve_f64(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
+                    double *Xc, int64_t ldx, const fs_cg_opts &o,
+                    fs_cg_info *infos, hipStream_t caller)
+{
+    FS_TRY(ensure_stream(A));
+    hipStream_t s = A->stream;
+    FS_HIP_TRY(hipEventRecord(A->ev, caller));
+    FS_HIP_TRY(hipStreamWaitEvent(s, A->ev, 0));
+    FS_TRY(ensure_sys(A->sys_f64, A, k, VT_F64, ST_F64, o.precond));
+    CgSys &S = *A->sys_f64;
+    S.rtol = o.rtol;
+    S.maxit = o.maxit;
+    FS_TRY(load_block(A, k, Bc, ldb, S.b, s));
+    if (o.x0_zero)
+        FS_HIP_TRY(hipMemsetAsync(S.x, 0, sizeof(double) * size_t(S.n) * k, s));
+    else
+        FS_TRY(load_block(A, k, Xc, ldx, S.x, s));
+    if (!A->batch_f64) A->batch_f64 = new Batch();
+    Batch &B = *A->batch_f64;
+    B.members.assign(1, &S);
+    B.vt = VT_F64;
+    B.st = ST_F64;
+    B.vec = A->host.vec;
+    FS_TRY(run_batch(B, o.check_every, o.use_graph != 0, o.x0_zero != 0, s));
+    // a column with b = 0 returns x = 0
+    for (int32_t c = 0; c < k; ++c)
+        if (B.h_stage[c].bnorm2 == 0.0)
+            FS_HIP_TRY(hipMemset2DAsync(static_cast<double *>(S.x) + c,
+                                        sizeof(double) * size_t(k), 0,
+                                        sizeof(double), size_t(S.n), s));
+    FS_TRY(store_block(A, k, S.x, Xc, ldx, s));
+    FS_HIP_TRY(hipStreamSynchronize(s));
+    fs_status ret = FS_OK;
+    const double it_bytes = 12.0 * double(A->nnz) +
+                            (o.precond ? 104.0 : 88.0) * double(A->n_rows) * k;
+    for (int32_t c = 0; c < k; ++c) {
+        fill_info(B.h_stage[c], infos[c]);
+        infos[c].outer = 0;
+        infos[c].bytes = double(B.h_stage[c].iter) * it_bytes / k +
+                         2.0 * (12.0 * double(A->nnz) + 16.0 * A->n_rows);
+        ret = worst(ret, infos[c].status);
+    }
+    return ret;
+}
+
+// Mixed-precision iterative refinement: FP64 residual and update, inner CG
+// on the FP32 / BF16 copy of A with float vectors.
+fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
+                   double *Xc, int64_t ldx, const fs_cg_opts &o,
+                   fs_cg_info *infos, hipStream_t caller)
+{
+    const int32_t dt = o.precision == FS_PREC_IR_F32 ? FS_DT_F32 : FS_DT_BF16;
+    const int32_t vt = dt == FS_DT_F32 ? VT_F32 : VT_BF16;
+    if (!(A->dtypes & dt)) FS_TRY(csr_add_dtype(A, dt, caller));
+    FS_TRY(ensure_stream(A));
+    hipStream_t s = A->stream;
+    FS_HIP_TRY(hipEventRecord(A->ev, caller));
+    FS_HIP_TRY(hipStreamWaitEvent(s, A->ev, 0));
+    FS_TRY(ensure_sys(A->sys_f64, A, k, VT_F64, ST_F64, o.precond));
+    FS_TRY(ensure_sys(A->sys_lo, A, k, vt, ST_F32, o.precond));
+    CgSys &Out = *A->sys_f64, &In = *A->sys_lo;
+    Out.rtol = o.rtol;
+    Out.maxit = o.maxit;
+    In.rtol = o.inner_rtol;
+    FS_TRY(load_block(A, k, Bc, ldb, Out.b, s));
+    if (o.x0_zero)
+        FS_HIP_TRY(hipMemsetAsync(Out.x, 0, sizeof(double) * size_t(Out.n) * k,
+                                  s));
+    else
+        FS_TRY(load_block(A, k, Xc, ldx, Out.x, s));
+    if (!A->batch_f64) A->batch_f64 = new Batch();
+    if (!A->batch_lo) A->batch_lo = new Batch();
+    Batch &BO = *A->batch_f64, &BI = *A->batch_lo;
+    BO.members.assign(1, &Out);
+    BO.vt = VT_F64;
+    BO.st = ST_F64;
+    BO.vec = A->host.vec;
+    BI.members.assign(1, &In);
+    BI.vt = vt;
+    BI.st = ST_F32;
+    BI.vec = A->host.vec;
+    FS_TRY(batch_build(BO, s));
+    const int64_t nk = int64_t(Out.n) * k;
+    int32_t outer = 0, inner_total = 0;
+    bool x_zero = o.x0_zero != 0, inner_bad = false;
+    std::vector<ColState> last(static_cast<size_t>(k));
+    for (;;) {
+        // FP64 residual r = b - A x and its norm against rtol |b|
+        FS_HIP_TRY(engine_residual(BO.L, 0, x_zero, s));
+        FS_TRY(batch_read_states(BO, s));
+        x_zero = false;
+        bool done = true;
+        for (int32_t c = 0; c < k; ++c) {
+            last[size_t(c)] = BO.h_stage[c];
+            done &= BO.h_stage[c].status == CG_CONVERGED;
+        }
+        if (done || outer >= o.max_outer || inner_bad ||
+            inner_total >= o.maxit)
+            break;
+        // inner solve A_lo d = r in single precision from d = 0
+        FS_HIP_TRY(to_f32(nk, static_cast<const double *>(Out.r),
+                          static_cast<float *>(In.b), s));
+        FS_HIP_TRY(hipMemsetAsync(In.x, 0, sizeof(float) * size_t(nk), s));
+        In.maxit = std::max(1, o.maxit - inner_total);
+        FS_TRY(run_batch(BI, o.check_every, o.use_graph != 0, true, s));
+        int32_t it = 0;
+        for (int32_t c = 0; c < k; ++c) {
+            it = std::max(it, BI.h_stage[c].iter);
+            if (BI.h_stage[c].status == CG_BREAKDOWN) inner_bad = true;
+        }
+        inner_total += it;
+        ++outer;
+        FS_HIP_TRY(add_f32(nk, static_cast<const float *>(In.x),
+                           static_cast<double *>(Out.x), s));
+    }
+    FS_TRY(store_block(A, k, Out.x, Xc, ldx, s));
+    FS_HIP_TRY(hipStreamSynchronize(s));
+    fs_status ret = FS_OK;
+    const double sv = dt == FS_DT_F32 ? 4.0 : 2.0;
+    const double in_bytes = (sv + 4.0) * double(A->nnz) +
+                            (o.precond ? 52.0 : 44.0) * A->n_rows * k;
+    const double out_bytes = 12.0 * double(A->nnz) + 40.0 * A->n_rows * k;
+    for (int32_t c = 0; c < k; ++c) {
+        const ColState &cs = last[size_t(c)];
+        fs_cg_info &info = infos[c];
+        info.status = cs.status == CG_CONVERGED
+                          ? FS_OK
+                          : inner_bad ? FS_E_BREAKDOWN : FS_E_NOT_CONVERGED;
+        info.iters = inner_total;
+        info.outer = outer;
+        info.replacements = 0;
+        info.relres = cs.bnorm2 > 0.0 ? std::sqrt(cs.rr_true / cs.bnorm2) : 0.0;
+        info.bytes = (inner_total * in_bytes + (outer + 1) * out_bytes) / k;
+        ret = worst(ret, info.status);
+    }
+    return ret;
+}
+
+fs_status check_solve_args(const fs_csr *A, int32_t k, const void *b,
+                           const void *x, int64_t ldb, int64_t ldx)
+{
+    if (!A) return set_error(FS_E_ARG, "NULL matrix handle");
+    if (A->n_rows != A->n_cols)
+        return set_error(FS_E_NOT_SQUARE, "CG needs a square matrix");
+    if (k < 1 || k > 16)
+        return set_error(FS_E_ARG, "k = %d, must be in [1, 16]", k);
+    if (ldb < k || ldx < k)
+        return set_error(FS_E_ARG, "leading dimension below k");
+    if (A->n_rows > 0 && (!b || !x)) return set_error(FS_E_ARG, "NULL vector");
+    return FS_OK;
+}
+
+fs_status solve_any(fs_csr *A, int32_t k, const double *B, int64_t ldb,
+                    double *X, int64_t ldx, const fs_cg_opts *opts,
+                    fs_cg_info *infos, hipStream_t s)
+{
+    fs_cg_opts o;
+    FS_TRY(normalise_opts(opts, o));
+    FS_TRY(check_solve_args(A, k, B, X, ldb, ldx));
+    if (A->n_rows == 0) {
+        for (int32_t c = 0; c < k; ++c) std::memset(&infos[c], 0, sizeof(fs_cg_info));
+        return FS_OK;
+    }
+    DeviceGuard g(A->device);
+    if (o.precision == FS_PREC_F64)
+        return solve_f64(A, k, B, ldb, X, ldx, o, infos, s);
+    return solve_ir(A, k, B, ldb, X, ldx, o, infos, s);
+}
+
+}  // namespace
+
+void free_solver_state(fs_csr *A)
+{
+    for (CgSys **S : {&A->sys_f64, &A->sys_lo}) {
+        if (*S) {
+            sys_free(**S);
+            delete *S;
+            *S = nullptr;
+        }
+    }
+    for (Batch **B : {&A->batch_f64, &A->batch_lo}) {
+        if (*B) {
+            batch_free(**B);
+            delete *B;
+            *B = nullptr;
+        }
+    }
+    if (A->ev) (void)hipEventDestroy(A->ev);
+    A->ev = nullptr;
+    if (A->stream) (void)hipStreamDestroy(A->stream);
+    A->stream = nullptr;
+}
+
+}  // namespace fs
+
+using namespace fs;
+
+extern "C" fs_status cg_solve(fs_csr_t A, const double *b, double *x,
+                              const fs_cg_opts *opts, fs_cg_info *info,
+                              hipStream_t s)
+{
+    const double t0 = now_ms();
+    fs_cg_info local;
+    std::memset(&local, 0, sizeof local);
+    fs_status st = solve_any(A, 1, b, 1, x, 1, opts, &local, s);
+    local.status = st;
+    local.ms = now_ms() - t0;
+    if (info) *info = local;
+    return st;
+}
+
+extern "C" fs_status cg_solve_multi(fs_csr_t A, int32_t k, const double *B,
+                                    int64_t ldb, double *X, int64_t ldx,
+                                    const fs_cg_opts *opts, fs_cg_info *info,
+                                    hipStream_t s)
+{
+    const double t0 = now_ms();
+    if (k < 1 || k > 16)
+        return set_error(FS_E_ARG, "k = %d, must be in [1, 16]", k);
+    std::vector<fs_cg_info> local(static_cast<size_t>(k));
+    std::memset(local.data(), 0, sizeof(fs_cg_info) * size_t(k));
+    fs_status st = solve_any(A, k, B, ldb, X, ldx, opts, local.data(), s);
+    const double ms = now_ms() - t0;
+    for (auto &i : local) {
+        if (st != FS_OK && i.status == FS_OK && i.iters == 0 && i.relres == 0)
+            i.status = st;
+        i.ms = ms;
+    }
+    if (info) std::memcpy(info, local.data(), sizeof(fs_cg_info) * size_t(k));
+    return st;
+}

@@ -1,0 +1,192 @@
+"""GPU parity of the multi-column products, the low-precision products, the
+multi-right-hand-side CG and mixed-precision refinement (through the C
+ABI), against the CPU oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads.meshes import CSR
+from tests.gpu_util import note, dev, host, make, assert_spmv_close
+from tests.test_abi_cpu import ragged
+from tests.test_gpu_cg import kappa
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_1501_00324_amd as fs
+    fs.load(build_if_missing=False)
+    return fs
+
+
+def true_relres(orc, A, x, b):
+    return np.linalg.norm(b - orc.spmv(A, x)) / np.linalg.norm(b)
+
+
+# ------------------------------------------------------------------ SpMM
+MATS = [
+    ("cfg0", W.config0_poisson2d, {}),
+    ("ela_perm", lambda: W.tet_p1(9, "elastic", seed=(40, 0), bc="x0",
+                                  permute=True), {}),
+    ("ela_v1_t4", lambda: W.tet_p1(7, "elastic", seed=(40, 1)),
+     dict(vec=1, lanes_min=4, lanes_max=4)),
+    ("ragged_rect", lambda: ragged(700, 333, seed=5), {}),
+]
+
+
+@pytest.mark.parametrize("name,gen,opts", MATS, ids=[m[0] for m in MATS])
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 13, 16])
+def test_spmm_parity(fs, orc, name, gen, opts, k):
+    import torch
+    A = gen()
+    note("spmm %s k=%d" % (name, k))
+    M = make(A, **opts)
+    X = W.random_vector(A.n_cols, 41, W.XVEC, k, k=k)
+    ld = k + 3
+    Xp = np.zeros((A.n_cols, ld))
+    Xp[:, :k] = X
+    Yd = torch.full((A.n_rows, ld), 7.0, dtype=torch.float64, device="cuda")
+    Xd = dev(Xp)
+    st = fs.load().spmm(M._h, k, Xd.data_ptr(), ld, Yd.data_ptr(), ld,
+                        torch.cuda.current_stream().cuda_stream)
+    assert st == fs.FS_OK, fs.last_error()
+    Y = host(Yd)
+    Yo = orc.spmm(A, X)
+    for c in range(k):
+        assert_spmv_close(Y[:, c], Yo[:, c], orc.spmv_abs(A, X[:, c].copy()),
+                          "spmm col %d" % c)
+    assert np.all(Y[:, k:] == 7.0)          # padding columns untouched
+    # k = 1 agrees bitwise with the single-vector product
+    if k == 1:
+        y1 = host(fs.spmv(M, dev(X[:, 0].copy())))
+        assert np.array_equal(Y[:, 0], y1)
+
+
+def test_spmm_rejects_bad_k(fs, orc):
+    A = W.config0_poisson2d()
+    M = make(A)
+    import torch
+    X = torch.zeros((A.n_rows, 17), dtype=torch.float64, device="cuda")
+    for k, ld in [(0, 17), (17, 17), (4, 3)]:
+        st = fs.load().spmm(M._h, k, X.data_ptr(), ld, X.data_ptr() + 8, ld,
+                            0)
+        assert st == fs.FS_E_ARG
+
+
+# ------------------------------------------------------- low precision
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_lowp_storage_is_exact_rounding(fs, orc, dtype):
+    """Unit vectors read back single columns of the stored copy: every
+    stored value equals the oracle's rounding (FP32 nearest; BF16 nearest
+    even of the FP32 value) bit for bit."""
+    import torch
+    A = W.tet_p1(6, "elastic", seed=(42, 0), bc="x0", permute=True)
+    note("lowp storage %s" % dtype)
+    M = make(A)
+    dt = fs.DT_F32 if dtype == "f32" else fs.DT_BF16
+    fs.csr_add_dtype(M, dt)
+    if dtype == "f32":
+        ref = orc.round_f32(A.val)
+    else:
+        ref = orc.bf16_bits_to_f32(orc.round_bf16(A.val))
+    Alo = CSR(A.n_rows, A.n_cols, A.rowptr, A.col, ref.astype(np.float64))
+    D = Alo.to_dense()
+    perm = fs.csr_get_perm(M)
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(len(perm))
+    for j in range(0, A.n_cols, 37):
+        e = np.zeros(A.n_cols, np.float32)
+        e[iperm[j]] = 1.0            # layout position of column j
+        y = host(fs.spmv_lowp(M, dt, dev(e)))
+        col = y[iperm]               # back to caller numbering
+        assert np.array_equal(col.astype(np.float64), D[:, j])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_lowp_product_error_bound(fs, orc, dtype):
+    A = W.config0_poisson2d()
+    note("lowp product %s" % dtype)
+    M = make(A)
+    dt = fs.DT_F32 if dtype == "f32" else fs.DT_BF16
+    fs.csr_add_dtype(M, dt)
+    a = orc.round_f32(A.val) if dtype == "f32" else \
+        orc.bf16_bits_to_f32(orc.round_bf16(A.val))
+    x = W.random_vector(A.n_cols, 43, W.XVEC).astype(np.float32)
+    perm = fs.csr_get_perm(M)
+    y = host(fs.spmv_lowp(M, dt, dev(x[perm])))
+    yo = orc.spmv_f32(A, a, x)[perm]
+    Af = CSR(A.n_rows, A.n_cols, A.rowptr, A.col, a.astype(float))
+    scale = orc.spmv_abs(Af, x.astype(float))[perm]
+    m = A.row_lengths().max()
+    u = 2.0 ** -24
+    assert np.all(np.abs(y.astype(float) - yo.astype(float)) <=
+                  2 * m * u * scale + 1e-30)
+
+
+# ------------------------------------------------------- multi-RHS CG
+def test_multi_rhs_columns_equal_single_solves(fs, orc):
+    A = W.tet_p1(8, "elastic", seed=(44, 0), bc="x0", permute=True)
+    k = 5
+    B = W.random_vector(A.n_rows, 44, W.BVEC, 0, k=k)
+    B[:, 3] = 0.0                          # a zero right-hand side
+    note("cg multi k=%d" % k)
+    M = make(A)
+    X, infos = fs.cg_solve_multi(M, dev(B), precond=1)
+    Xh = host(X)
+    for c in range(k):
+        x1, i1 = fs.cg_solve(M, dev(B[:, c].copy()), precond=1)
+        assert np.array_equal(Xh[:, c], host(x1)), c
+        assert infos[c]["iters"] == i1["iters"]
+        if c == 3:
+            assert infos[c]["iters"] == 0 and not Xh[:, c].any()
+        else:
+            assert infos[c]["status"] == fs.FS_OK
+            assert true_relres(orc, A, Xh[:, c], B[:, c]) <= 1.001e-8
+
+
+@pytest.mark.parametrize("k", [2, 16])
+def test_multi_rhs_parity(fs, orc, k):
+    global KAPPA0
+    A = W.config0_poisson2d()
+    KAPPA0 = kappa(A)
+    B = W.random_vector(A.n_rows, 45, W.BVEC, k, k=k)
+    note("cg multi parity k=%d" % k)
+    M = make(A)
+    X, infos = fs.cg_solve_multi(M, dev(B), precond=0)
+    Xh = host(X)
+    for c in range(k):
+        xo, st, it, rr = orc.pcg(A, B[:, c].copy(), precond=0)
+        assert infos[c]["status"] == fs.FS_OK
+        assert true_relres(orc, A, Xh[:, c], B[:, c]) <= 1.001e-8
+        assert np.linalg.norm(Xh[:, c] - xo) <= 2e-8 * KAPPA0 * \
+            np.linalg.norm(xo)
+
+
+# ------------------------------------------------ mixed precision (IR)
+IR_CASES = [
+    ("cfg0", W.config0_poisson2d),
+    ("ela8", lambda: W.tet_p1(8, "elastic", seed=(46, 0), bc="x0",
+                              permute=True)),
+]
+
+
+@pytest.mark.parametrize("name,gen", IR_CASES, ids=[c[0] for c in IR_CASES])
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_ir_reaches_fp64_residual(fs, orc, name, gen, prec):
+    A = gen()
+    b = W.random_vector(A.n_rows, 46, W.BVEC)
+    note("ir %s %s" % (name, prec))
+    M = make(A)
+    p = fs.PREC_IR_F32 if prec == "f32" else fs.PREC_IR_BF16
+    x, info = fs.cg_solve(M, dev(b), precond=1, precision=p, inner_rtol=1e-2)
+    xg = host(x)
+    assert info["status"] == fs.FS_OK, info
+    assert info["outer"] >= 2
+    assert info["relres"] <= 1e-8
+    assert true_relres(orc, A, xg, b) <= 1.001e-8
+    xo, st, it, rr = orc.pcg(A, b, precond=1)
+    assert np.linalg.norm(xg - xo) <= 4e-8 * kappa(A) * np.linalg.norm(xo)
