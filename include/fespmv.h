@@ -248,6 +248,20 @@ fs_status cg_solve_multi(fs_csr_t A, int32_t k, const double *B, int64_t ldb,
                          double *X, int64_t ldx, const fs_cg_opts *opts,
                          fs_cg_info *info, hipStream_t s);
 
+/* m independent systems A[i] X[i] = B[i] with k[i] right-hand sides each
+ * (1 <= k[i] <= 16), advanced by the same launches: every iteration is one
+ * batched product kernel and a fixed number of vector / reduction kernels
+ * for all systems together, so many small systems cost what one does.
+ * B[i] and X[i] are n_i x k[i] row-major device blocks (row stride k[i]).
+ * Each system's iterates, reductions included, are bitwise those of solving
+ * it alone.  FP64 only (FS_E_UNSUPPORTED otherwise).  info (may be NULL)
+ * receives sum(k) entries, systems in order.  Blocking; returns the worst
+ * status over all right-hand sides. */
+fs_status cg_solve_batch(int32_t m, const fs_csr_t *A, const int32_t *k,
+                         const double *const *B, double *const *X,
+                         const fs_cg_opts *opts, fs_cg_info *info,
+                         hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

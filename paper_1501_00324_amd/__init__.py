@@ -83,7 +83,8 @@ EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "csr_layout_host",
            "csr_update_values", "csr_add_dtype", "csr_info", "csr_get_perm",
            "csr_destroy", "spmv", "spmv_perm", "csr_permute", "spmm",
-           "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_multi"]
+           "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_multi",
+           "cg_solve_batch"]
 
 _lib = None
 
@@ -125,6 +126,7 @@ def load(build_if_missing=True):
         "cg_solve": [vp, vp, vp, P(CgOpts), P(CgInfo), vp],
         "cg_solve_multi": [vp, i32, vp, i64, vp, i64, P(CgOpts), P(CgInfo),
                            vp],
+        "cg_solve_batch": [i32, vp, vp, vp, vp, P(CgOpts), P(CgInfo), vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -391,3 +393,32 @@ def cg_solve_multi(A, B, X=None, stream=None, check=True, **opts):
                                             FS_E_BREAKDOWN)):
         raise FsError(st, msg)
     return X, out
+
+
+def cg_solve_batch(mats, Bs, Xs=None, stream=None, check=True, **opts):
+    """Solve m independent systems mats[i] X_i = Bs[i] (each n_i x k_i, or a
+    vector) with shared launches; returns (Xs, per-RHS info dicts)."""
+    import torch
+    m = len(mats)
+    Bs = [b if b.dim() == 2 else b.reshape(-1, 1) for b in Bs]
+    if Xs is None:
+        Xs = [torch.zeros_like(b) for b in Bs]
+        opts.setdefault("x0_zero", 1)
+    else:
+        Xs = [x if x.dim() == 2 else x.reshape(-1, 1) for x in Xs]
+    ks = (C.c_int32 * m)(*[b.shape[1] for b in Bs])
+    hs = (C.c_void_p * m)(*[M._h for M in mats])
+    bp = (C.c_void_p * m)(*[_ptr(b, torch.float64, M.n_rows * b.shape[1],
+                                 "B") for M, b in zip(mats, Bs)])
+    xp = (C.c_void_p * m)(*[_ptr(x, torch.float64, M.n_rows * x.shape[1],
+                                 "X") for M, x in zip(mats, Xs)])
+    o = cg_opts(**opts)
+    infos = (CgInfo * max(1, sum(ks)))()
+    st = load().cg_solve_batch(m, hs, ks, bp, xp, C.byref(o), infos,
+                               _stream(stream))
+    out = [infos[i].as_dict() for i in range(sum(ks))]
+    msg = last_error() if st != FS_OK else ""
+    if st != FS_OK and (check or st not in (FS_E_NOT_CONVERGED,
+                                            FS_E_BREAKDOWN)):
+        raise FsError(st, msg)
+    return Xs, out

@@ -647,3 +647,112 @@ extern "C" fs_status cg_solve_multi(fs_csr_t A, int32_t k, const double *B,
     if (info) std::memcpy(info, local.data(), sizeof(fs_cg_info) * size_t(k));
     return st;
 }
+
+extern "C" fs_status cg_solve_batch(int32_t m, const fs_csr_t *A,
+                                    const int32_t *k, const double *const *B,
+                                    double *const *X, const fs_cg_opts *opts,
+                                    fs_cg_info *info, hipStream_t caller)
+{
+    const double t0 = now_ms();
+    fs_cg_opts o;
+    FS_TRY(normalise_opts(opts, o));
+    if (m < 0 || (m > 0 && (!A || !k || !B || !X)))
+        return set_error(FS_E_ARG, "NULL batch array or negative count");
+    if (o.precision != FS_PREC_F64)
+        return set_error(FS_E_UNSUPPORTED,
+                         "batched solves run in FP64 (mixed precision is "
+                         "available per system through cg_solve)");
+    int32_t ncols = 0, dev = -1;
+    for (int32_t i = 0; i < m; ++i) {
+        FS_TRY(check_solve_args(A[i], k[i], B[i], X[i], k[i], k[i]));
+        if (dev >= 0 && A[i]->device != dev)
+            return set_error(FS_E_ARG, "batch members on different devices");
+        dev = A[i]->device;
+        ncols += k[i];
+    }
+    std::vector<fs_cg_info> local(static_cast<size_t>(ncols));
+    std::memset(local.data(), 0, sizeof(fs_cg_info) * size_t(ncols));
+    if (m == 0) return FS_OK;
+    DeviceGuard g(dev);
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    FS_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    std::vector<CgSys> sys(static_cast<size_t>(m));
+    fs_status st = FS_OK;
+    auto run = [&]() -> fs_status {
+        FS_HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        FS_HIP_TRY(hipEventRecord(ev, caller));
+        FS_HIP_TRY(hipStreamWaitEvent(s, ev, 0));
+        for (int32_t i = 0; i < m; ++i) {
+            CgSys &S = sys[size_t(i)];
+            if (A[i]->n_rows == 0) continue;
+            FS_TRY(sys_alloc(S, A[i], k[i], VT_F64, ST_F64, o.precond));
+            S.rtol = o.rtol;
+            S.maxit = o.maxit;
+            FS_TRY(load_block(A[i], k[i], B[i], k[i], S.b, s));
+            if (o.x0_zero)
+                FS_HIP_TRY(hipMemsetAsync(S.x, 0, sizeof(double) * size_t(S.n) *
+                                                      size_t(k[i]), s));
+            else
+                FS_TRY(load_block(A[i], k[i], X[i], k[i], S.x, s));
+        }
+        // one batch per slot vector width (the width is a template
+        // parameter of the product)
+        for (int32_t vec = 1; vec <= 2; ++vec) {
+            Batch Bt;
+            Bt.vt = VT_F64;
+            Bt.st = ST_F64;
+            Bt.vec = vec;
+            std::vector<int32_t> idx;
+            for (int32_t i = 0; i < m; ++i)
+                if (A[i]->n_rows > 0 && A[i]->host.vec == vec) {
+                    Bt.members.push_back(&sys[size_t(i)]);
+                    idx.push_back(i);
+                }
+            if (Bt.members.empty()) continue;
+            fs_status r = run_batch(Bt, o.check_every, o.use_graph != 0,
+                                    o.x0_zero != 0, s);
+            if (r == FS_OK) {
+                int32_t j = 0;
+                for (int32_t i : idx) {
+                    CgSys &S = sys[size_t(i)];
+                    int32_t off = 0;
+                    for (int32_t q = 0; q < i; ++q) off += k[q];
+                    for (int32_t c = 0; c < S.k; ++c, ++j) {
+                        const ColState &cs = Bt.h_stage[j];
+                        fill_info(cs, local[size_t(off + c)]);
+                        local[size_t(off + c)].bytes =
+                            cs.iter * (12.0 * double(A[i]->nnz) / S.k +
+                                       (o.precond ? 104.0 : 88.0) * S.n);
+                        if (cs.bnorm2 == 0.0)
+                            FS_HIP_TRY(hipMemset2DAsync(
+                                static_cast<double *>(S.x) + c,
+                                sizeof(double) * size_t(S.k), 0,
+                                sizeof(double), size_t(S.n), s));
+                    }
+                    FS_TRY(store_block(A[i], S.k, S.x, X[i], S.k, s));
+                }
+            }
+            batch_free(Bt);
+            FS_TRY(r);
+        }
+        FS_HIP_TRY(hipStreamSynchronize(s));
+        return FS_OK;
+    };
+    st = run();
+    (void)hipStreamSynchronize(s);
+    for (CgSys &S : sys) sys_free(S);
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(s);
+    if (st != FS_OK) return st;
+    const double ms = now_ms() - t0;
+    for (auto &i : local) {
+        i.ms = ms;
+        st = worst(st, i.status);
+    }
+    if (info) std::memcpy(info, local.data(), sizeof(fs_cg_info) * size_t(ncols));
+    if (st != FS_OK)
+        set_error(st, "batched CG: at least one right-hand side did not "
+                      "converge");
+    return st;
+}
