@@ -30,6 +30,42 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def bench_small_batch(fs, W, oracle, d, torch, m=64):
+    """m small systems (2-D Poisson, 48x48 nodes, each its own jittered
+    mesh and right-hand side): one at a time vs. all m in shared launches."""
+    mats, Ms, bs = [], [], []
+    for i in range(m):
+        A = W.poisson_2d_p1(48, seed=(4, i), bc="all")
+        mats.append(A)
+        Ms.append(fs.csr_create(d(A.rowptr), d(A.col), d(A.val), A.n_rows,
+                                A.n_cols))
+        bs.append(d(W.random_vector(A.n_rows, 4, W.BVEC, i)))
+    fs.cg_solve(Ms[0], bs[0], precond=fs.PC_JACOBI)          # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs1 = [fs.cg_solve(M, b, precond=fs.PC_JACOBI)[0] for M, b in
+           zip(Ms, bs)]
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    fs.cg_solve_batch(Ms[:2], bs[:2], precond=fs.PC_JACOBI)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xsb, infos = fs.cg_solve_batch(Ms, bs, precond=fs.PC_JACOBI)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    same = all(torch.equal(a.reshape(-1), bb.reshape(-1))
+               for a, bb in zip(xs1, xsb))
+    worst = max(float(np.linalg.norm(bs[i].cpu().numpy() - oracle.spmv(
+        mats[i], xsb[i].reshape(-1).cpu().numpy())) /
+        np.linalg.norm(bs[i].cpu().numpy())) for i in range(m))
+    return {"systems": m, "rows_each": mats[0].n_rows,
+            "one_at_a_time_solves_per_s": m / t_one,
+            "batched_solves_per_s": m / t_b,
+            "speedup": t_one / t_b, "bitwise_equal_to_alone": bool(same),
+            "relres_oracle_worst": worst,
+            "iters_max": max(i["iters"] for i in infos)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,27 +148,62 @@ def main():
     log("spmv (caller numbering): %.2f us, %.1f GB/s"
         % (ms_caller * 1e3, gbs_caller))
 
-    cg = None
+    cg = ir = multi = batch = None
     if not args.no_cg:
         b = W.random_vector(A.n_rows, 1, W.BVEC)
         bd = d(b)
         fs.cg_solve(M, bd, precond=fs.PC_JACOBI, maxit=3, check=False)
-        times = []
-        for _ in range(3):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            xs, ci = fs.cg_solve(M, bd, precond=fs.PC_JACOBI, rtol=1e-8)
-            times.append(time.perf_counter() - t0)
-        xs_h = xs.cpu().numpy()
-        rel = float(np.linalg.norm(b - oracle.spmv(A, xs_h)) /
-                    np.linalg.norm(b))
-        tmed = float(np.median(times))
-        cg = {"precond": "jacobi", "rtol": 1e-8, "iters": ci["iters"],
-              "ms": tmed * 1e3, "solves_per_s": 1.0 / tmed,
-              "relres_oracle": rel, "relres_gpu": ci["relres"],
-              "replacements": ci["replacements"],
-              "gbs_per_solve": ci["bytes"] / tmed / 1e9}
-        log("cg: %s" % json.dumps(cg))
+
+        def timed_solve(reps=3, **kw):
+            times = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                xs, ci = fs.cg_solve(M, bd, precond=fs.PC_JACOBI, rtol=1e-8,
+                                     check=False, **kw)
+                times.append(time.perf_counter() - t0)
+            xs_h = xs.cpu().numpy()
+            rel = float(np.linalg.norm(b - oracle.spmv(A, xs_h)) /
+                        np.linalg.norm(b))
+            tmed = float(np.median(times))
+            return xs_h, {"status": ci["status"], "iters": ci["iters"],
+                          "outer": ci["outer"], "ms": tmed * 1e3,
+                          "solves_per_s": 1.0 / tmed,
+                          "relres_oracle": rel, "relres_gpu": ci["relres"],
+                          "replacements": ci["replacements"],
+                          "gbs_per_solve": ci["bytes"] / tmed / 1e9}
+
+        x64, cg = timed_solve()
+        cg.update(precond="jacobi", rtol=1e-8)
+        log("cg fp64: %s" % json.dumps(cg))
+        ir = {}
+        for name, prec in (("f32", fs.PREC_IR_F32), ("bf16", fs.PREC_IR_BF16)):
+            xl, r = timed_solve(reps=2, precision=prec, inner_rtol=1e-2)
+            r["forward_err_vs_fp64"] = float(np.linalg.norm(xl - x64) /
+                                             np.linalg.norm(x64))
+            r["speedup_vs_fp64"] = cg["ms"] / r["ms"]
+            ir[name] = r
+            log("cg ir-%s: %s" % (name, json.dumps(r)))
+        # k right-hand sides through one multi-column product per iteration
+        k = 16
+        Bk = W.random_vector(A.n_rows, 1, W.BVEC, 1, k=k)
+        Bkd = d(Bk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xk, infos = fs.cg_solve_multi(M, Bkd, precond=fs.PC_JACOBI,
+                                      check=False)
+        tk = time.perf_counter() - t0
+        Xk_h = Xk.cpu().numpy()
+        worst = max(float(np.linalg.norm(Bk[:, c] - oracle.spmv(A, Xk_h[:, c]
+                                                                .copy())) /
+                          np.linalg.norm(Bk[:, c])) for c in range(k))
+        multi = {"k": k, "ms": tk * 1e3, "solves_per_s": k / tk,
+                 "speedup_vs_one_at_a_time": (k / tk) / cg["solves_per_s"],
+                 "iters_max": max(i["iters"] for i in infos),
+                 "relres_oracle_worst": worst}
+        log("cg multi-rhs: %s" % json.dumps(multi))
+        batch = bench_small_batch(fs, W, oracle, d, torch)
+        log("batched small systems: %s" % json.dumps(batch))
 
     # CPU oracle on a bounded sample: repeated full products
     reps, tc = 0, 0.0
@@ -177,6 +248,9 @@ def main():
                                         "groups_by_lanes", "t_build_ms")},
         "parity_all_rows": ok,
         "cg": cg,
+        "cg_mixed_precision": ir,
+        "cg_multi_rhs": multi,
+        "cg_batched_small": batch,
     }
     print(json.dumps(out), flush=True)
 

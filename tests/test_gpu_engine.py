@@ -190,3 +190,60 @@ def test_ir_reaches_fp64_residual(fs, orc, name, gen, prec):
     assert true_relres(orc, A, xg, b) <= 1.001e-8
     xo, st, it, rr = orc.pcg(A, b, precond=1)
     assert np.linalg.norm(xg - xo) <= 4e-8 * kappa(A) * np.linalg.norm(xo)
+
+
+# ------------------------------------------------------- batched systems
+def batch_members():
+    return [
+        (W.poisson_2d_p1(20, seed=(47, 0), bc="all"), 1),
+        (W.tet_p1(6, "elastic", seed=(47, 1), bc="x0", permute=True), 3),
+        (W.poisson_2d_p1(33, seed=(47, 2), bc="all", permute=True), 2),
+        (W.hex_q1(5, "laplace", seed=(47, 3), bc="all"), 1),
+        (W.tet_p1(9, "laplace", seed=(47, 4), bc="all"), 16),
+    ]
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_batch_alone_equals_mix(fs, orc, precond):
+    """Every system of a batch gets bitwise the result of solving it alone,
+    whatever else shares the launches (the reductions depend only on the
+    system's own grid)."""
+    mem = batch_members()
+    note("cg batch of %d, precond %d" % (len(mem), precond))
+    Ms = [make(A) for A, _ in mem]
+    Bs = [W.random_vector(A.n_rows, 48, W.BVEC, i, k=k)
+          for i, (A, k) in enumerate(mem)]
+    alone = []
+    for M, B in zip(Ms, Bs):
+        X, inf = fs.cg_solve_multi(M, dev(B), precond=precond)
+        alone.append((host(X), [i["iters"] for i in inf]))
+    Xs, infos = fs.cg_solve_batch(Ms, [dev(B) for B in Bs], precond=precond)
+    j = 0
+    for (A, k), X, B, (Xa, its) in zip(mem, Xs, Bs, alone):
+        Xh = host(X)
+        assert np.array_equal(Xh, Xa)
+        for c in range(k):
+            assert infos[j]["iters"] == its[c]
+            assert infos[j]["status"] == fs.FS_OK
+            assert true_relres(orc, A, Xh[:, c], B[:, c]) <= 1.001e-8
+            j += 1
+    # a different mix: reversed order, half the members
+    sub = list(range(len(mem)))[::-2]
+    Xs2, _ = fs.cg_solve_batch([Ms[i] for i in sub],
+                               [dev(Bs[i]) for i in sub], precond=precond)
+    for i, X in zip(sub, Xs2):
+        assert np.array_equal(host(X), alone[i][0])
+
+
+def test_batch_reports_per_rhs_status(fs, orc):
+    Ind = CSR(2, 2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32),
+              np.array([1.0, -1.0]))
+    A = W.poisson_2d_p1(12, seed=(49, 0), bc="all")
+    note("cg batch status")
+    Ms = [make(A), make(Ind)]
+    Bs = [dev(W.random_vector(A.n_rows, 49, W.BVEC)), dev(np.ones(2))]
+    Xs, infos = fs.cg_solve_batch(Ms, Bs, precond=0, check=False)
+    assert infos[0]["status"] == fs.FS_OK
+    assert infos[1]["status"] == fs.FS_E_BREAKDOWN
+    assert true_relres(orc, A, host(Xs[0]).reshape(-1),
+                       host(Bs[0])) <= 1.001e-8
