@@ -66,6 +66,119 @@ def bench_small_batch(fs, W, oracle, d, torch, m=64):
             "iters_max": max(i["iters"] for i in infos)}
 
 
+def serving_pool(W, n_mats=6):
+    """P1-tet Laplacian (all boundary nodes removed) or elasticity (x = 0
+    face clamped) meshes with random numbering, row counts log-uniform in
+    [5e3, 5e5]."""
+    g = W.rng(4, W.SIZES, 0)
+    pool = []
+    for i in range(n_mats):
+        rows = float(np.exp(g.uniform(np.log(5e3), np.log(5e5))))
+        if g.uniform() < 0.5:
+            n = max(4, int(round(rows ** (1 / 3))) + 2)
+            A = W.tet_p1(n, "laplace", seed=(4, 100 + i), bc="all",
+                         permute=True)
+        else:
+            n = max(4, int(round((rows / 3) ** (1 / 3))))
+            A = W.tet_p1(n, "elastic", seed=(4, 100 + i), bc="x0",
+                         permute=True)
+        pool.append(A)
+    return pool
+
+
+def percentile(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def bench_serving(fs, W, oracle, d, torch, n_req=32, lam_factors=(1, 2, 4)):
+    """Poisson arrivals of CG requests (pool matrix, k ~ U{1..16} right-hand
+    sides ~ U(-1,1)).  Baseline: the same requests served one at a time
+    (FIFO, each request by cg_solve_multi, service times measured, queueing
+    computed from the arrival times).  Server: live continuous batching."""
+    pool = serving_pool(W)
+    Ms = [fs.csr_create(d(A.rowptr), d(A.col), d(A.val), A.n_rows, A.n_cols)
+          for A in pool]
+    g = W.rng(4, W.ARRIVALS, 0)
+    reqs = []
+    for i in range(n_req):
+        mi = int(g.integers(0, len(pool)))
+        k = int(g.integers(1, 17))
+        reqs.append((mi, k, d(W.random_vector(pool[mi].n_rows, 4, W.BVEC,
+                                              1000 + i, k=k))))
+    # warm every matrix once
+    for M in Ms:
+        fs.cg_solve(M, torch.ones(M.n_rows, dtype=torch.float64,
+                                  device="cuda"), maxit=2, check=False)
+    service, alone = [], []
+    for mi, k, B in reqs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, _ = fs.cg_solve_multi(Ms[mi], B, precond=fs.PC_JACOBI)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        alone.append(X)
+    total_k = sum(k for _, k, _ in reqs)
+    mu = n_req / sum(service)                   # requests per second
+    out = {"pool_rows": [A.n_rows for A in pool],
+           "pool_nnz": [A.nnz for A in pool], "requests": n_req,
+           "rhs_total": total_k,
+           "one_at_a_time_requests_per_s": mu,
+           "one_at_a_time_solves_per_s": total_k / sum(service),
+           "by_lambda": []}
+    same_all = True
+    for f in lam_factors:
+        lam = f * mu
+        gaps = g.exponential(1.0 / lam, n_req)
+        arrivals = np.cumsum(gaps) - gaps[0]
+        # FIFO single-server baseline on the measured service times
+        finish, lat_b = 0.0, []
+        for a, s in zip(arrivals, service):
+            finish = max(finish, a) + s
+            lat_b.append(finish - a)
+        srv = fs.Server(precond=fs.PC_JACOBI, check_every=16)
+        t0 = time.perf_counter()
+        xs = {}
+        done = []
+        for i, (mi, k, B) in enumerate(reqs):
+            while time.perf_counter() - t0 < arrivals[i]:
+                done += srv.poll()
+                time.sleep(0.0002)
+            rid, X = srv.submit(Ms[mi], B)
+            xs[rid] = (i, X)
+        done += srv.drain()
+        makespan = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat_s = [dd["info"]["ms"] / 1e3 for dd in done]
+        ok = all(dd["info"]["status"] == fs.FS_OK for dd in done)
+        same = all(torch.equal(xs[dd["req_id"]][1], alone[xs[dd["req_id"]][0]])
+                   for dd in done)
+        same_all &= same
+        out["by_lambda"].append({
+            "lambda_over_mu": f, "lambda_req_per_s": lam,
+            "server": {"p50_ms": percentile(lat_s, 50) * 1e3,
+                       "p99_ms": percentile(lat_s, 99) * 1e3,
+                       "solves_per_s": total_k / makespan,
+                       "requests_per_s": n_req / makespan,
+                       "all_converged": ok, "peak_active": st["peak_active"],
+                       "peak_bytes": st["peak_bytes"]},
+            "one_at_a_time": {"p50_ms": percentile(lat_b, 50) * 1e3,
+                              "p99_ms": percentile(lat_b, 99) * 1e3,
+                              "solves_per_s": total_k / max(
+                                  finish, arrivals[-1])}})
+    out["bitwise_equal_to_alone"] = bool(same_all)
+    # true residuals of one served run, recomputed by the oracle
+    worst = 0.0
+    for (mi, k, B), X in zip(reqs, alone):
+        Bh, Xh = B.cpu().numpy(), X.cpu().numpy()
+        for c in range(k):
+            worst = max(worst, float(np.linalg.norm(
+                Bh[:, c] - oracle.spmv(pool[mi], Xh[:, c].copy())) /
+                np.linalg.norm(Bh[:, c])))
+    out["relres_oracle_worst"] = worst
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +186,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is a single-GPU "
@@ -204,6 +318,11 @@ def main():
         log("cg multi-rhs: %s" % json.dumps(multi))
         batch = bench_small_batch(fs, W, oracle, d, torch)
         log("batched small systems: %s" % json.dumps(batch))
+    serving = None
+    if args.serving_requests > 0:
+        serving = bench_serving(fs, W, oracle, d, torch,
+                                n_req=args.serving_requests)
+        log("serving: %s" % json.dumps(serving))
 
     # CPU oracle on a bounded sample: repeated full products
     reps, tc = 0, 0.0
@@ -251,6 +370,7 @@ def main():
         "cg_mixed_precision": ir,
         "cg_multi_rhs": multi,
         "cg_batched_small": batch,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

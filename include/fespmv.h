@@ -262,6 +262,67 @@ fs_status cg_solve_batch(int32_t m, const fs_csr_t *A, const int32_t *k,
                          const fs_cg_opts *opts, fs_cg_info *info,
                          hipStream_t s);
 
+/* ------------------------------------------------------------- serving */
+/* A solve server: requests (a matrix handle and k right-hand sides) are
+ * admitted in arrival order while a device-memory budget and a slot count
+ * allow, and every admitted request is advanced by the same batched
+ * launches as the others (continuous batching: requests join and leave at
+ * chunk boundaries of check_every iterations).  Each result is bitwise the
+ * result of solving that request alone with cg_solve_multi and the same
+ * options.  One worker thread per server does all device work on its own
+ * stream; submit / poll / stats may be called from any thread. */
+typedef struct fs_server *fs_server_t;
+
+typedef struct fs_server_opts {
+    int64_t hbm_budget_bytes; /* device bytes for admitted requests: their
+                                 Krylov state plus the handle of every
+                                 matrix in use; 0 = 16 GiB                  */
+    int32_t max_slots;        /* requests in flight; 0 = 64                 */
+    int32_t check_every;      /* iterations per chunk; 0 = 16               */
+    int32_t precond;          /* FS_PC_*; default JACOBI                     */
+    int32_t maxit;            /* 0 = 20000                                  */
+    double rtol;              /* true relative residual; 0 = 1e-8          */
+    int32_t use_graph;        /* replay chunks as HIP graphs (default 1)    */
+    int32_t reserved[7];
+} fs_server_opts;
+
+typedef struct fs_server_done {
+    uint64_t req_id;
+    int32_t k;
+    int32_t pad;
+    fs_cg_info info;          /* worst status, max iterations and max true
+                                 relative residual over the k columns;
+                                 info.ms = submit-to-done latency           */
+    double t_submit_ms, t_admit_ms, t_done_ms;   /* server clock (ms)       */
+} fs_server_done;
+
+typedef struct fs_server_stats {
+    int32_t queued, active, peak_active, pad;
+    uint64_t submitted, completed;
+    int64_t bytes_in_use, peak_bytes;
+} fs_server_stats;
+
+fs_status server_opts_default(fs_server_opts *o);
+fs_status server_create(const fs_server_opts *opts, fs_server_t *out);
+
+/* Queue a request: solve A X = B for the k columns (1..16) of the n x k
+ * row-major device block B (row stride k) into X (same shape).  B and X
+ * stay owned by the caller and must stay valid, and A must not be
+ * destroyed, until the request is returned by server_poll.  Returns at
+ * once with *req_id.  FS_E_BUDGET if the request alone exceeds the budget
+ * (it could never be admitted). */
+fs_status server_submit(fs_server_t S, fs_csr_t A, int32_t k, const double *B,
+                        double *X, uint64_t *req_id);
+
+/* Move up to cap finished requests into done[]; *n receives the count.
+ * Non-blocking. */
+fs_status server_poll(fs_server_t S, fs_server_done *done, int32_t cap,
+                      int32_t *n);
+fs_status server_stats(fs_server_t S, fs_server_stats *st);
+
+/* Finish every queued and running request, then free the server. */
+fs_status server_destroy(fs_server_t S);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,7 +84,8 @@ EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "csr_update_values", "csr_add_dtype", "csr_info", "csr_get_perm",
            "csr_destroy", "spmv", "spmv_perm", "csr_permute", "spmm",
            "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_multi",
-           "cg_solve_batch"]
+           "cg_solve_batch", "server_opts_default", "server_create",
+           "server_submit", "server_poll", "server_stats", "server_destroy"]
 
 _lib = None
 
@@ -422,3 +423,116 @@ def cg_solve_batch(mats, Bs, Xs=None, stream=None, check=True, **opts):
                                             FS_E_BREAKDOWN)):
         raise FsError(st, msg)
     return Xs, out
+
+
+# ------------------------------------------------------------------ serving
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32),
+                ("check_every", C.c_int32), ("precond", C.c_int32),
+                ("maxit", C.c_int32), ("rtol", C.c_double),
+                ("use_graph", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class ServerDone(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("k", C.c_int32), ("pad", C.c_int32),
+                ("info", CgInfo), ("t_submit_ms", C.c_double),
+                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("queued", C.c_int32), ("active", C.c_int32),
+                ("peak_active", C.c_int32), ("pad", C.c_int32),
+                ("submitted", C.c_uint64), ("completed", C.c_uint64),
+                ("bytes_in_use", C.c_int64), ("peak_bytes", C.c_int64)]
+
+
+def _declare_server(L):
+    vp, i32 = C.c_void_p, C.c_int32
+    P = C.POINTER
+    for name, args in {
+            "server_opts_default": [P(ServerOpts)],
+            "server_create": [P(ServerOpts), P(vp)],
+            "server_submit": [vp, vp, i32, vp, vp, P(C.c_uint64)],
+            "server_poll": [vp, P(ServerDone), i32, P(i32)],
+            "server_stats": [vp, P(ServerStats)],
+            "server_destroy": [vp]}.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int32
+
+
+class Server:
+    """Continuous-batching solve server (marshalling around server_*)."""
+
+    def __init__(self, **opts):
+        L = load()
+        if not hasattr(L, "_server_declared"):
+            _declare_server(L)
+            L._server_declared = True
+        o = ServerOpts()
+        L.server_opts_default(C.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        h = C.c_void_p()
+        _check(L.server_create(C.byref(o), C.byref(h)))
+        self.h = h.value
+        self.keep = {}          # req_id -> (B, X) tensors kept alive
+
+    def submit(self, A, B, X=None):
+        import torch
+        if B.dim() == 1:
+            B = B.reshape(-1, 1)
+        if X is None:
+            X = torch.zeros_like(B)
+        n, k = B.shape
+        rid = C.c_uint64()
+        _check(load().server_submit(self.h, A._h, k,
+                                    _ptr(B, torch.float64, n * k, "B"),
+                                    _ptr(X, torch.float64, n * k, "X"),
+                                    C.byref(rid)))
+        self.keep[rid.value] = (B, X, A)
+        return rid.value, X
+
+    def poll(self, cap=256):
+        buf = (ServerDone * cap)()
+        n = C.c_int32()
+        _check(load().server_poll(self.h, buf, cap, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            d = buf[i]
+            out.append({"req_id": d.req_id, "k": d.k,
+                        "info": d.info.as_dict(),
+                        "t_submit_ms": d.t_submit_ms,
+                        "t_admit_ms": d.t_admit_ms,
+                        "t_done_ms": d.t_done_ms})
+            self.keep.pop(d.req_id, None)
+        return out
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().server_stats(self.h, C.byref(st)))
+        return {n: getattr(st, n) for n, _ in st._fields_ if n != "pad"}
+
+    def drain(self, timeout_s=600.0):
+        import time
+        done = []
+        t0 = time.time()
+        while self.keep and time.time() - t0 < timeout_s:
+            got = self.poll()
+            done += got
+            if not got:
+                time.sleep(0.0005)
+        return done
+
+    def close(self):
+        if self.h:
+            st = load().server_destroy(self.h)
+            self.h = None
+            self.keep.clear()
+            _check(st)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

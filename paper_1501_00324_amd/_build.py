@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfespmv.so")
-SOURCES = ["api.cpp", "layout.cpp", "solver.cpp", "kernels.hip", "engine.hip"]
+SOURCES = ["api.cpp", "layout.cpp", "solver.cpp", "server.cpp", "kernels.hip",
+           "engine.hip"]
 ARCH = os.environ.get("FESPMV_ARCH", "gfx950")
 
 FLAGS = [
