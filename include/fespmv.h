@@ -93,7 +93,12 @@ typedef struct fs_csr_opts {
     int32_t dtypes;        /* extra low-precision copies (FS_DT_F32/BF16)   */
     int32_t vec;           /* slots each lane loads at once: 1 or 2; 0 =
                               auto (2 unless it adds > 6% padded slots)    */
-    int32_t reserved[7];   /* must be zero                                   */
+    int32_t autotune;      /* 1: time the product for several lanes-per-row
+                              and slots-per-load shapes on this matrix and
+                              keep the fastest (results cached per matrix
+                              signature for the process); lanes_min/max and
+                              vec are then ignored                          */
+    int32_t reserved[6];   /* must be zero                                   */
 } fs_csr_opts;
 
 /* Fill *o with the defaults (AUTO reorder, window 256, threshold 48,
@@ -138,6 +143,9 @@ typedef struct fs_csr_stats {
     double mean_band_after;   /* same, layout order                         */
     double t_build_ms;        /* wall time of csr_create                    */
     int64_t device_bytes;     /* device memory held by the handle          */
+    int32_t tuned;            /* 0 no, 1 tuned now, 2 from the tuning cache */
+    int32_t tune_candidates;  /* layouts timed                              */
+    double tune_best_us;      /* product time of the kept layout            */
 } fs_csr_stats;
 
 fs_status csr_info(fs_csr_t A, fs_csr_stats *st);

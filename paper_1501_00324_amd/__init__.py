@@ -38,7 +38,7 @@ class CsrOpts(C.Structure):
                 ("sort_window", C.c_int32), ("threshold", C.c_int32),
                 ("lanes_min", C.c_int32), ("lanes_max", C.c_int32),
                 ("dtypes", C.c_int32), ("vec", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("autotune", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class CsrStats(C.Structure):
@@ -50,7 +50,9 @@ class CsrStats(C.Structure):
                 ("groups_by_lanes", C.c_int32 * 7), ("dtypes", C.c_int32),
                 ("vec", C.c_int32), ("mean_band_before", C.c_double),
                 ("mean_band_after", C.c_double),
-                ("t_build_ms", C.c_double), ("device_bytes", C.c_int64)]
+                ("t_build_ms", C.c_double), ("device_bytes", C.c_int64),
+                ("tuned", C.c_int32), ("tune_candidates", C.c_int32),
+                ("tune_best_us", C.c_double)]
 
     def as_dict(self):
         d = {}

@@ -4,6 +4,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "internal.h"
 
@@ -121,48 +124,25 @@ fs_status cg_opts_default(fs_cg_opts *o)
     return FS_OK;
 }
 
-fs_status csr_create(int32_t n_rows, int32_t n_cols, int64_t nnz,
-                     const int32_t *rowptr, const int32_t *colind,
-                     const double *vals, const fs_csr_opts *opts,
-                     hipStream_t s, fs_csr_t *out)
+}  // extern "C"
+
+namespace fs {
+namespace {
+
+// Device handle from host structure arrays (layout built here) and device
+// values.  Synchronises s.
+fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                           const int32_t *h_rp, const int32_t *h_col,
+                           const double *vals, const fs_csr_opts &o,
+                           hipStream_t s, int dev, fs_csr **out)
 {
-    const double t0 = now_ms();
-    if (!out) return set_error(FS_E_ARG, "NULL output handle pointer");
-    *out = nullptr;
-    if (n_rows < 0 || n_cols < 0 || nnz < 0)
-        return set_error(FS_E_ARG, "negative size (%d x %d, nnz %lld)",
-                         n_rows, n_cols, (long long)nnz);
-    if (nnz >= INT32_MAX)
-        return set_error(FS_E_UNSUPPORTED, "nnz must be below 2^31");
-    if (!rowptr || (nnz > 0 && (!colind || !vals)))
-        return set_error(FS_E_ARG, "NULL CSR array");
-    fs_csr_opts o;
-    csr_opts_default(&o);
-    if (opts) o = *opts;
-    if (o.dtypes & ~(FS_DT_F64 | FS_DT_F32 | FS_DT_BF16))
-        return set_error(FS_E_ARG, "unknown dtype bits 0x%x", o.dtypes);
-
-    int dev = 0;
-    FS_HIP_TRY(hipGetDevice(&dev));
-    std::vector<int32_t> h_rp(static_cast<size_t>(n_rows) + 1);
-    std::vector<int32_t> h_col(static_cast<size_t>(nnz));
-    FS_HIP_TRY(hipMemcpyAsync(h_rp.data(), rowptr,
-                              sizeof(int32_t) * (size_t(n_rows) + 1),
-                              hipMemcpyDeviceToHost, s));
-    if (nnz > 0)
-        FS_HIP_TRY(hipMemcpyAsync(h_col.data(), colind,
-                                  sizeof(int32_t) * size_t(nnz),
-                                  hipMemcpyDeviceToHost, s));
-    FS_HIP_TRY(hipStreamSynchronize(s));
-
     fs_csr *A = new (std::nothrow) fs_csr();
     if (!A) return set_error(FS_E_OOM, "host allocation failed");
     A->n_rows = n_rows;
     A->n_cols = n_cols;
     A->nnz = nnz;
     A->device = dev;
-    fs_status st = build_layout(n_rows, n_cols, nnz, h_rp.data(),
-                                h_col.data(), o, A->host);
+    fs_status st = build_layout(n_rows, n_cols, nnz, h_rp, h_col, o, A->host);
     if (st != FS_OK) {
         delete A;
         return st;
@@ -235,6 +215,193 @@ fs_status csr_create(int32_t n_rows, int32_t n_cols, int64_t nnz,
     // info / permutation queries need on the host
     std::vector<int32_t>().swap(L.slot_col);
     std::vector<int32_t>().swap(L.map);
+    *out = A;
+    return FS_OK;
+}
+
+// Mean time of one layout-numbering product, from HIP events around
+// `reps` launches on s.
+fs_status time_product(fs_csr *A, const double *x, double *y, int reps,
+                       hipStream_t s, double &us)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    FS_HIP_TRY(hipEventCreate(&e0));
+    FS_HIP_TRY(hipEventCreate(&e1));
+    for (int i = 0; i < 3; ++i) FS_HIP_TRY(launch_spmv_f64(A, x, y, nullptr, s));
+    FS_HIP_TRY(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) FS_HIP_TRY(launch_spmv_f64(A, x, y, nullptr, s));
+    FS_HIP_TRY(hipEventRecord(e1, s));
+    FS_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    FS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    us = 1e3 * double(ms) / reps;
+    return FS_OK;
+}
+
+// Tuned layout choices, by matrix signature (sizes and a hash of the row
+// length sequence), for the life of the process.
+struct TuneKey {
+    int32_t n_rows, n_cols;
+    int64_t nnz;
+    uint64_t hash;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(n_rows, n_cols, nnz, hash) <
+               std::tie(o.n_rows, o.n_cols, o.nnz, o.hash);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int32_t, int32_t>> g_tune;  // -> (lanes, vec)
+
+uint64_t row_hash(int32_t n, const int32_t *rp)
+{
+    uint64_t h = 1469598103934665603ull;                   // FNV-1a
+    for (int32_t i = 0; i < n; ++i) {
+        h ^= uint64_t(uint32_t(rp[i + 1] - rp[i]));
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Project autotuner: time the product for a small set of row-group shapes
+// (lanes per row T and slots per load V) on the real matrix and keep the
+// fastest.  The locality permutation is computed once and reused.
+fs_status create_tuned(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                       const int32_t *h_rp, const int32_t *h_col,
+                       const double *vals, fs_csr_opts o, hipStream_t s,
+                       int dev, fs_csr **out)
+{
+    const TuneKey key{n_rows, n_cols, nnz, row_hash(n_rows, h_rp)};
+    std::pair<int32_t, int32_t> chosen{0, 0};   // {0, 0}: default shape
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            chosen = it->second;
+            cached = true;
+        }
+    }
+    // the first candidate is the default shape; it fixes the permutation
+    fs_csr *best = nullptr;
+    fs_csr_opts o0 = o;
+    if (cached && chosen.first > 0) {
+        o0.lanes_min = o0.lanes_max = chosen.first;
+        o0.vec = chosen.second;
+    }
+    FS_TRY(create_from_host(n_rows, n_cols, nnz, h_rp, h_col, vals, o0, s,
+                            dev, &best));
+    if (cached || n_rows != n_cols || n_rows == 0) {
+        best->tuned = cached ? 2 : 0;
+        *out = best;
+        return FS_OK;
+    }
+    double *x = nullptr, *y = nullptr;
+    int64_t dummy = 0;
+    fs_status st = FS_OK;
+    if ((st = dalloc(&x, n_cols, dummy)) || (st = dalloc(&y, n_rows, dummy))) {
+        dfree(x);
+        free_handle(best);
+        delete best;
+        return st;
+    }
+    (void)hipMemsetAsync(x, 0, sizeof(double) * size_t(n_cols), s);
+    double best_us = 0.0;
+    st = time_product(best, x, y, 20, s, best_us);
+    const std::vector<int32_t> perm = best->host.perm;
+    const int32_t reorder0 = best->host.reorder;
+    const int32_t cand[][2] = {{1, 2}, {1, 1}, {2, 2}, {2, 1}, {4, 2}, {8, 1}};
+    int32_t ntried = 1;
+    for (const auto &c : cand) {
+        if (st != FS_OK) break;
+        fs_csr_opts oc = o;
+        oc.reorder = FS_REORDER_USER;
+        oc.perm = perm.data();
+        oc.sort_window = 1;
+        oc.lanes_min = oc.lanes_max = c[0];
+        oc.vec = c[1];
+        fs_csr *A = nullptr;
+        st = create_from_host(n_rows, n_cols, nnz, h_rp, h_col, vals, oc, s,
+                              dev, &A);
+        if (st != FS_OK) break;
+        double us = 0.0;
+        st = time_product(A, x, y, 20, s, us);
+        ++ntried;
+        if (st == FS_OK && us < best_us) {
+            std::swap(A, best);
+            best_us = us;
+            chosen = {c[0], c[1]};
+        }
+        free_handle(A);
+        delete A;
+    }
+    dfree(x);
+    dfree(y);
+    if (st != FS_OK) {
+        free_handle(best);
+        delete best;
+        return st;
+    }
+    // candidates reuse the first build's permutation: report its origin
+    best->host.reorder = reorder0;
+    best->tuned = 1;
+    best->tune_candidates = ntried;
+    best->tune_best_us = best_us;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = chosen;
+    }
+    *out = best;
+    return FS_OK;
+}
+
+}  // namespace
+}  // namespace fs
+
+extern "C" {
+
+fs_status csr_create(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                     const int32_t *rowptr, const int32_t *colind,
+                     const double *vals, const fs_csr_opts *opts,
+                     hipStream_t s, fs_csr_t *out)
+{
+    const double t0 = now_ms();
+    if (!out) return set_error(FS_E_ARG, "NULL output handle pointer");
+    *out = nullptr;
+    if (n_rows < 0 || n_cols < 0 || nnz < 0)
+        return set_error(FS_E_ARG, "negative size (%d x %d, nnz %lld)",
+                         n_rows, n_cols, (long long)nnz);
+    if (nnz >= INT32_MAX)
+        return set_error(FS_E_UNSUPPORTED, "nnz must be below 2^31");
+    if (!rowptr || (nnz > 0 && (!colind || !vals)))
+        return set_error(FS_E_ARG, "NULL CSR array");
+    fs_csr_opts o;
+    csr_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.dtypes & ~(FS_DT_F64 | FS_DT_F32 | FS_DT_BF16))
+        return set_error(FS_E_ARG, "unknown dtype bits 0x%x", o.dtypes);
+
+    int dev = 0;
+    FS_HIP_TRY(hipGetDevice(&dev));
+    std::vector<int32_t> h_rp(static_cast<size_t>(n_rows) + 1);
+    std::vector<int32_t> h_col(static_cast<size_t>(nnz));
+    FS_HIP_TRY(hipMemcpyAsync(h_rp.data(), rowptr,
+                              sizeof(int32_t) * (size_t(n_rows) + 1),
+                              hipMemcpyDeviceToHost, s));
+    if (nnz > 0)
+        FS_HIP_TRY(hipMemcpyAsync(h_col.data(), colind,
+                                  sizeof(int32_t) * size_t(nnz),
+                                  hipMemcpyDeviceToHost, s));
+    FS_HIP_TRY(hipStreamSynchronize(s));
+    fs_csr *A = nullptr;
+    if (o.autotune)
+        FS_TRY(create_tuned(n_rows, n_cols, nnz, h_rp.data(), h_col.data(),
+                            vals, o, s, dev, &A));
+    else
+        FS_TRY(create_from_host(n_rows, n_cols, nnz, h_rp.data(),
+                                h_col.data(), vals, o, s, dev, &A));
     A->t_build_ms = now_ms() - t0;
     *out = A;
     return FS_OK;
@@ -303,6 +470,9 @@ fs_status csr_info(fs_csr_t A, fs_csr_stats *st)
     st->mean_band_before = A->host.band_before;
     st->mean_band_after = A->host.band_after;
     st->t_build_ms = A->t_build_ms;
+    st->tuned = A->tuned;
+    st->tune_candidates = A->tune_candidates;
+    st->tune_best_us = A->tune_best_us;
     st->device_bytes = A->device_bytes;
     return FS_OK;
 }

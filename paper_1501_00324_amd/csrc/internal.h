@@ -203,6 +203,8 @@ struct fs_csr {
     int32_t dtypes = FS_DT_F64;
     double t_build_ms = 0.0;
     int64_t device_bytes = 0;
+    int32_t tuned = 0, tune_candidates = 0;
+    double tune_best_us = 0.0;
     // solver state, created on the first solve and kept for reuse
     hipStream_t stream = nullptr;  // solves run here, ordered after the
     hipEvent_t ev = nullptr;       // caller's stream by an event
