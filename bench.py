@@ -13,8 +13,10 @@ on the same matrix.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -24,6 +26,44 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# Counter profile of the timed kernel (HBM bytes per launch) and the sources
+# that determine that kernel's code and data layout: the profile is used only
+# while they are unchanged.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles",
+                               "spmv_f64_elasticity64_traffic.md")
+KERNEL_SOURCES = ["paper_1501_00324_amd/csrc/kernels.hip",
+                  "paper_1501_00324_amd/csrc/device.h",
+                  "paper_1501_00324_amd/csrc/internal.h",
+                  "paper_1501_00324_amd/csrc/layout.cpp"]
+CALIB_DOUBLES = 1 << 27          # plain copy of 1 GiB for counter scaling
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed product from the committed counter
+    profile (FETCH_SIZE and WRITE_SIZE, each scaled by the counter's reading
+    for a plain copy of known size), or None when the profile is missing or
+    was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^- (\w+): (\S+)\s*$", text, re.M))
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return int(round(float(vals["traffic_bytes_per_launch"])))
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -187,6 +227,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 1 GiB copy kernel first (reference "
+                         "for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is a single-GPU "
@@ -230,6 +273,17 @@ def main():
     ok = bool(np.all(err <= 1e-12 * oracle.spmv_abs(A, x)[perm]))
     log("parity (all %d rows vs oracle): %s, max abs err %.3e"
         % (A.n_rows, ok, err.max()))
+
+    if args.calibrate_copy:
+        ca = torch.ones(CALIB_DOUBLES, dtype=torch.float64, device=dev)
+        cb = torch.empty_like(ca)
+        for _ in range(3):
+            torch.neg(ca, out=cb)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x neg of %d doubles (%d bytes read and "
+            "%d written per launch)" % (CALIB_DOUBLES, 8 * CALIB_DOUBLES,
+                                        8 * CALIB_DOUBLES))
+        del ca, cb
 
     for _ in range(args.warmup):
         fs.spmv_perm(M, xp, yp)
@@ -331,8 +385,16 @@ def main():
         oracle.spmv(A, x)
         reps += 1
         tc = time.perf_counter() - t0
-    cpu_gbs = bytes_alg * reps / tc / 1e9
-    log("cpu oracle: %d products in %.1f s, %.2f GB/s" % (reps, tc, cpu_gbs))
+    cpu = None
+    if reps:
+        cpu_gbs = bytes_alg * reps / tc / 1e9
+        log("cpu oracle: %d products in %.1f s, %.2f GB/s"
+            % (reps, tc, cpu_gbs))
+        cpu = {"value": round(cpu_gbs, 3), "unit": "GB/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "%d full FP64 CSR products of the same matrix, "
+                         "single thread" % reps}
+    traffic = measured_traffic()
 
     out = {
         "metric": "SpMV effective GB/s (% HBM peak); CG solves/s + p99 "
@@ -356,11 +418,11 @@ def main():
         "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
-        "cpu_baseline": {"value": round(cpu_gbs, 3), "unit": "GB/s",
-                         "cores": 1, "kind": "oracle",
-                         "sample": "%d full FP64 CSR products of the same "
-                                   "matrix, single thread" % reps},
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "bytes_algorithmic": bytes_alg,
+                     "kernel": "k_spmv_f64"},
+        "cpu_baseline": cpu,
         "spmv_caller_numbering_gbs": round(gbs_caller, 2),
         "paper_model_gbs": round(20 * A.nnz / (ms_kernel * 1e-3) / 1e9, 2),
         "layout": {k: info[k] for k in ("slots", "padding", "n_groups",

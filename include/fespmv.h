@@ -184,6 +184,19 @@ fs_status spmv(fs_csr_t A, const double *x, double *y, hipStream_t s);
  * numbering and never pays the final re-mapping).  Asynchronous on s. */
 fs_status spmv_perm(fs_csr_t A, const double *xp, double *yp, hipStream_t s);
 
+/* m independent products y_i = A_i x_i in the caller's numbering, the
+ * batch form of spmv (same statement of the problem; each result is bitwise
+ * the spmv result).  A, x and y are HOST arrays of m entries holding handles
+ * and DEVICE vector pointers; all handles live on one device.  The y_i are
+ * distinct and no x_i is any y_j; a handle may appear more than once.  The products of
+ * up to 64 matrices share each launch (per-matrix descriptors are passed as
+ * kernel arguments: nothing is allocated or copied to the device), so many
+ * small matrices cost one launch latency instead of m.  m = 0 is a no-op.
+ * Asynchronous on s; errors: FS_E_ARG (NULL entries, aliasing, mixed
+ * devices), FS_E_HIP. */
+fs_status spmv_batch(int32_t m, const fs_csr_t *A, const double *const *x,
+                     double *const *y, hipStream_t s);
+
 enum { FS_TO_LAYOUT = 0, FS_FROM_LAYOUT = 1 };
 /* out(i) = in(perm[i]) (FS_TO_LAYOUT) or out(perm[i]) = in(i)
  * (FS_FROM_LAYOUT); n_rows entries; in and out must not alias. */

@@ -84,7 +84,8 @@ class CgInfo(C.Structure):
 EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "csr_layout_host",
            "csr_update_values", "csr_add_dtype", "csr_info", "csr_get_perm",
-           "csr_destroy", "spmv", "spmv_perm", "csr_permute", "spmm",
+           "csr_destroy", "spmv", "spmv_batch", "spmv_perm", "csr_permute",
+           "spmm",
            "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_multi",
            "cg_solve_batch", "server_opts_default", "server_create",
            "server_submit", "server_poll", "server_stats", "server_destroy"]
@@ -121,6 +122,7 @@ def load(build_if_missing=True):
         "csr_get_perm": [vp, vp],
         "csr_destroy": [vp],
         "spmv": [vp, vp, vp, vp],
+        "spmv_batch": [i32, vp, vp, vp, vp],
         "spmv_perm": [vp, vp, vp, vp],
         "csr_permute": [vp, i32, vp, vp, vp],
         "spmm": [vp, i32, vp, i64, vp, i64, vp],
@@ -297,6 +299,22 @@ def spmv(A, x, y=None, stream=None):
                        _ptr(y, torch.float64, A.n_rows, "y"),
                        _stream(stream)))
     return y
+
+
+def spmv_batch(mats, xs, ys=None, stream=None):
+    """ys[i] = mats[i] @ xs[i] for every i, shared launches; returns ys."""
+    import torch
+    m = len(mats)
+    if ys is None:
+        ys = [torch.empty(M.n_rows, dtype=torch.float64, device=x.device)
+              for M, x in zip(mats, xs)]
+    hs = (C.c_void_p * max(1, m))(*[M._h for M in mats])
+    xp = (C.c_void_p * max(1, m))(*[_ptr(x, torch.float64, M.n_cols, "x")
+                                    for M, x in zip(mats, xs)])
+    yp = (C.c_void_p * max(1, m))(*[_ptr(y, torch.float64, M.n_rows, "y")
+                                    for M, y in zip(mats, ys)])
+    _check(load().spmv_batch(m, hs, xp, yp, _stream(stream)))
+    return ys
 
 
 def spmv_perm(A, xp, yp=None, stream=None):

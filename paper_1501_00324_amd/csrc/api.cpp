@@ -1,4 +1,5 @@
 // The C ABI: handle lifetime, products and the CG driver.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -514,6 +515,37 @@ fs_status spmv(fs_csr_t A, const double *x, double *y, hipStream_t s)
     } else {
         FS_HIP_TRY(launch_spmv_f64(A, x, y, A->d_perm, s));
     }
+    return FS_OK;
+}
+
+fs_status spmv_batch(int32_t m, const fs_csr_t *A, const double *const *x,
+                     double *const *y, hipStream_t s)
+{
+    if (m < 0) return set_error(FS_E_ARG, "negative batch size %d", m);
+    if (m == 0) return FS_OK;
+    if (!A || !x || !y) return set_error(FS_E_ARG, "NULL batch array");
+    int dev = -1;
+    for (int32_t i = 0; i < m; ++i) {
+        FS_TRY(check_handle(A[i]));
+        if ((!x[i] && A[i]->n_cols) || (!y[i] && A[i]->n_rows))
+            return set_error(FS_E_ARG, "NULL vector in batch entry %d", i);
+        if (dev >= 0 && A[i]->device != dev)
+            return set_error(FS_E_ARG, "batch members on different devices");
+        dev = A[i]->device;
+    }
+    // no x_i may alias any y_j (the products run concurrently)
+    std::vector<const void *> ys;
+    for (int32_t i = 0; i < m; ++i)
+        if (A[i]->n_rows) ys.push_back(y[i]);
+    std::sort(ys.begin(), ys.end());
+    if (std::adjacent_find(ys.begin(), ys.end()) != ys.end())
+        return set_error(FS_E_ARG, "two batch entries share one y");
+    for (int32_t i = 0; i < m; ++i)
+        if (A[i]->n_cols && std::binary_search(ys.begin(), ys.end(),
+                                               static_cast<const void *>(x[i])))
+            return set_error(FS_E_ARG, "x of batch entry %d is some y", i);
+    DeviceGuard g(dev);
+    FS_HIP_TRY(launch_spmv_batch(m, A, x, y, s));
     return FS_OK;
 }
 

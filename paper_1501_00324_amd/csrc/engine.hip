@@ -21,9 +21,12 @@
 // block per (system, column) sums them in index order.  No atomics and no
 // fences: kernel boundaries order everything, and the sums depend only on
 // the system's own grid.
-// Vectors are n x k row-major.  Sums over a row's slots follow one fixed
-// order per column (even slots, odd slots, then the lanes of the row), so a
-// column's result does not depend on how many columns share the launch.
+// Vectors are n x k row-major.  Systems share a launch only with systems of
+// the same column-count class (k rounded up to 1, 2, 4, 8, 16), and the
+// order of every sum is fixed by the class and the system's own shape, so a
+// system's results do not depend on the other members of its batch.  With
+// one column a lane gathers x for its own slots; with KM > 1 columns the
+// lanes of a wavefront gather rows of X cooperatively (coop_group).
 // The vector type ST is double for FP64 solves and float for the inner
 // solve of mixed-precision refinement; values VT are double, float or bf16;
 // every dot product is accumulated in double.
@@ -196,8 +199,117 @@ __device__ __forceinline__ void sum_partials(const double *partials, int nblk,
     }
 }
 
-// Q = A P for every column, gamma_c = p_c . q_c; the system's last block
-// sets alpha_c = rho_c / gamma_c or flags a breakdown.
+// Per-column block partials for column-split thread mappings: thread t
+// carries column t % KM.  Lanes of equal column are folded with butterflies
+// over the lane bits above log2(KM), the waves in order, and partial
+// NVPC*c + j of this block is stored at partials[(NVPC*c + j) * nblk + b].
+// With KM = 1 this is exactly store_partials.
+template <int NVPC, int KM>
+__device__ __forceinline__ void store_col_partials(double (&v)[NVPC], int k,
+                                                   double *partials, int nblk,
+                                                   int b)
+{
+    __shared__ double sh[NVPC][KM][kWavesPerBlock];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int j = 0; j < NVPC; ++j) {
+        double s = v[j];
+#pragma unroll
+        for (int o = 32; o >= KM; o >>= 1) s += __shfl_xor(s, o, kWave);
+        if (lane < KM) sh[j][lane][w] = s;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < NVPC * k) {
+        const int c = t / NVPC, j = t % NVPC;
+        double s = 0.0;
+        for (int i = 0; i < kWavesPerBlock; ++i) s += sh[j][c][i];
+        partials[long(t) * nblk + b] = s;
+    }
+}
+
+// Multi-column product of one row group with cooperative gathers (KM > 1).
+// Lane L works on column q = L % KM for the slot pairs held by lanes
+// p = r * (64/KM) + L / KM, rounds r = 0..KM-1: the matrix entry (column,
+// value) of lane p is broadcast with cross-lane shuffles and 64/KM rows of
+// X are read per instruction, each a contiguous run of KM values.  (A lane
+// gathering its own row of X would touch 64 cache lines per instruction.)
+// emit(row_in_group, q, value) is called once per (row, column < k).
+template <typename VT, typename ST, int V, int KM, class Emit>
+__device__ __forceinline__ void coop_group(const Group &g, int lane,
+                                           const VT *__restrict__ val,
+                                           const int *__restrict__ col,
+                                           const ST *__restrict__ X, int k,
+                                           long ldx, Emit emit)
+{
+    static_assert(KM > 1, "single-column products use lane_sums");
+    typedef typename Pack<VT, V>::T PV;
+    typedef typename Slots<V>::I PI;
+    constexpr int R = kWave / KM;
+    const int q = lane % KM, m = lane / KM;
+    const int width = g.width_lt & 0xffffff;
+    const long base = long(g.base64) * kWave;
+    const PV *pv = reinterpret_cast<const PV *>(val + base) + lane;
+    const PI *pc = reinterpret_cast<const PI *>(col + base) + lane;
+    ST acc[KM];
+#pragma unroll
+    for (int r = 0; r < KM; ++r) acc[r] = ST(0);
+    const int nch = width / V;
+    for (int j = 0; j < nch; ++j) {
+        int cc[V];
+        ST aa[V];
+        unpack_col<V>(__builtin_nontemporal_load(pc + j * kWave), cc);
+        unpack<VT, ST, V>(__builtin_nontemporal_load(pv + j * kWave), aa);
+#pragma unroll
+        for (int t = 0; t < V; ++t) {
+#pragma unroll
+            for (int r = 0; r < KM; ++r) {
+                const int src = r * R + m;
+                const int cs = __shfl(cc[t], src, kWave);
+                const ST as = __shfl(aa[t], src, kWave);
+                if (q < k) {
+                    const ST xv = X[long(cs < 0 ? 0 : cs) * ldx + q];
+                    acc[r] = fma(as, cs >= 0 ? xv : ST(0), acc[r]);
+                }
+            }
+        }
+    }
+    const int lt = g.width_lt >> 24, T = 1 << lt;
+    if (T <= R) {
+        // the T lanes of a row sit at consecutive m within one round
+#pragma unroll
+        for (int r = 0; r < KM; ++r)
+            for (int o = KM; o < KM * T; o <<= 1)
+                acc[r] += __shfl_xor(acc[r], o, kWave);
+#pragma unroll
+        for (int r = 0; r < KM; ++r) {
+            const int rg = (r * R + m) >> lt;
+            if ((m & (T - 1)) == 0 && rg < g.nrows && q < k) emit(rg, q, acc[r]);
+        }
+    } else {
+        // a row spans T / R whole rounds
+        const int rounds = T / R;
+#pragma unroll
+        for (int r = 0; r < KM; ++r)
+#pragma unroll
+            for (int o = KM; o < kWave; o <<= 1)
+                acc[r] += __shfl_xor(acc[r], o, kWave);
+#pragma unroll
+        for (int s = 1; s < KM; s <<= 1)
+            if (s < rounds) {
+#pragma unroll
+                for (int r = 0; r + s < KM; r += 2 * s) acc[r] += acc[r + s];
+            }
+#pragma unroll
+        for (int r = 0; r < KM; ++r) {
+            const int rg = (r * R) >> lt;
+            if (r % rounds == 0 && m == 0 && rg < g.nrows && q < k)
+                emit(rg, q, acc[r]);
+        }
+    }
+}
+
+// Q = A P for every column with per-block partials of p_c . q_c.
 template <typename VT, typename ST, int V, int KM>
 __global__ __launch_bounds__(kBlock) void k_spmm_dot(
     const SysDesc *__restrict__ sys, const int *__restrict__ smap)
@@ -212,29 +324,29 @@ __global__ __launch_bounds__(kBlock) void k_spmm_dot(
     const int g0 = int(long(lb) * S.ngroups / nb);
     const int g1 = int(long(lb + 1) * S.ngroups / nb);
     const int lane = threadIdx.x & (kWave - 1);
-    double dot[KM];
-#pragma unroll
-    for (int c = 0; c < KM; ++c) dot[c] = 0.0;
+    double dot[1] = {0.0};
     for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
         const Group gd = load_group(S.groups, __builtin_amdgcn_readfirstlane(g));
-        ST a0[KM], a1[KM];
-#pragma unroll
-        for (int c = 0; c < KM; ++c) a0[c] = a1[c] = ST(0);
-        lane_sums<VT, ST, V, KM>(gd, lane, val, S.col, P, k, k, a0, a1);
-        const int lt = gd.width_lt >> 24, r = lane >> lt;
-        const bool owner = (lane & ((1 << lt) - 1)) == 0 && r < gd.nrows;
-        const long row = gd.row0 + r;
-#pragma unroll
-        for (int c = 0; c < KM; ++c) {
-            if (KM > 1 && c >= k) continue;
-            const ST v = row_reduce(a0[c] + a1[c], lt);
-            if (owner) {
-                Q[row * k + c] = v;
-                dot[c] += double(P[row * k + c]) * double(v);
+        if constexpr (KM == 1) {
+            ST a0[1] = {ST(0)}, a1[1] = {ST(0)};
+            lane_sums<VT, ST, V, 1>(gd, lane, val, S.col, P, 1, 1, a0, a1);
+            const int lt = gd.width_lt >> 24, r = lane >> lt;
+            const ST v = row_reduce(a0[0] + a1[0], lt);
+            if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
+                const long row = gd.row0 + r;
+                Q[row] = v;
+                dot[0] += double(P[row]) * double(v);
             }
+        } else {
+            coop_group<VT, ST, V, KM>(
+                gd, lane, val, S.col, P, k, k, [&](int rg, int q, ST v) {
+                    const long e = long(gd.row0 + rg) * k + q;
+                    Q[e] = v;
+                    dot[0] += double(P[e]) * double(v);
+                });
         }
     }
-    store_partials<KM>(dot, KM == 1 ? 1 : k, S.partials, nb, lb);
+    store_col_partials<1, KM>(dot, k, S.partials, nb, lb);
 }
 
 // One block per (system, column): gamma = p.q, alpha = rho / gamma.
@@ -265,34 +377,26 @@ __global__ __launch_bounds__(kBlock) void k_update(
     const ST *P = static_cast<const ST *>(S.p);
     const ST *Q = static_cast<const ST *>(S.q);
     const ST *D = static_cast<const ST *>(S.dinv);
-    bool run[KM];
-    ST alpha[KM];
-    bool anyr = false;
-#pragma unroll
-    for (int c = 0; c < KM; ++c) {
-        run[c] = c < k && S.cs[c].status == CG_RUNNING;
-        alpha[c] = run[c] ? ST(S.cs[c].alpha) : ST(0);
-        anyr |= run[c];
-    }
-    if (!anyr) return;
-    double v[2 * KM];
-#pragma unroll
-    for (int c = 0; c < 2 * KM; ++c) v[c] = 0.0;
-    for (int i = lb * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
-        const ST di = D ? D[i] : ST(1);
-#pragma unroll
-        for (int c = 0; c < KM; ++c) {
-            if (!run[c]) continue;
-            const long e = long(i) * k + c;
-            const ST ri = R[e] - alpha[c] * Q[e];
-            X[e] += alpha[c] * P[e];
+    if (!any_running(S)) return;
+    // thread t: column c = t % KM of rows lb*RPB + t/KM, + nb*RPB, ...: a
+    // wavefront covers 64/KM consecutive rows x KM columns, contiguous
+    constexpr int RPB = kBlock / KM;
+    const int c = int(threadIdx.x) % KM;
+    const bool run = c < k && S.cs[c].status == CG_RUNNING;
+    const ST alpha = run ? ST(S.cs[c].alpha) : ST(0);
+    double v[2] = {0.0, 0.0};
+    if (run)
+        for (long i = long(lb) * RPB + threadIdx.x / KM; i < n;
+             i += long(nb) * RPB) {
+            const long e = i * k + c;
+            const ST ri = R[e] - alpha * Q[e];
+            X[e] += alpha * P[e];
             R[e] = ri;
-            const ST zi = D ? di * ri : ri;
-            v[2 * c] += double(ri) * double(zi);
-            v[2 * c + 1] += double(ri) * double(ri);
+            const ST zi = D ? D[i] * ri : ri;
+            v[0] += double(ri) * double(zi);
+            v[1] += double(ri) * double(ri);
         }
-    }
-    store_partials<2 * KM>(v, 2 * (KM == 1 ? 1 : k), S.partials, nb, lb);
+    store_col_partials<2, KM>(v, k, S.partials, nb, lb);
 }
 
 // One block per (system, column): count the iteration; stop when the
@@ -335,26 +439,17 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(
     ST *P = static_cast<ST *>(S.p);
     const ST *R = static_cast<const ST *>(S.r);
     const ST *D = static_cast<const ST *>(S.dinv);
-    bool upd[KM];
-    ST beta[KM];
-    bool anyu = false;
-#pragma unroll
-    for (int c = 0; c < KM; ++c) {
-        upd[c] = c < k && (PENDING ? S.cs[c].pending != 0
-                                   : S.cs[c].status == CG_RUNNING);
-        beta[c] = upd[c] ? ST(S.cs[c].beta) : ST(0);
-        anyu |= upd[c];
-    }
-    if (!anyu) return;
-    for (int i = lb * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
-        const ST di = D ? D[i] : ST(1);
-#pragma unroll
-        for (int c = 0; c < KM; ++c) {
-            if (!upd[c]) continue;
-            const long e = long(i) * k + c;
-            const ST zi = D ? di * R[e] : R[e];
-            P[e] = zi + beta[c] * P[e];
-        }
+    constexpr int RPB = kBlock / KM;
+    const int c = int(threadIdx.x) % KM;
+    const bool upd = c < k && (PENDING ? S.cs[c].pending != 0
+                                       : S.cs[c].status == CG_RUNNING);
+    if (!upd) return;
+    const ST beta = ST(S.cs[c].beta);
+    for (long i = long(lb) * RPB + threadIdx.x / KM; i < n;
+         i += long(nb) * RPB) {
+        const long e = i * k + c;
+        const ST zi = D ? D[i] * R[e] : R[e];
+        P[e] = zi + beta * P[e];
     }
 }
 
@@ -521,19 +616,21 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
     if (g >= ngroups) return;
     const int lane = threadIdx.x & (kWave - 1);
     const Group gd = load_group(groups, g);
-    ST a0[KM], a1[KM];
-#pragma unroll
-    for (int c = 0; c < KM; ++c) a0[c] = a1[c] = ST(0);
-    lane_sums<VT, ST, V, KM>(gd, lane, val, col, X, k, ldx, a0, a1);
-    const int lt = gd.width_lt >> 24, r = lane >> lt;
-    const bool owner = (lane & ((1 << lt) - 1)) == 0 && r < gd.nrows;
-    const int row = gd.row0 + r;
-    const long yr = SCATTER ? (owner ? long(yperm[row]) : 0) : long(row);
-#pragma unroll
-    for (int c = 0; c < KM; ++c) {
-        if (KM > 1 && c >= k) continue;
-        const ST v = row_reduce(a0[c] + a1[c], lt);
-        if (owner) Y[yr * ldy + c] = v;
+    if constexpr (KM == 1) {
+        ST a0[1] = {ST(0)}, a1[1] = {ST(0)};
+        lane_sums<VT, ST, V, 1>(gd, lane, val, col, X, 1, ldx, a0, a1);
+        const int lt = gd.width_lt >> 24, r = lane >> lt;
+        const ST v = row_reduce(a0[0] + a1[0], lt);
+        if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
+            const int row = gd.row0 + r;
+            Y[(SCATTER ? long(yperm[row]) : long(row)) * ldy] = v;
+        }
+    } else {
+        coop_group<VT, ST, V, KM>(
+            gd, lane, val, col, X, k, ldx, [&](int rg, int q, ST v) {
+                const int row = gd.row0 + rg;
+                Y[(SCATTER ? long(yperm[row]) : long(row)) * ldy + q] = v;
+            });
     }
 }
 
@@ -708,13 +805,13 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(long n,
         b[e] = float(a[e]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_add_f32(long n,
+__global__ __launch_bounds__(kBlock) void k_add_f32(long n, double alpha,
                                                     const float *__restrict__ d,
                                                     double *__restrict__ x)
 {
     for (long e = long(blockIdx.x) * kBlock + threadIdx.x; e < n;
          e += long(gridDim.x) * kBlock)
-        x[e] += double(d[e]);
+        x[e] += alpha * double(d[e]);
 }
 
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)
@@ -782,11 +879,12 @@ hipError_t to_f32(int64_t n, const double *a, float *b, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t add_f32(int64_t n, const float *d, double *x, hipStream_t s)
+hipError_t add_f32(int64_t n, double alpha, const float *d, double *x,
+                   hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_add_f32, dim3(flat_blocks(n)), dim3(kBlock), 0, s,
-                       long(n), d, x);
+                       long(n), alpha, d, x);
     return hipGetLastError();
 }
 

@@ -98,6 +98,20 @@ struct SysDesc {
     double rtol;
 };
 
+// Column-count class of a system with k right-hand sides: the launch's
+// compile-time column count (1, 2, 4, 8 or 16) and its index 0..4.  Systems
+// share a launch only with systems of the same class, so the arithmetic of
+// a system never depends on the other members of its batch.
+constexpr int kKmClasses = 5;
+inline int32_t km_for(int32_t k)
+{
+    return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+}
+inline int32_t km_index(int32_t k)
+{
+    return k <= 1 ? 0 : k <= 2 ? 1 : k <= 4 ? 2 : k <= 8 ? 3 : 4;
+}
+
 // Value / vector type classes of a launch.
 enum { VT_F64 = 0, VT_F32 = 1, VT_BF16 = 2 };
 enum { ST_F64 = 0, ST_F32 = 1 };
@@ -133,7 +147,9 @@ hipError_t permute_rows(int32_t n, int32_t k, const int32_t *perm,
                         const double *src, int64_t lds, double *dst,
                         int64_t ldd, bool to_layout, hipStream_t s);
 hipError_t to_f32(int64_t n, const double *a, float *b, hipStream_t s);
-hipError_t add_f32(int64_t n, const float *d, double *x, hipStream_t s);
+// x += alpha * d (d widened exactly)
+hipError_t add_f32(int64_t n, double alpha, const float *d, double *x,
+                   hipStream_t s);
 hipError_t cast_slots(int64_t n, const double *v, float *f32, uint16_t *bf16,
                       hipStream_t s);
 
@@ -230,6 +246,12 @@ hipError_t launch_spmv_f64(const fs_csr *A, const double *x, double *y,
 hipError_t launch_spmm_f64(const fs_csr *A, int32_t k, const double *X,
                            int64_t ldx, double *Y, int64_t ldy,
                            const int32_t *yperm, hipStream_t s);
+// m products y_i = A_i x_i in caller numbering, descriptors passed as
+// kernel arguments (kBatchPerLaunch matrices per launch).
+constexpr int kBatchPerLaunch = 64;
+hipError_t launch_spmv_batch(int32_t m, const fs_csr *const *A,
+                             const double *const *x, double *const *y,
+                             hipStream_t s);
 // Low-precision product in layout numbering: y = A_lo x (float vectors,
 // float accumulation), A_lo the FP32 or BF16 copy.
 hipError_t launch_spmv_lowp(const fs_csr *A, int32_t dtype, const float *x,

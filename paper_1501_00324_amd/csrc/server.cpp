@@ -73,8 +73,8 @@ struct fs_server {
     std::string fatal_msg;
     int64_t peak_used = 0;
     int32_t peak_active = 0;
-    fs::Batch batch[2], check;                 // running members per slot
-                                               // width; joiners
+    // running members per slot width and column-count class; joiners
+    fs::Batch batch[2 * fs::kKmClasses], check;
     uint64_t submitted = 0, completed = 0;
 };
 
@@ -172,12 +172,14 @@ fs_status step(fs_server *S)
                                       sizeof(double) * size_t(R->sys.n) * R->k,
                                       S->s));
         }
-        // start the joiners (diagonal, initial residual) per slot width
-        for (int32_t vec = 1; vec <= 2; ++vec) {
+        // start the joiners (diagonal, initial residual) per launch class
+        for (int32_t cls = 0; cls < 2 * kKmClasses; ++cls) {
+            const int32_t vec = 1 + cls / kKmClasses, kc = cls % kKmClasses;
             J.members.clear();
             J.vec = vec;
             for (Request *R : joining)
-                if (R->A->host.vec == vec) J.members.push_back(&R->sys);
+                if (R->A->host.vec == vec && km_index(R->k) == kc)
+                    J.members.push_back(&R->sys);
             if (J.members.empty()) continue;
             FS_TRY(batch_build(J, S->s));
             if (S->o.precond) FS_HIP_TRY(engine_diag_inv(J.L, S->s));
@@ -191,13 +193,15 @@ fs_status step(fs_server *S)
         }
     }
     if (S->active.empty()) return FS_OK;
-    // one batch per slot width; members iterate, then leave when done
-    for (int32_t vec = 1; vec <= 2; ++vec) {
-        Batch &B = S->batch[vec - 1];
+    // one batch per slot width and column-count class; members iterate,
+    // then leave when done
+    for (int32_t cls = 0; cls < 2 * kKmClasses; ++cls) {
+        const int32_t vec = 1 + cls / kKmClasses, kc = cls % kKmClasses;
+        Batch &B = S->batch[cls];
         std::vector<Request *> mem;
         std::vector<CgSys *> syss;
         for (Request *R : S->active)
-            if (R->A->host.vec == vec) {
+            if (R->A->host.vec == vec && km_index(R->k) == kc) {
                 mem.push_back(R);
                 syss.push_back(&R->sys);
             }
@@ -427,8 +431,7 @@ fs_status server_destroy(fs_server_t S)
     }
     for (Request *R : S->queue) delete R;
     (void)hipStreamSynchronize(S->s);
-    batch_free(S->batch[0]);
-    batch_free(S->batch[1]);
+    for (Batch &B : S->batch) batch_free(B);
     batch_free(S->check);
     (void)hipStreamDestroy(S->s);
     const fs_status f = S->fatal;

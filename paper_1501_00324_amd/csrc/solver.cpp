@@ -20,11 +20,6 @@ double now_ms()
                steady_clock::now().time_since_epoch()).count();
 }
 
-int32_t km_for(int32_t k)
-{
-    return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
-}
-
 size_t st_size(int32_t st) { return st == ST_F64 ? 8 : 4; }
 
 fs_status dmalloc(void **p, size_t bytes, int64_t &acct)
@@ -500,18 +495,35 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
     FS_TRY(batch_build(BO, s));
     const int64_t nk = int64_t(Out.n) * k;
     int32_t outer = 0, inner_total = 0;
-    bool x_zero = o.x0_zero != 0, inner_bad = false;
+    bool x_zero = o.x0_zero != 0, inner_bad = false, stalled = false;
     std::vector<ColState> last(static_cast<size_t>(k));
+    double prev_rr = 0.0;
     for (;;) {
         // FP64 residual r = b - A x and its norm against rtol |b|
         FS_HIP_TRY(engine_residual(BO.L, 0, x_zero, s));
         FS_TRY(batch_read_states(BO, s));
         x_zero = false;
         bool done = true;
+        double rr = 0.0;
         for (int32_t c = 0; c < k; ++c) {
-            last[size_t(c)] = BO.h_stage[c];
             done &= BO.h_stage[c].status == CG_CONVERGED;
+            rr += BO.h_stage[c].rr_true;
         }
+        if (outer > 0 && !done && !(rr < prev_rr)) {
+            // the last correction did not reduce the FP64 residual: the
+            // low-precision matrix is too far from A for refinement to
+            // converge (rounding error times condition number >= 1).  Undo
+            // it, re-measure, and stop.
+            FS_HIP_TRY(add_f32(nk, -1.0, static_cast<const float *>(In.x),
+                               static_cast<double *>(Out.x), s));
+            FS_HIP_TRY(engine_residual(BO.L, 0, false, s));
+            FS_TRY(batch_read_states(BO, s));
+            for (int32_t c = 0; c < k; ++c) last[size_t(c)] = BO.h_stage[c];
+            stalled = true;
+            break;
+        }
+        for (int32_t c = 0; c < k; ++c) last[size_t(c)] = BO.h_stage[c];
+        prev_rr = rr;
         if (done || outer >= o.max_outer || inner_bad ||
             inner_total >= o.maxit)
             break;
@@ -528,7 +540,7 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
         }
         inner_total += it;
         ++outer;
-        FS_HIP_TRY(add_f32(nk, static_cast<const float *>(In.x),
+        FS_HIP_TRY(add_f32(nk, 1.0, static_cast<const float *>(In.x),
                            static_cast<double *>(Out.x), s));
     }
     FS_TRY(store_block(A, k, Out.x, Xc, ldx, s));
@@ -551,6 +563,13 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
         info.bytes = (inner_total * in_bytes + (outer + 1) * out_bytes) / k;
         ret = worst(ret, info.status);
     }
+    if (stalled && ret != FS_OK)
+        set_error(ret, "mixed-precision refinement stopped after %d steps: "
+                       "the FP64 residual stopped decreasing (relative "
+                       "residual %.3e)", outer, infos[0].relres);
+    else if (ret != FS_OK)
+        set_error(ret, "mixed-precision refinement: relative residual %.3e "
+                       "after %d steps", infos[0].relres, outer);
     return ret;
 }
 
@@ -696,16 +715,18 @@ extern "C" fs_status cg_solve_batch(int32_t m, const fs_csr_t *A,
             else
                 FS_TRY(load_block(A[i], k[i], X[i], k[i], S.x, s));
         }
-        // one batch per slot vector width (the width is a template
-        // parameter of the product)
-        for (int32_t vec = 1; vec <= 2; ++vec) {
+        // one batch per slot vector width and column-count class (both
+        // are template parameters of the kernels)
+        for (int32_t cls = 0; cls < 2 * kKmClasses; ++cls) {
+            const int32_t vec = 1 + cls / kKmClasses, kc = cls % kKmClasses;
             Batch Bt;
             Bt.vt = VT_F64;
             Bt.st = ST_F64;
             Bt.vec = vec;
             std::vector<int32_t> idx;
             for (int32_t i = 0; i < m; ++i)
-                if (A[i]->n_rows > 0 && A[i]->host.vec == vec) {
+                if (A[i]->n_rows > 0 && A[i]->host.vec == vec &&
+                    km_index(k[i]) == kc) {
                     Bt.members.push_back(&sys[size_t(i)]);
                     idx.push_back(i);
                 }

@@ -137,15 +137,36 @@ def test_multi_rhs_columns_equal_single_solves(fs, orc):
     M = make(A)
     X, infos = fs.cg_solve_multi(M, dev(B), precond=1)
     Xh = host(X)
+    kap = kappa(A)
     for c in range(k):
+        # one column alone runs the single-column kernels, whose sums are
+        # ordered differently: equal up to rounding, not bitwise
         x1, i1 = fs.cg_solve(M, dev(B[:, c].copy()), precond=1)
-        assert np.array_equal(Xh[:, c], host(x1)), c
-        assert infos[c]["iters"] == i1["iters"]
+        x1 = host(x1)
+        assert np.linalg.norm(Xh[:, c] - x1) <= \
+            4e-8 * kap * max(np.linalg.norm(x1), 1e-300), c
+        assert abs(infos[c]["iters"] - i1["iters"]) <= \
+            max(2, i1["iters"] // 20)
         if c == 3:
             assert infos[c]["iters"] == 0 and not Xh[:, c].any()
         else:
             assert infos[c]["status"] == fs.FS_OK
             assert true_relres(orc, A, Xh[:, c], B[:, c]) <= 1.001e-8
+
+
+@pytest.mark.parametrize("k0,k1", [(5, 8), (3, 4), (9, 16)])
+def test_multi_rhs_columns_depend_only_on_class(fs, k0, k1):
+    """k0 and k1 share a column-count class: the first k0 columns of a
+    k1-column solve equal the k0-column solve bit for bit."""
+    A = W.tet_p1(8, "elastic", seed=(49, 0), bc="x0", permute=True)
+    B = W.random_vector(A.n_rows, 49, W.BVEC, k1, k=k1)
+    note("cg multi class k=%d,%d" % (k0, k1))
+    M = make(A)
+    X1, i1 = fs.cg_solve_multi(M, dev(B), precond=1)
+    X0, i0 = fs.cg_solve_multi(M, dev(np.ascontiguousarray(B[:, :k0])),
+                               precond=1)
+    assert np.array_equal(host(X0), host(X1)[:, :k0])
+    assert [i["iters"] for i in i0] == [i["iters"] for i in i1[:k0]]
 
 
 @pytest.mark.parametrize("k", [2, 16])

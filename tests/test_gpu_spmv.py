@@ -141,3 +141,72 @@ def test_config1_full_size(fs, orc):
     info = fs.csr_info(M)
     assert info["nnz"] == 33967818 and info["reorder"] == fs.REORDER_RCM
     assert info["padding"] < 0.15
+
+
+# ------------------------------------------------------------ batched
+def batch_matrices():
+    """Mixed members: natural and relabelled numbering, both slot widths,
+    a rectangular ragged matrix (rows permuted, columns not), a 1-row
+    matrix."""
+    return [
+        (W.poisson_2d_p1(20, seed=(51, 0), bc="all"), {}),
+        (W.tet_p1(6, "elastic", seed=(51, 1), bc="x0", permute=True), {}),
+        (ragged(300, 157, seed=51), {}),
+        (W.hex_q1(5, "laplace", seed=(51, 3), bc="all"), dict(vec=1)),
+        (W.tet_p2(3, "laplace", seed=(51, 4), permute=True),
+         dict(lanes_min=4, lanes_max=4)),
+        (CSR(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32),
+             np.array([2.5])), {}),
+    ]
+
+
+def test_spmv_batch_equals_single(fs, orc):
+    mats = batch_matrices()
+    note("spmv_batch mixed, %d members" % len(mats))
+    Ms = [make(A, **o) for A, o in mats]
+    # every handle twice, the second time with another x (a relabelled
+    # handle gathers into its own buffer: the batch must split there)
+    order = list(range(len(mats))) * 2
+    xs = [W.random_vector(mats[i][0].n_cols, 52, W.XVEC, j)
+          for j, i in enumerate(order)]
+    ys = fs.spmv_batch([Ms[i] for i in order], [dev(x) for x in xs])
+    for j, i in enumerate(order):
+        A = mats[i][0]
+        y = host(ys[j])
+        assert_spmv_close(y, orc.spmv(A, xs[j]), orc.spmv_abs(A, xs[j]),
+                          "batch member %d" % j)
+        y1 = host(fs.spmv(Ms[i], dev(xs[j])))
+        assert np.array_equal(y, y1), j
+
+
+def test_spmv_batch_many_members(fs, orc):
+    """More members than one launch holds."""
+    A = W.poisson_2d_p1(12, seed=(53, 0), bc="all", permute=True)
+    B = W.poisson_2d_p1(9, seed=(53, 1), bc="all")
+    note("spmv_batch 150 members")
+    MA, MB = make(A), make(B)
+    mats, xs = [], []
+    for j in range(150):
+        M, S = (MA, A) if j % 3 == 0 else (MB, B)
+        mats.append((M, S))
+        xs.append(W.random_vector(S.n_cols, 54, W.XVEC, j))
+    ys = fs.spmv_batch([M for M, _ in mats], [dev(x) for x in xs])
+    for j, ((M, S), x) in enumerate(zip(mats, xs)):
+        assert_spmv_close(host(ys[j]), orc.spmv(S, x), orc.spmv_abs(S, x),
+                          "member %d" % j)
+
+
+def test_spmv_batch_rejects_aliasing(fs, orc):
+    import torch
+    A = W.poisson_2d_p1(8, seed=(55, 0), bc="all")
+    note("spmv_batch argument errors")
+    M = make(A)
+    v = dev(np.ones(A.n_rows))
+    w = torch.empty_like(v)
+    with pytest.raises(fs.FsError) as e:
+        fs.spmv_batch([M, M], [v, w], [w, torch.empty_like(v)])
+    assert e.value.status == fs.FS_E_ARG
+    with pytest.raises(fs.FsError) as e:
+        fs.spmv_batch([M, M], [v, v], [w, w])
+    assert e.value.status == fs.FS_E_ARG
+    assert fs.spmv_batch([], []) == []
