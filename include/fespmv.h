@@ -254,16 +254,45 @@ typedef struct fs_cg_info {
  * entry (unless opts->x0_zero) and the solution on return.  Blocking: the
  * call synchronises stream s.  opts NULL = defaults; info may be NULL.
  * Returns FS_OK when the true residual meets rtol, FS_E_NOT_CONVERGED
- * (x = last iterate), FS_E_BREAKDOWN, or an argument/runtime error. */
+ * (x = last iterate), FS_E_BREAKDOWN, or an argument/runtime error.
+ * Mixed precision (opts->precision IR_F32 / IR_BF16): a refinement step
+ * that does not reduce the FP64 residual is undone and the solve stops,
+ * with FS_E_BREAKDOWN if the inner solve on the low-precision copy broke
+ * down (that copy need not be positive definite when rounding error times
+ * the condition number exceeds 1), else FS_E_NOT_CONVERGED. */
 fs_status cg_solve(fs_csr_t A, const double *b, double *x,
                    const fs_cg_opts *opts, fs_cg_info *info, hipStream_t s);
+
+/* Stream-ordered form of cg_solve (FP64, one right-hand side): the call
+ * only enqueues work on s and returns.  The whole solve -- Jacobi scaling,
+ * start residual, every iteration, true-residual confirmation with residual
+ * replacement -- is one cooperative launch that holds its scalars on the
+ * device (no host round trip per chunk), between the permutation of b in
+ * and of x out.  The iteration and the stopping rule are those of cg_solve;
+ * sums are ordered differently, so x and the iteration count agree with
+ * cg_solve up to rounding.  Work that follows on s sees the solution in x.
+ * info is HOST memory that receives the result (status, iters,
+ * replacements, relres, ms = device time of the solve kernel, bytes) by an
+ * asynchronous copy when s reaches the end of the solve; with pinned memory
+ * (hipHostMalloc) the call returns at once, pageable memory makes that copy
+ * synchronous.  opts->precision must be FP64 (else FS_E_UNSUPPORTED);
+ * use_graph and check_every are ignored.  Uses per-handle workspace (6 n
+ * doubles, allocated on the first call): calls on one handle must be
+ * ordered on one stream.  Returns FS_OK once enqueued, or FS_E_ARG,
+ * FS_E_NOT_SQUARE, FS_E_UNSUPPORTED (no cooperative launch), FS_E_OOM,
+ * FS_E_HIP; the solve's own status arrives in info->status. */
+fs_status cg_solve_async(fs_csr_t A, const double *b, double *x,
+                         const fs_cg_opts *opts, fs_cg_info *info,
+                         hipStream_t s);
 
 /* k independent solves A X[:, c] = B[:, c], 1 <= k <= 16, advanced
  * together: one multi-column product per iteration (the k columns of a row
  * of X are contiguous, so one gathered row serves all k).  B and X are
- * n x k row-major device blocks with row strides ldb, ldx >= k.  Each
- * column's iterates are exactly those of a cg_solve of that column alone
- * (columns stop independently).  info (may be NULL) receives k entries.
+ * n x k row-major device blocks with row strides ldb, ldx >= k.  Columns
+ * stop independently.  The order of every sum is fixed by the column-count
+ * class (k rounded up to 1, 2, 4, 8 or 16): a column's iterates are bitwise
+ * the same for any k of one class, and equal those of a cg_solve of the
+ * column alone up to rounding.  info (may be NULL) receives k entries.
  * Blocking; returns the worst column status. */
 fs_status cg_solve_multi(fs_csr_t A, int32_t k, const double *B, int64_t ldb,
                          double *X, int64_t ldx, const fs_cg_opts *opts,
@@ -275,7 +304,8 @@ fs_status cg_solve_multi(fs_csr_t A, int32_t k, const double *B, int64_t ldb,
  * for all systems together, so many small systems cost what one does.
  * B[i] and X[i] are n_i x k[i] row-major device blocks (row stride k[i]).
  * Each system's iterates, reductions included, are bitwise those of solving
- * it alone.  FP64 only (FS_E_UNSUPPORTED otherwise).  info (may be NULL)
+ * it alone with cg_solve_multi (systems are launched with others of the
+ * same slot width and column-count class only).  FP64 only (FS_E_UNSUPPORTED otherwise).  info (may be NULL)
  * receives sum(k) entries, systems in order.  Blocking; returns the worst
  * status over all right-hand sides. */
 fs_status cg_solve_batch(int32_t m, const fs_csr_t *A, const int32_t *k,

@@ -86,7 +86,8 @@ EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "csr_update_values", "csr_add_dtype", "csr_info", "csr_get_perm",
            "csr_destroy", "spmv", "spmv_batch", "spmv_perm", "csr_permute",
            "spmm",
-           "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_multi",
+           "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_async",
+           "cg_solve_multi",
            "cg_solve_batch", "server_opts_default", "server_create",
            "server_submit", "server_poll", "server_stats", "server_destroy"]
 
@@ -129,6 +130,7 @@ def load(build_if_missing=True):
         "spmv_lowp": [vp, i32, vp, vp, vp],
         "cg_opts_default": [P(CgOpts)],
         "cg_solve": [vp, vp, vp, P(CgOpts), P(CgInfo), vp],
+        "cg_solve_async": [vp, vp, vp, P(CgOpts), vp, vp],
         "cg_solve_multi": [vp, i32, vp, i64, vp, i64, P(CgOpts), P(CgInfo),
                            vp],
         "cg_solve_batch": [i32, vp, vp, vp, vp, P(CgOpts), P(CgInfo), vp],
@@ -389,6 +391,44 @@ def cg_solve(A, b, x=None, stream=None, check=True, **opts):
                                             FS_E_BREAKDOWN)):
         raise FsError(st, d["message"])
     return x, d
+
+
+class AsyncSolve:
+    """Result of cg_solve_async: x (filled when the stream gets there) and
+    the info record in pinned host memory."""
+
+    def __init__(self, x, buf, stream):
+        self.x, self._buf, self._stream = x, buf, stream
+
+    def info(self):
+        """Wait for the stream, return the info dict."""
+        import torch
+        if self._stream is None:
+            torch.cuda.current_stream().synchronize()
+        elif isinstance(self._stream, int):
+            torch.cuda.synchronize()
+        else:
+            self._stream.synchronize()
+        d = CgInfo.from_address(self._buf.data_ptr()).as_dict()
+        d["message"] = ""
+        return d
+
+
+def cg_solve_async(A, b, x=None, stream=None, **opts):
+    """Enqueue the FP64 solve A x = b on the stream and return at once (an
+    AsyncSolve; .x is the solution once the stream reaches it, .info()
+    waits and returns the info dict)."""
+    import torch
+    if x is None:
+        x = torch.zeros(A.n_rows, dtype=torch.float64, device=b.device)
+        opts.setdefault("x0_zero", 1)
+    o = cg_opts(**opts)
+    buf = torch.zeros(C.sizeof(CgInfo), dtype=torch.uint8, pin_memory=True)
+    _check(load().cg_solve_async(A._h, _ptr(b, torch.float64, A.n_rows, "b"),
+                                 _ptr(x, torch.float64, A.n_rows, "x"),
+                                 C.byref(o), C.c_void_p(buf.data_ptr()),
+                                 _stream(stream)))
+    return AsyncSolve(x, buf, stream)
 
 
 def cg_solve_multi(A, B, X=None, stream=None, check=True, **opts):

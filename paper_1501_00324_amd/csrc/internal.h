@@ -227,6 +227,10 @@ struct fs_csr {
     fs::CgSys *sys_f64 = nullptr;  // one right-hand side, FP64
     fs::CgSys *sys_lo = nullptr;   // inner system of mixed precision
     fs::Batch *batch_f64 = nullptr, *batch_lo = nullptr;
+    // stream-ordered solves (cg_solve_async): b, x, r, p, q, dinv in layout
+    // numbering, block partials, the device result
+    double *d_async = nullptr, *d_apart = nullptr;
+    fs_cg_info *d_ainfo = nullptr;
 };
 
 namespace fs {
@@ -252,6 +256,16 @@ constexpr int kBatchPerLaunch = 64;
 hipError_t launch_spmv_batch(int32_t m, const fs_csr *const *A,
                              const double *const *x, double *const *y,
                              hipStream_t s);
+// Whole-solve persistent CG (one cooperative launch, one right-hand side,
+// FP64, layout numbering): grid size for the handle, and the launch.  info
+// is a device struct written at the end.
+constexpr int kPersistMaxBlocks = 1024;
+int32_t persistent_blocks(const fs_csr *A);
+hipError_t launch_cg_persistent(const fs_csr *A, int32_t nblocks,
+                                const double *b, double *x, double *r,
+                                double *p, double *q, double *dinv,
+                                double *part, fs_cg_info *info, double rtol,
+                                int32_t maxit, bool x_zero, hipStream_t s);
 // Low-precision product in layout numbering: y = A_lo x (float vectors,
 // float accumulation), A_lo the FP32 or BF16 copy.
 hipError_t launch_spmv_lowp(const fs_csr *A, int32_t dtype, const float *x,

@@ -1,0 +1,353 @@
+// Whole-solve persistent CG: one cooperative launch runs the Jacobi-PCG
+// iteration of one system (the solver the paper runs around its SpMV) to
+// the end, so the solve is ordered on the caller's stream like any kernel
+// and needs no host round trip per chunk of iterations.
+//
+// Every block owns a contiguous range of row groups (products) and of rows
+// (vector steps).  Grid-wide barriers separate the phases; after each
+// barrier every block sums the per-block partials itself, in one fixed
+// order, so all blocks hold bitwise the same scalars (alpha, beta, the
+// residual norms) and take the same branch at every decision: the number
+// of barriers is the same in every block.  Per iteration:
+//   q = A p, partials of p.q        | barrier | gamma, alpha
+//   x += alpha p, r -= alpha q,     |
+//   z = D^-1 r, partials r.z, r.r   | barrier | rz, rr, beta
+//   p = z + beta p                  | barrier
+// When |r| meets the tolerance, b - A x is recomputed (one more product);
+// if it misses, it replaces r and the iteration continues.
+#include <algorithm>
+
+#include <hip/hip_cooperative_groups.h>
+
+#include "device.h"
+
+namespace fs {
+namespace {
+
+namespace cgr = cooperative_groups;
+
+struct PcgArgs {
+    const Group *groups;
+    const double *val;
+    const int32_t *col;
+    int32_t n, ngroups;
+    const double *b;               // layout numbering
+    double *x, *r, *p, *q, *dinv;  // dinv NULL: no preconditioner
+    double *part;                  // 3 * gridDim.x partials
+    fs_cg_info *info;              // device copy of the result
+    double rtol, nnz, clock_khz;
+    int32_t maxit, x_zero;
+};
+
+// Block partial sums of NJ values -> part[j * nb + b].
+template <int NJ>
+__device__ __forceinline__ void put_partials(const double (&v)[NJ],
+                                             double *part, int nb, int b)
+{
+    __shared__ double sh[3][kWavesPerBlock];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const double s = wave_sum(v[j]);
+        if (lane == 0) sh[j][w] = s;
+    }
+    __syncthreads();
+    if (int(threadIdx.x) < NJ) {
+        double t = 0.0;
+        for (int i = 0; i < kWavesPerBlock; ++i) t += sh[threadIdx.x][i];
+        part[long(threadIdx.x) * nb + b] = t;
+    }
+    __syncthreads();
+}
+
+// After a grid barrier: the NJ grid-wide sums, identical in every block.
+// The partials are read with device-scope loads (never a stale line of
+// this CU's vector cache), so every block sees the same values and takes
+// the same branches -- the barrier count cannot diverge between blocks.
+template <int NJ>
+__device__ __forceinline__ void get_sums(double *part, int nb,
+                                         double (&out)[NJ])
+{
+    __shared__ double res[3];
+    if (threadIdx.x < kWave) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            double s = 0.0;
+            for (int i = threadIdx.x; i < nb; i += kWave)
+                s += __hip_atomic_load(part + j * nb + i, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            s = wave_sum(s);
+            if (threadIdx.x == 0) res[j] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) out[j] = res[j];
+    __syncthreads();
+}
+
+// b - A x for the rows of this block's groups (A x skipped when XZ); calls
+// f(row, r_row) on the owner lane of every row.
+template <int V, bool XZ, class F>
+__device__ __forceinline__ void residual_rows(const PcgArgs &a, int g0, int g1,
+                                              F f)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
+        const Group gd = load_group(a.groups, __builtin_amdgcn_readfirstlane(g));
+        const int lt = gd.width_lt >> 24;
+        double ax = 0.0;
+        if (!XZ)
+            ax = row_reduce(group_lane_sum<V>(gd, lane, a.val, a.col, a.x), lt);
+        const int r = lane >> lt;
+        if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
+            const int row = gd.row0 + r;
+            f(row, a.b[row] - ax);
+        }
+    }
+}
+
+enum { P_RUNNING = 0, P_CONVERGED = 1, P_BREAKDOWN = 2, P_MAXIT = 3 };
+
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_cg_persistent(const PcgArgs a)
+{
+    cgr::grid_group grid = cgr::this_grid();
+    const long t_start = wall_clock64();
+    const int nb = int(gridDim.x);
+    const int lb = xcd_remap(int(blockIdx.x), nb);
+    const int g0 = int(long(lb) * a.ngroups / nb);
+    const int g1 = int(long(lb + 1) * a.ngroups / nb);
+    const int r0 = int(long(lb) * a.n / nb), r1 = int(long(lb + 1) * a.n / nb);
+    const int lane = threadIdx.x & (kWave - 1);
+    double *D = a.dinv;
+
+    // Jacobi scaling for this block's groups (the same rows the start pass
+    // below writes, so no barrier is needed in between)
+    if (D) {
+        for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
+            const Group gd =
+                load_group(a.groups, __builtin_amdgcn_readfirstlane(g));
+            const int lt = gd.width_lt >> 24, width = gd.width_lt & 0xffffff;
+            const int r = lane >> lt, row = gd.row0 + r;
+            const long base = long(gd.base64) * kWave;
+            double d = 0.0;
+            for (int s = 0; s < width; ++s) {
+                const long idx = base + long(s / V) * kWave * V + lane * V + s % V;
+                if (a.col[idx] == row) d += a.val[idx];
+            }
+            d = row_reduce(d, lt);
+            if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows)
+                D[row] = 1.0 / d;
+        }
+    }
+    // start: r = b - A x, p = z = D^-1 r; |r|^2, r.z, |b|^2
+    double v3[3] = {0.0, 0.0, 0.0};
+    auto start = [&](int row, double ri) {
+        const double zi = D ? D[row] * ri : ri;
+        const double bi = a.b[row];
+        a.r[row] = ri;
+        a.p[row] = zi;
+        v3[0] += ri * ri;
+        v3[1] += ri * zi;
+        v3[2] += bi * bi;
+    };
+    if (a.x_zero) residual_rows<V, true>(a, g0, g1, start);
+    else residual_rows<V, false>(a, g0, g1, start);
+    put_partials<3>(v3, a.part, nb, lb);
+    grid.sync();
+    double s3[3];
+    get_sums<3>(a.part, nb, s3);
+    const double bb = s3[2], tol2 = a.rtol * a.rtol * bb;
+    double rho = s3[1], rr = s3[0], rr_true = s3[0];
+    int status = P_RUNNING, it = 0, repl = 0;
+    if (bb == 0.0) {
+        // b = 0: x = 0 is the solution
+        for (int i = r0 + int(threadIdx.x); i < r1; i += kBlock) a.x[i] = 0.0;
+        status = P_CONVERGED;
+        rr_true = 0.0;
+    } else if (rr <= tol2) {
+        status = P_CONVERGED;
+    } else if (!isfinite(rr) || !isfinite(rho)) {
+        status = P_BREAKDOWN;
+    }
+    while (status == P_RUNNING) {
+        // q = A p, p.q
+        double v1[1] = {0.0};
+        for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
+            const Group gd =
+                load_group(a.groups, __builtin_amdgcn_readfirstlane(g));
+            const int lt = gd.width_lt >> 24;
+            const double qv =
+                row_reduce(group_lane_sum<V>(gd, lane, a.val, a.col, a.p), lt);
+            const int r = lane >> lt;
+            if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
+                const int row = gd.row0 + r;
+                a.q[row] = qv;
+                v1[0] += a.p[row] * qv;
+            }
+        }
+        put_partials<1>(v1, a.part, nb, lb);
+        grid.sync();
+        double s1[1];
+        get_sums<1>(a.part, nb, s1);
+        const double gamma = s1[0];
+        if (!(gamma > 0.0) || !isfinite(gamma)) {
+            status = P_BREAKDOWN;
+            break;
+        }
+        const double alpha = rho / gamma;
+        // x, r update; z = D^-1 r; r.z, r.r
+        double v2[2] = {0.0, 0.0};
+        for (int i = r0 + int(threadIdx.x); i < r1; i += kBlock) {
+            const double ri = a.r[i] - alpha * a.q[i];
+            a.x[i] += alpha * a.p[i];
+            a.r[i] = ri;
+            const double zi = D ? D[i] * ri : ri;
+            v2[0] += ri * zi;
+            v2[1] += ri * ri;
+        }
+        put_partials<2>(v2, a.part, nb, lb);
+        grid.sync();
+        double s2[2];
+        get_sums<2>(a.part, nb, s2);
+        ++it;
+        double rz = s2[0];
+        rr = s2[1];
+        if (rr <= tol2) {
+            // confirm against the true residual; replace r if it misses
+            double w2[2] = {0.0, 0.0};
+            residual_rows<V, false>(a, g0, g1, [&](int row, double ri) {
+                a.r[row] = ri;
+                const double zi = D ? D[row] * ri : ri;
+                w2[0] += ri * zi;
+                w2[1] += ri * ri;
+            });
+            put_partials<2>(w2, a.part, nb, lb);
+            grid.sync();
+            get_sums<2>(a.part, nb, s2);
+            rr_true = s2[1];
+            if (rr_true <= tol2) {
+                status = P_CONVERGED;
+                break;
+            }
+            ++repl;
+            rz = s2[0];
+            rr = rr_true;
+        } else if (!isfinite(rr)) {
+            status = P_BREAKDOWN;
+            break;
+        }
+        const double beta = rz / rho;
+        if (!isfinite(beta)) {
+            status = P_BREAKDOWN;
+            break;
+        }
+        rho = rz;
+        if (it >= a.maxit) {
+            status = P_MAXIT;
+            break;
+        }
+        // p = z + beta p (rows of this block; r of these rows was written
+        // by this block, or before the last barrier)
+        for (int i = r0 + int(threadIdx.x); i < r1; i += kBlock) {
+            const double zi = D ? D[i] * a.r[i] : a.r[i];
+            a.p[i] = zi + beta * a.p[i];
+        }
+        grid.sync();
+    }
+    if (status != P_CONVERGED) {
+        // report the true residual of the returned x
+        grid.sync();
+        double w1[1] = {0.0};
+        residual_rows<V, false>(a, g0, g1,
+                                [&](int, double ri) { w1[0] += ri * ri; });
+        put_partials<1>(w1, a.part, nb, lb);
+        grid.sync();
+        double s1[1];
+        get_sums<1>(a.part, nb, s1);
+        rr_true = s1[0];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        fs_cg_info o;
+        o.status = status == P_CONVERGED ? FS_OK
+                   : status == P_MAXIT   ? FS_E_NOT_CONVERGED
+                                         : FS_E_BREAKDOWN;
+        o.iters = it;
+        o.outer = 0;
+        o.replacements = repl;
+        o.relres = bb > 0.0 ? sqrt(rr_true / bb) : 0.0;
+        o.ms = double(wall_clock64() - t_start) / a.clock_khz;
+        o.bytes = double(it) * (12.0 * a.nnz + (D ? 104.0 : 88.0) * a.n) +
+                  2.0 * (12.0 * a.nnz + 16.0 * a.n);
+        *a.info = o;
+    }
+}
+
+template <int V> int max_coresident(int device)
+{
+    static int cached[64];
+    if (device < 0 || device >= 64) return 0;
+    if (cached[device] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, k_cg_persistent<V>, kBlock, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                  device) != hipSuccess)
+            return 0;
+        cached[device] = per_cu * cus;
+    }
+    return cached[device];
+}
+
+}  // namespace
+
+int32_t persistent_blocks(const fs_csr *A)
+{
+    const int want = std::max((A->n_groups + kWavesPerBlock - 1) / kWavesPerBlock,
+                              (A->n_rows + kBlock - 1) / kBlock);
+    const int cap = A->host.vec == 1 ? max_coresident<1>(A->device)
+                                     : max_coresident<2>(A->device);
+    return std::max(1, std::min({want, cap, kPersistMaxBlocks}));
+}
+
+hipError_t launch_cg_persistent(const fs_csr *A, int32_t nblocks,
+                                const double *b, double *x, double *r,
+                                double *p, double *q, double *dinv,
+                                double *part, fs_cg_info *info, double rtol,
+                                int32_t maxit, bool x_zero, hipStream_t s)
+{
+    int khz = 0;
+    hipError_t e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate,
+                                         A->device);
+    if (e != hipSuccess) return e;
+    PcgArgs a;
+    a.groups = A->d_groups;
+    a.val = A->d_val;
+    a.col = A->d_col;
+    a.n = A->n_rows;
+    a.ngroups = A->n_groups;
+    a.b = b;
+    a.x = x;
+    a.r = r;
+    a.p = p;
+    a.q = q;
+    a.dinv = dinv;
+    a.part = part;
+    a.info = info;
+    a.rtol = rtol;
+    a.nnz = double(A->nnz);
+    a.clock_khz = double(khz > 0 ? khz : 100000);
+    a.maxit = maxit;
+    a.x_zero = x_zero ? 1 : 0;
+    void *args[] = {&a};
+    if (A->host.vec == 1)
+        return hipLaunchCooperativeKernel(
+            reinterpret_cast<const void *>(k_cg_persistent<1>), dim3(nblocks),
+            dim3(kBlock), args, 0, s);
+    return hipLaunchCooperativeKernel(
+        reinterpret_cast<const void *>(k_cg_persistent<2>), dim3(nblocks),
+        dim3(kBlock), args, 0, s);
+}
+
+}  // namespace fs

@@ -495,6 +495,9 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
     FS_TRY(batch_build(BO, s));
     const int64_t nk = int64_t(Out.n) * k;
     int32_t outer = 0, inner_total = 0;
+    // inner_bad: the last inner solve broke down (the low-precision copy
+    // need not be positive definite when A is ill-conditioned); its partial
+    // correction is still applied, and the residual test below decides
     bool x_zero = o.x0_zero != 0, inner_bad = false, stalled = false;
     std::vector<ColState> last(static_cast<size_t>(k));
     double prev_rr = 0.0;
@@ -524,9 +527,7 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
         }
         for (int32_t c = 0; c < k; ++c) last[size_t(c)] = BO.h_stage[c];
         prev_rr = rr;
-        if (done || outer >= o.max_outer || inner_bad ||
-            inner_total >= o.maxit)
-            break;
+        if (done || outer >= o.max_outer || inner_total >= o.maxit) break;
         // inner solve A_lo d = r in single precision from d = 0
         FS_HIP_TRY(to_f32(nk, static_cast<const double *>(Out.r),
                           static_cast<float *>(In.b), s));
@@ -534,6 +535,7 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
         In.maxit = std::max(1, o.maxit - inner_total);
         FS_TRY(run_batch(BI, o.check_every, o.use_graph != 0, true, s));
         int32_t it = 0;
+        inner_bad = false;
         for (int32_t c = 0; c < k; ++c) {
             it = std::max(it, BI.h_stage[c].iter);
             if (BI.h_stage[c].status == CG_BREAKDOWN) inner_bad = true;
@@ -553,9 +555,9 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
     for (int32_t c = 0; c < k; ++c) {
         const ColState &cs = last[size_t(c)];
         fs_cg_info &info = infos[c];
-        info.status = cs.status == CG_CONVERGED
-                          ? FS_OK
-                          : inner_bad ? FS_E_BREAKDOWN : FS_E_NOT_CONVERGED;
+        info.status = cs.status == CG_CONVERGED ? FS_OK
+                      : stalled && inner_bad    ? FS_E_BREAKDOWN
+                                                : FS_E_NOT_CONVERGED;
         info.iters = inner_total;
         info.outer = outer;
         info.replacements = 0;
@@ -566,7 +568,10 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
     if (stalled && ret != FS_OK)
         set_error(ret, "mixed-precision refinement stopped after %d steps: "
                        "the FP64 residual stopped decreasing (relative "
-                       "residual %.3e)", outer, infos[0].relres);
+                       "residual %.3e)%s", outer, infos[0].relres,
+                  inner_bad ? "; the inner solve on the low-precision copy "
+                              "broke down (that copy is not positive "
+                              "definite)" : "");
     else if (ret != FS_OK)
         set_error(ret, "mixed-precision refinement: relative residual %.3e "
                        "after %d steps", infos[0].relres, outer);
@@ -622,6 +627,9 @@ void free_solver_state(fs_csr *A)
             *B = nullptr;
         }
     }
+    dfree(A->d_async);
+    dfree(A->d_apart);
+    dfree(A->d_ainfo);
     if (A->ev) (void)hipEventDestroy(A->ev);
     A->ev = nullptr;
     if (A->stream) (void)hipStreamDestroy(A->stream);
@@ -644,6 +652,57 @@ extern "C" fs_status cg_solve(fs_csr_t A, const double *b, double *x,
     local.ms = now_ms() - t0;
     if (info) *info = local;
     return st;
+}
+
+extern "C" fs_status cg_solve_async(fs_csr_t A, const double *b, double *x,
+                                    const fs_cg_opts *opts, fs_cg_info *info,
+                                    hipStream_t s)
+{
+    fs_cg_opts o;
+    FS_TRY(normalise_opts(opts, o));
+    FS_TRY(check_solve_args(A, 1, b, x, 1, 1));
+    if (!info) return set_error(FS_E_ARG, "info is required");
+    if (o.precision != FS_PREC_F64)
+        return set_error(FS_E_UNSUPPORTED,
+                         "the stream-ordered solve runs in FP64");
+    if (A->n_rows == 0) {
+        std::memset(info, 0, sizeof(fs_cg_info));
+        return FS_OK;
+    }
+    DeviceGuard g(A->device);
+    int coop = 0;
+    FS_HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch,
+                                     A->device));
+    if (!coop)
+        return set_error(FS_E_UNSUPPORTED,
+                         "device without cooperative launches");
+    const int64_t n = A->n_rows;
+    if (!A->d_async) {
+        // first use: workspace of the handle (allocation synchronises)
+        int64_t acct = 0;
+        FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_async),
+                       sizeof(double) * size_t(6 * n), acct));
+        FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_apart),
+                       sizeof(double) * 3 * kPersistMaxBlocks, acct));
+        FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_ainfo),
+                       sizeof(fs_cg_info), acct));
+        A->device_bytes += acct;
+    }
+    double *B = A->d_async, *X = B + n, *R = X + n, *P = R + n, *Q = P + n,
+           *Dv = Q + n;
+    FS_TRY(load_block(A, 1, b, 1, B, s));
+    if (o.x0_zero)
+        FS_HIP_TRY(hipMemsetAsync(X, 0, sizeof(double) * size_t(n), s));
+    else
+        FS_TRY(load_block(A, 1, x, 1, X, s));
+    FS_HIP_TRY(launch_cg_persistent(A, persistent_blocks(A), B, X, R, P, Q,
+                                    o.precond ? Dv : nullptr, A->d_apart,
+                                    A->d_ainfo, o.rtol, o.maxit,
+                                    o.x0_zero != 0, s));
+    FS_TRY(store_block(A, 1, X, x, 1, s));
+    FS_HIP_TRY(hipMemcpyAsync(info, A->d_ainfo, sizeof(fs_cg_info),
+                              hipMemcpyDeviceToHost, s));
+    return FS_OK;
 }
 
 extern "C" fs_status cg_solve_multi(fs_csr_t A, int32_t k, const double *B,

@@ -1,7 +1,7 @@
 """Mixed-precision refinement where it cannot converge: the BF16 copy of an
 ill-conditioned matrix (rounding error times condition number far above 1).
-The solve must stop by itself, report FS_E_NOT_CONVERGED, and return an x
-no worse than the one before the last correction."""
+The solve must stop by itself with a failure status and a message, and
+return an x no worse than the one before the last correction."""
 import numpy as np
 import pytest
 
@@ -50,13 +50,15 @@ def test_bf16_refinement_stops_when_it_stalls(fs, orc):
     M = make(A)
     x, info = fs.cg_solve(M, dev(b), precond=1, precision=fs.PREC_IR_BF16,
                           inner_rtol=1e-2, check=False)
-    assert info["status"] == fs.FS_E_NOT_CONVERGED
+    # the BF16 copy of so ill-conditioned a matrix need not even be positive
+    # definite: the inner solve may break down (FS_E_BREAKDOWN) or only stall
+    assert info["status"] in (fs.FS_E_NOT_CONVERGED, fs.FS_E_BREAKDOWN)
     assert info["outer"] < 50
     xg = host(x)
     rel = np.linalg.norm(b - orc.spmv(A, xg)) / np.linalg.norm(b)
     assert abs(rel - info["relres"]) <= 1e-6 * max(rel, 1e-300)
     assert rel <= 1.0 + 1e-12            # the failed correction was undone
-    assert "stopped" in info["message"] or "after" in info["message"]
+    assert "stopped" in info["message"]
     # the same system in FP64 converges
     x64, i64 = fs.cg_solve(M, dev(b), precond=1)
     assert i64["status"] == fs.FS_OK

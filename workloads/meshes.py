@@ -197,36 +197,36 @@ def _physical_gradients(dN, X):
 
 
 def _laplace_kernel(G, wdet):
-    # K_ab = sum_q w|det| grad N_a . grad N_b
+    # K_ab = sum_q w|det| grad N_a . grad N_b, one batched product per
+    # coordinate direction
     ne, nq, nloc, d = G.shape
     out = np.zeros((ne, nloc, nloc))
-    for q in range(nq):
-        for i in range(d):
-            gq = G[:, q, :, i]
-            out += (gq * wdet[:, q, None])[:, :, None] * gq[:, None, :]
-    return out
-
-
-def _outer_sum(wg, g):
-    """sum over q of the outer products wg[e, q, :] x g[e, q, :]."""
-    out = wg[:, 0, :, None] * g[:, 0, None, :]
-    for q in range(1, wg.shape[1]):
-        out += wg[:, q, :, None] * g[:, q, None, :]
+    for i in range(d):
+        gi = np.ascontiguousarray(G[:, :, :, i])              # (ne, nq, nloc)
+        wgt = np.ascontiguousarray((gi * wdet[:, :, None]).transpose(0, 2, 1))
+        out += np.matmul(wgt, gi)
     return out
 
 
 def _elastic_kernel(lam, mu):
     def k(G, wdet):
+        # M[i][j][e, a, b] = sum_q w dN_a/dx_i dN_b/dx_j; the element matrix
+        # K[a,i,b,j] = lam M[i][j] + mu M[j][i] + mu d_ij sum_k M[k][k]
         ne, nq, nloc, d = G.shape
-        g = G.reshape(ne, nq, nloc * d)
-        wg = g * wdet[:, :, None]
-        # T[e, (a,i), (b,j)] = sum_q w G_a,i G_b,j
-        T = _outer_sum(wg, g).reshape(ne, nloc, d, nloc, d)
-        # K[a,i,b,j] = lam T[a,i,b,j] + mu T[a,j,b,i] + mu d_ij sum_k T[a,k,b,k]
-        K = lam * T + mu * T.transpose(0, 1, 4, 3, 2)
-        tr = np.einsum("eakbk->eab", T)
+        gd = [np.ascontiguousarray(G[:, :, :, i]) for i in range(d)]
+        wgt = [np.ascontiguousarray((g * wdet[:, :, None]).transpose(0, 2, 1))
+               for g in gd]
+        M = [[np.matmul(wgt[i], gd[j]) for j in range(d)] for i in range(d)]
+        tr = M[0][0].copy()
+        for i in range(1, d):
+            tr += M[i][i]
+        K = np.empty((ne, nloc, d, nloc, d))
         for i in range(d):
-            K[:, :, i, :, i] += mu * tr
+            for j in range(d):
+                blk = lam * M[i][j] + mu * M[j][i]
+                if i == j:
+                    blk += mu * tr
+                K[:, :, i, :, j] = blk
         return K.reshape(ne, nloc * d, nloc * d)
     return k
 
@@ -241,7 +241,7 @@ def lame(E=1.0, nu=0.3):
 # stencil assembly over a grid of cells
 # --------------------------------------------------------------------------
 def _assemble_stencil(shape, X, etypes, cell_shape, stride, dN, w, kernel,
-                      dof, chunk=65536, check_orientation=True):
+                      dof, chunk=16384, check_orientation=True):
     """Assemble element matrices of every cell into per-node stencils.
 
     Returns S (N, nD, dof, dof), cov (N, nD) and the offset list D (nD, d).
