@@ -34,7 +34,7 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles",
                                "spmv_f64_elasticity64_traffic.md")
 KERNEL_SOURCES = ["paper_1501_00324_amd/csrc/kernels.hip",
                   "paper_1501_00324_amd/csrc/device.h",
-                  "paper_1501_00324_amd/csrc/internal.h",
+                  "paper_1501_00324_amd/csrc/layout.h",
                   "paper_1501_00324_amd/csrc/layout.cpp"]
 CALIB_DOUBLES = 1 << 27          # plain copy of 1 GiB for counter scaling
 
@@ -219,6 +219,180 @@ def bench_serving(fs, W, oracle, d, torch, n_req=32, lam_factors=(1, 2, 4)):
     return out
 
 
+
+def event_times_us(torch, fn, reps, stream, flush=None):
+    """Per-call device times (HIP events on the launch stream) of reps calls
+    of fn; flush() runs before each call (cold caches) outside the pair."""
+    out = []
+    for _ in range(reps):
+        if flush is not None:
+            flush()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1) * 1e3)
+    return out
+
+
+def dist(v):
+    return {"median": percentile(v, 50), "p10": percentile(v, 10),
+            "p90": percentile(v, 90), "n": len(v)}
+
+
+def back_to_back_us(torch, fn, steps, warmup, stream):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / steps
+
+
+def measure_matrix(fs, oracle, torch, A, d, steps, warmup, stream,
+                   cold=True):
+    """Layout build, parity of the timed launch against the oracle on every
+    row, warm (back to back, and per call) and cold product times, and the
+    plain CSR product without a layout."""
+    dev = torch.device("cuda:0")
+    rp, ci, va = d(A.rowptr), d(A.col), d(A.val)
+    M = fs.csr_create(rp, ci, va, A.n_rows, A.n_cols)
+    info = fs.csr_info(M)
+    import workloads as W
+    x = W.random_vector(A.n_cols, 1, W.XVEC)
+    perm = fs.csr_get_perm(M)
+    xp = d(x[perm])
+    yp = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    fs.spmv_perm(M, xp, yp)
+    torch.cuda.synchronize()
+    yo = oracle.spmv(A, x)[perm]
+    err = np.abs(yp.cpu().numpy() - yo)
+    ok = bool(np.all(err <= 1e-12 * oracle.spmv_abs(A, x)[perm]))
+    bytes_alg = 12 * A.nnz + 8 * A.n_cols + 8 * A.n_rows
+    fn = lambda: fs.spmv_perm(M, xp, yp)
+    t_b2b = back_to_back_us(torch, fn, steps, warmup, stream)
+    warm = event_times_us(torch, fn, 20, stream)
+    out = {"n_rows": A.n_rows, "nnz": A.nnz, "parity_all_rows": ok,
+           "max_abs_err": float(err.max()) if len(err) else 0.0,
+           "us": t_b2b, "gbs": bytes_alg / (t_b2b * 1e-6) / 1e9,
+           "warm_us": dist(warm),
+           "slots": info["slots"], "padding": info["padding"],
+           "groups_by_lanes": info["groups_by_lanes"],
+           "reorder": info["reorder"], "t_build_ms": info["t_build_ms"]}
+    out["frac"] = out["gbs"] / HBM_PEAK_GBS
+    if cold:
+        junk = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        c = event_times_us(torch, fn, 20, stream,
+                           flush=lambda: junk.fill_(1.0))
+        out["cold_us"] = dist(c)
+        out["cold_gbs"] = bytes_alg / (out["cold_us"]["median"] * 1e-6) / 1e9
+        del junk
+    # plain CSR product (no layout) in caller numbering
+    xd = d(x)
+    y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    fs.spmv_csr(rp, ci, va, A.n_rows, A.n_cols, xd, y)
+    torch.cuda.synchronize()
+    ok_csr = bool(np.all(np.abs(y.cpu().numpy() - oracle.spmv(A, x)) <=
+                         1e-12 * oracle.spmv_abs(A, x)))
+    t_csr = back_to_back_us(torch, lambda: fs.spmv_csr(
+        rp, ci, va, A.n_rows, A.n_cols, xd, y), steps, warmup, stream)
+    out["csr_plain"] = {"us": t_csr,
+                        "gbs": bytes_alg / (t_csr * 1e-6) / 1e9,
+                        "parity_all_rows": ok_csr}
+    # products after which building the layout has paid for itself
+    gain = t_csr - t_b2b
+    out["break_even_products"] = (info["t_build_ms"] * 1e3 / gain
+                                  if gain > 0 else None)
+    return M, out
+
+
+def bench_async(fs, oracle, torch, A, M, d, b, reps):
+    """One right-hand side: the host-driven solve (chunks of iterations as
+    graphs, a state read per chunk) vs the stream-ordered solve (one
+    cooperative launch)."""
+    bd = d(b)
+    fs.cg_solve(M, bd, precond=fs.PC_JACOBI)
+    fs.cg_solve_async(M, bd, precond=fs.PC_JACOBI).info()
+    t_h, t_a = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xh, ih = fs.cg_solve(M, bd, precond=fs.PC_JACOBI)
+        t_h.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        res = fs.cg_solve_async(M, bd, precond=fs.PC_JACOBI)
+        ia = res.info()
+        t_a.append(time.perf_counter() - t0)
+    xa = res.x.cpu().numpy()
+    rel = float(np.linalg.norm(b - oracle.spmv(A, xa)) / np.linalg.norm(b))
+    return {"n_rows": A.n_rows, "iters_host_driven": ih["iters"],
+            "iters_async": ia["iters"],
+            "host_driven_ms": dist([t * 1e3 for t in t_h]),
+            "async_ms": dist([t * 1e3 for t in t_a]),
+            "async_kernel_ms": ia["ms"],
+            "speedup": float(np.median(t_h) / np.median(t_a)),
+            "async_status": ia["status"], "async_relres_oracle": rel}
+
+
+def bench_spmv_batch(fs, W, oracle, d, torch, stream, m=64):
+    """m small products (2-D Poisson, 48x48 nodes, random numbering): one
+    spmv call each vs one spmv_batch call."""
+    mats, Ms, xs = [], [], []
+    for i in range(m):
+        A = W.poisson_2d_p1(48, seed=(5, i), bc="all", permute=True)
+        mats.append(A)
+        Ms.append(fs.csr_create(d(A.rowptr), d(A.col), d(A.val), A.n_rows,
+                                A.n_cols))
+        xs.append(d(W.random_vector(A.n_cols, 5, W.XVEC, i)))
+    ys = [torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+          for A in mats]
+    one = lambda: [fs.spmv(M, x, y) for M, x, y in zip(Ms, xs, ys)]
+    bat = lambda: fs.spmv_batch(Ms, xs, ys)
+    t_one = back_to_back_us(torch, one, 20, 3, stream)
+    t_bat = back_to_back_us(torch, bat, 20, 3, stream)
+    ok = all(np.all(np.abs(y.cpu().numpy() - oracle.spmv(A, x.cpu().numpy()))
+                    <= 1e-12 * oracle.spmv_abs(A, x.cpu().numpy()))
+             for A, x, y in zip(mats, xs, ys))
+    return {"products": m, "rows_each": mats[0].n_rows,
+            "one_at_a_time_us_per_product": t_one / m,
+            "batched_us_per_product": t_bat / m,
+            "speedup": t_one / t_bat, "parity_all_rows": bool(ok)}
+
+
+def run_sweep(fs, W, oracle, torch, d, steps, warmup, stream):
+    """Every sweep matrix in natural and random numbering: layout, parity,
+    product GB/s, the plain CSR product, build time."""
+    rows = []
+    for i, (name, *_rest) in enumerate(W.SWEEP):
+        for permuted in (False, True):
+            t = time.time()
+            try:
+                A = W.sweep_matrix(i, permuted)
+            except NotImplementedError as e:
+                log("sweep %s: skipped (%s)" % (name, e))
+                rows.append({"matrix": name, "permuted": permuted,
+                             "skipped": str(e)})
+                break
+            tg = time.time() - t
+            M, r = measure_matrix(fs, oracle, torch, A, d, steps, warmup,
+                                  stream, cold=False)
+            del M
+            r.update(matrix=name, permuted=permuted, t_generate_s=tg)
+            rows.append(r)
+            log("sweep %s %s: %.1f GB/s (%.1f%% of peak), csr %.1f GB/s, "
+                "parity %s" % (name, "perm" if permuted else "nat", r["gbs"],
+                               100 * r["frac"], r["csr_plain"]["gbs"],
+                               r["parity_all_rows"]))
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,7 +400,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-largest", action="store_true",
+                    help="skip the largest sweep matrix (S12, 156M nnz)")
     ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the sparsity sweep: every sweep matrix, "
+                         "natural and random numbering, one JSON line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB copy kernel first (reference "
                          "for scaling the HBM byte counters)")
@@ -240,39 +419,26 @@ def main():
     import torch
     import paper_1501_00324_amd as fs
     import workloads as W
+    import oracle
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     fs.load(build_if_missing=True)
     dev = torch.device("cuda:0")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    stream = torch.cuda.current_stream()
+
+    if args.sweep:
+        rows = run_sweep(fs, W, oracle, torch, d, 50, 5, stream)
+        print(json.dumps({"metric": "SpMV effective GB/s per sweep matrix",
+                          "unit": "GB/s", "n_gpus": 1, "dtype": "f64",
+                          "data": "synthetic", "peak_gbs": HBM_PEAK_GBS,
+                          "sweep": rows}), flush=True)
+        return
 
     t = time.time()
     A = W.config1_elasticity3d()
     log("generated config-1 matrix: %d rows, %d nnz in %.1f s"
         % (A.n_rows, A.nnz, time.time() - t))
-    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    M = fs.csr_create(d(A.rowptr), d(A.col), d(A.val), A.n_rows, A.n_cols)
-    info = fs.csr_info(M)
-    log("layout: %s" % json.dumps({k: info[k] for k in (
-        "slots", "n_groups", "padding", "reorder", "groups_by_lanes",
-        "mean_band_before", "mean_band_after", "t_build_ms")}))
-    x = W.random_vector(A.n_cols, 1, W.XVEC)
-    xd = d(x)
-    perm = fs.csr_get_perm(M)
-    xp = d(x[perm])
-    yp = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
-    y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
-    bytes_alg = 12 * A.nnz + 8 * A.n_cols + 8 * A.n_rows
-
-    # parity spot check of the exact launch configuration that is timed
-    import oracle
-    fs.spmv_perm(M, xp, yp)
-    torch.cuda.synchronize()
-    yo = oracle.spmv(A, x)
-    err = np.abs(yp.cpu().numpy() - yo[perm])
-    ok = bool(np.all(err <= 1e-12 * oracle.spmv_abs(A, x)[perm]))
-    log("parity (all %d rows vs oracle): %s, max abs err %.3e"
-        % (A.n_rows, ok, err.max()))
 
     if args.calibrate_copy:
         ca = torch.ones(CALIB_DOUBLES, dtype=torch.float64, device=dev)
@@ -285,38 +451,29 @@ def main():
                                         8 * CALIB_DOUBLES))
         del ca, cb
 
-    for _ in range(args.warmup):
-        fs.spmv_perm(M, xp, yp)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        fs.spmv_perm(M, xp, yp)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_kernel = e0.elapsed_time(e1) / args.steps
-    gbs = bytes_alg / (ms_kernel * 1e-3) / 1e9
-    log("spmv_perm: %.2f us/launch (events), wall %.3f s for %d, %.1f GB/s"
-        % (ms_kernel * 1e3, wall, args.steps, gbs))
+    # the timed product: spmv_perm (layout numbering, as inside CG), K
+    # launches back to back between two events on the launch stream
+    M, prod = measure_matrix(fs, oracle, torch, A, d, args.steps,
+                             args.warmup, stream)
+    us = prod["us"]
+    gbs = prod["gbs"]
+    bytes_alg = 12 * A.nnz + 8 * A.n_cols + 8 * A.n_rows
+    log("spmv_perm: %.2f us/launch, %.1f GB/s; cold median %.2f us; plain "
+        "CSR %.2f us; parity %s" % (us, gbs, prod["cold_us"]["median"],
+                                    prod["csr_plain"]["us"],
+                                    prod["parity_all_rows"]))
 
     # caller numbering (gather of x + fused scatter of y)
-    for _ in range(args.warmup):
-        fs.spmv(M, xd, y)
-    e0.record(stream)
-    for _ in range(args.steps):
-        fs.spmv(M, xd, y)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_caller = e0.elapsed_time(e1) / args.steps
-    gbs_caller = bytes_alg / (ms_caller * 1e-3) / 1e9
-    log("spmv (caller numbering): %.2f us, %.1f GB/s"
-        % (ms_caller * 1e3, gbs_caller))
+    x = W.random_vector(A.n_cols, 1, W.XVEC)
+    xd = d(x)
+    y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    us_caller = back_to_back_us(torch, lambda: fs.spmv(M, xd, y), args.steps,
+                                args.warmup, stream)
+    gbs_caller = bytes_alg / (us_caller * 1e-6) / 1e9
+    log("spmv (caller numbering): %.2f us, %.1f GB/s" % (us_caller,
+                                                         gbs_caller))
 
-    cg = ir = multi = batch = None
+    cg = ir = multi = batch = asy = asy_small = sbatch = None
     if not args.no_cg:
         b = W.random_vector(A.n_rows, 1, W.BVEC)
         bd = d(b)
@@ -352,31 +509,59 @@ def main():
             r["speedup_vs_fp64"] = cg["ms"] / r["ms"]
             ir[name] = r
             log("cg ir-%s: %s" % (name, json.dumps(r)))
+        asy = bench_async(fs, oracle, torch, A, M, d, b, reps=3)
+        log("cg stream-ordered (config 1): %s" % json.dumps(asy))
+        A0 = W.config0_poisson2d()
+        M0 = fs.csr_create(d(A0.rowptr), d(A0.col), d(A0.val), A0.n_rows,
+                           A0.n_cols)
+        asy_small = bench_async(fs, oracle, torch, A0, M0, d,
+                                W.random_vector(A0.n_rows, 0, W.BVEC),
+                                reps=20)
+        log("cg stream-ordered (config 0): %s" % json.dumps(asy_small))
         # k right-hand sides through one multi-column product per iteration
-        k = 16
-        Bk = W.random_vector(A.n_rows, 1, W.BVEC, 1, k=k)
-        Bkd = d(Bk)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Xk, infos = fs.cg_solve_multi(M, Bkd, precond=fs.PC_JACOBI,
-                                      check=False)
-        tk = time.perf_counter() - t0
-        Xk_h = Xk.cpu().numpy()
-        worst = max(float(np.linalg.norm(Bk[:, c] - oracle.spmv(A, Xk_h[:, c]
-                                                                .copy())) /
-                          np.linalg.norm(Bk[:, c])) for c in range(k))
-        multi = {"k": k, "ms": tk * 1e3, "solves_per_s": k / tk,
-                 "speedup_vs_one_at_a_time": (k / tk) / cg["solves_per_s"],
-                 "iters_max": max(i["iters"] for i in infos),
-                 "relres_oracle_worst": worst}
-        log("cg multi-rhs: %s" % json.dumps(multi))
+        multi = {}
+        for k in (4, 8, 16):
+            Bk = W.random_vector(A.n_rows, 1, W.BVEC, 1, k=k)
+            Bkd = d(Bk)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Xk, infos = fs.cg_solve_multi(M, Bkd, precond=fs.PC_JACOBI,
+                                          check=False)
+            tk = time.perf_counter() - t0
+            Xk_h = Xk.cpu().numpy()
+            worst = max(float(np.linalg.norm(
+                Bk[:, c] - oracle.spmv(A, Xk_h[:, c].copy())) /
+                np.linalg.norm(Bk[:, c])) for c in range(k))
+            multi[str(k)] = {
+                "k": k, "ms": tk * 1e3, "solves_per_s": k / tk,
+                "speedup_vs_one_at_a_time": (k / tk) / cg["solves_per_s"],
+                "iters_max": max(i["iters"] for i in infos),
+                "all_converged": all(i["status"] == fs.FS_OK
+                                     for i in infos),
+                "relres_oracle_worst": worst}
+            log("cg multi-rhs k=%d: %s" % (k, json.dumps(multi[str(k)])))
         batch = bench_small_batch(fs, W, oracle, d, torch)
         log("batched small systems: %s" % json.dumps(batch))
+        sbatch = bench_spmv_batch(fs, W, oracle, d, torch, stream)
+        log("batched small products: %s" % json.dumps(sbatch))
     serving = None
     if args.serving_requests > 0:
         serving = bench_serving(fs, W, oracle, d, torch,
                                 n_req=args.serving_requests)
         log("serving: %s" % json.dumps(serving))
+
+    largest = None
+    if not args.no_largest:
+        i12 = [i for i, r in enumerate(W.SWEEP) if r[0].startswith("S12")][0]
+        t = time.time()
+        A12 = W.sweep_matrix(i12, False)
+        tg = time.time() - t
+        M12, largest = measure_matrix(fs, oracle, torch, A12, d, 50, 5,
+                                      stream)
+        largest.update(matrix=W.SWEEP[i12][0], numbering="natural",
+                       t_generate_s=tg)
+        del M12
+        log("largest FEM matrix: %s" % json.dumps(largest))
 
     # CPU oracle on a bounded sample: repeated full products
     reps, tc = 0, 0.0
@@ -404,7 +589,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_kernel,
+        "ms_per_step": us * 1e-3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -423,15 +608,17 @@ def main():
                      "bytes_algorithmic": bytes_alg,
                      "kernel": "k_spmv_f64"},
         "cpu_baseline": cpu,
+        "spmv": prod,
         "spmv_caller_numbering_gbs": round(gbs_caller, 2),
-        "paper_model_gbs": round(20 * A.nnz / (ms_kernel * 1e-3) / 1e9, 2),
-        "layout": {k: info[k] for k in ("slots", "padding", "n_groups",
-                                        "groups_by_lanes", "t_build_ms")},
-        "parity_all_rows": ok,
+        "paper_model_gbs": round(20 * A.nnz / (us * 1e-6) / 1e9, 2),
+        "parity_all_rows": prod["parity_all_rows"],
+        "largest_fem_matrix": largest,
         "cg": cg,
         "cg_mixed_precision": ir,
+        "cg_stream_ordered": {"config1": asy, "config0": asy_small},
         "cg_multi_rhs": multi,
         "cg_batched_small": batch,
+        "spmv_batched_small": sbatch,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

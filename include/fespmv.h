@@ -184,6 +184,20 @@ fs_status spmv(fs_csr_t A, const double *x, double *y, hipStream_t s);
  * numbering and never pays the final re-mapping).  Asynchronous on s. */
 fs_status spmv_perm(fs_csr_t A, const double *xp, double *yp, hipStream_t s);
 
+/* y = A x straight from CSR device arrays (rowptr n_rows + 1, colind and
+ * vals nnz entries), without building a layout: T lanes per row stride over
+ * the row's entries (T = the largest power of two not above half the mean
+ * row length, at most 64) and are reduced by shuffles.  The product for a
+ * matrix used once, and the reference for the layout build's break-even
+ * count (section "Cost of Reordering Matrix Values": reordering pays off
+ * after enough products).  No validation pass: a malformed CSR gives wrong
+ * values but no out-of-bounds access (row bounds and columns are clamped).
+ * x and y must not alias.  Asynchronous on s. */
+fs_status spmv_csr(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                   const int32_t *rowptr, const int32_t *colind,
+                   const double *vals, const double *x, double *y,
+                   hipStream_t s);
+
 /* m independent products y_i = A_i x_i in the caller's numbering, the
  * batch form of spmv (same statement of the problem; each result is bitwise
  * the spmv result).  A, x and y are HOST arrays of m entries holding handles

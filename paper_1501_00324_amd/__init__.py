@@ -84,7 +84,8 @@ class CgInfo(C.Structure):
 EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "csr_layout_host",
            "csr_update_values", "csr_add_dtype", "csr_info", "csr_get_perm",
-           "csr_destroy", "spmv", "spmv_batch", "spmv_perm", "csr_permute",
+           "csr_destroy", "spmv", "spmv_csr", "spmv_batch", "spmv_perm",
+           "csr_permute",
            "spmm",
            "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_async",
            "cg_solve_multi",
@@ -124,6 +125,7 @@ def load(build_if_missing=True):
         "csr_destroy": [vp],
         "spmv": [vp, vp, vp, vp],
         "spmv_batch": [i32, vp, vp, vp, vp],
+        "spmv_csr": [i32, i32, i64, vp, vp, vp, vp, vp, vp],
         "spmv_perm": [vp, vp, vp, vp],
         "csr_permute": [vp, i32, vp, vp, vp],
         "spmm": [vp, i32, vp, i64, vp, i64, vp],
@@ -300,6 +302,22 @@ def spmv(A, x, y=None, stream=None):
     _check(load().spmv(A._h, _ptr(x, torch.float64, A.n_cols, "x"),
                        _ptr(y, torch.float64, A.n_rows, "y"),
                        _stream(stream)))
+    return y
+
+
+def spmv_csr(rowptr, col, val, n_rows, n_cols, x, y=None, stream=None):
+    """y = A x from CSR device tensors, no layout (the plain product)."""
+    import torch
+    nnz = col.numel()
+    if y is None:
+        y = torch.empty(n_rows, dtype=torch.float64, device=x.device)
+    _check(load().spmv_csr(n_rows, n_cols, nnz,
+                           _ptr(rowptr, torch.int32, n_rows + 1, "rowptr"),
+                           _ptr(col, torch.int32, nnz, "col"),
+                           _ptr(val, torch.float64, nnz, "val"),
+                           _ptr(x, torch.float64, n_cols, "x"),
+                           _ptr(y, torch.float64, n_rows, "y"),
+                           _stream(stream)))
     return y
 
 

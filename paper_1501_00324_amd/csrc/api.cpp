@@ -518,6 +518,23 @@ fs_status spmv(fs_csr_t A, const double *x, double *y, hipStream_t s)
     return FS_OK;
 }
 
+fs_status spmv_csr(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                   const int32_t *rowptr, const int32_t *colind,
+                   const double *vals, const double *x, double *y,
+                   hipStream_t s)
+{
+    if (n_rows < 0 || n_cols < 0 || nnz < 0)
+        return set_error(FS_E_ARG, "negative size");
+    if (n_rows == 0) return FS_OK;
+    if (!rowptr || !y || (nnz > 0 && (!colind || !vals)) ||
+        (n_cols > 0 && !x))
+        return set_error(FS_E_ARG, "NULL array");
+    if (x == y) return set_error(FS_E_ARG, "x and y must not alias");
+    FS_HIP_TRY(launch_spmv_csr(n_rows, n_cols, nnz, rowptr, colind, vals, x,
+                               y, s));
+    return FS_OK;
+}
+
 fs_status spmv_batch(int32_t m, const fs_csr_t *A, const double *const *x,
                      double *const *y, hipStream_t s)
 {

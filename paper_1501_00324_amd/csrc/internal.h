@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/fespmv.h"
+#include "layout.h"
 
 namespace fs {
 
@@ -31,23 +32,7 @@ void clear_error();
     } while (0)
 
 // ----------------------------------------------------------------- layout
-// One row group is processed by one 64-lane wavefront.  A group holds
-// 64 / T consecutive layout rows, T lanes per row (T a power of two); entry
-// e of a row (columns ascending) goes to lane (row_in_group * T + e % T),
-// slot e / T of that lane.  Slots are interleaved so that one wave-wide
-// load of V consecutive slots per lane (V = 1 or 2, per matrix) is one
-// contiguous 64*V element block:
-//     element index = base + (s / V) * 64 * V + lane * V + s % V.
-constexpr int kWave = 64;
-constexpr int kBlock = 256;        // threads per workgroup (4 waves)
-
-struct Group {                     // 16 bytes, read once per wave
-    int32_t base64;                // first element index / 64
-    int32_t row0;                  // first layout row
-    int32_t nrows;                 // rows in the group (1..64/T)
-    int32_t width_lt;              // slots per lane | log2(T) << 24
-};
-
+// Group, kWave and kBlock (the device data layout) are in layout.h.
 struct HostLayout {
     std::vector<int32_t> perm;     // layout row i <- caller row perm[i]
     std::vector<int32_t> iperm;
@@ -266,6 +251,12 @@ hipError_t launch_cg_persistent(const fs_csr *A, int32_t nblocks,
                                 double *p, double *q, double *dinv,
                                 double *part, fs_cg_info *info, double rtol,
                                 int32_t maxit, bool x_zero, hipStream_t s);
+// Plain CSR product (no layout), lanes per row from the mean row length.
+int32_t csr_lanes_log2(int32_t n_rows, int64_t nnz);
+hipError_t launch_spmv_csr(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                           const int32_t *rowptr, const int32_t *col,
+                           const double *val, const double *x, double *y,
+                           hipStream_t s);
 // Low-precision product in layout numbering: y = A_lo x (float vectors,
 // float accumulation), A_lo the FP32 or BF16 copy.
 hipError_t launch_spmv_lowp(const fs_csr *A, int32_t dtype, const float *x,

@@ -210,3 +210,36 @@ def test_spmv_batch_rejects_aliasing(fs, orc):
         fs.spmv_batch([M, M], [v, v], [w, w])
     assert e.value.status == fs.FS_E_ARG
     assert fs.spmv_batch([], []) == []
+
+
+# ------------------------------------------------- plain CSR (no layout)
+def long_rows(n_rows, n_cols, seed):
+    """Rows of 300..1200 entries (mean above 256: 64 lanes per row)."""
+    g = np.random.default_rng(seed)
+    lens = g.integers(300, 1200, n_rows)
+    cols = [np.sort(g.choice(n_cols, L, replace=False)) for L in lens]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    return CSR(n_rows, n_cols, rp, np.concatenate(cols).astype(np.int32),
+               g.uniform(-1, 1, int(rp[-1])))
+
+
+CSR_CASES = [
+    ("cfg0", W.config0_poisson2d),
+    ("ela_perm", lambda: W.tet_p1(9, "elastic", seed=(57, 0), bc="x0",
+                                  permute=True)),
+    ("p2ela", lambda: W.tet_p2(4, "elastic", seed=(57, 1))),
+    ("ragged", lambda: ragged(900, 411, seed=57)),
+    ("long_rows", lambda: long_rows(70, 5000, seed=58)),
+    ("no_entries", lambda: CSR(5, 3, np.zeros(6, np.int32),
+                               np.zeros(0, np.int32), np.zeros(0))),
+]
+
+
+@pytest.mark.parametrize("name,gen", CSR_CASES, ids=[c[0] for c in CSR_CASES])
+def test_spmv_csr_parity(fs, orc, name, gen):
+    A = gen()
+    note("spmv_csr %s n=%d nnz=%d" % (name, A.n_rows, A.nnz))
+    x = W.random_vector(A.n_cols, 59, W.XVEC)
+    y = host(fs.spmv_csr(dev(A.rowptr), dev(A.col), dev(A.val), A.n_rows,
+                         A.n_cols, dev(x)))
+    assert_spmv_close(y, orc.spmv(A, x), orc.spmv_abs(A, x), name)
