@@ -26,6 +26,12 @@ namespace {
 
 namespace cgr = cooperative_groups;
 
+// 1024-thread blocks (16 wavefronts, one block per CU at this kernel's
+// register use): a grid barrier costs roughly a fixed time per arriving
+// block, so fewer, larger blocks make each barrier cheaper.
+constexpr int kPB = 1024;
+constexpr int kPW = kPB / kWave;
+
 struct PcgArgs {
     const Group *groups;
     const double *val;
@@ -44,7 +50,7 @@ template <int NJ>
 __device__ __forceinline__ void put_partials(const double (&v)[NJ],
                                              double *part, int nb, int b)
 {
-    __shared__ double sh[3][kWavesPerBlock];
+    __shared__ double sh[3][kPW];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -54,7 +60,7 @@ __device__ __forceinline__ void put_partials(const double (&v)[NJ],
     __syncthreads();
     if (int(threadIdx.x) < NJ) {
         double t = 0.0;
-        for (int i = 0; i < kWavesPerBlock; ++i) t += sh[threadIdx.x][i];
+        for (int i = 0; i < kPW; ++i) t += sh[threadIdx.x][i];
         part[long(threadIdx.x) * nb + b] = t;
     }
     __syncthreads();
@@ -93,7 +99,7 @@ __device__ __forceinline__ void residual_rows(const PcgArgs &a, int g0, int g1,
                                               F f)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
+    for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kPW) {
         const Group gd = load_group(a.groups, __builtin_amdgcn_readfirstlane(g));
         const int lt = gd.width_lt >> 24;
         double ax = 0.0;
@@ -110,7 +116,7 @@ __device__ __forceinline__ void residual_rows(const PcgArgs &a, int g0, int g1,
 enum { P_RUNNING = 0, P_CONVERGED = 1, P_BREAKDOWN = 2, P_MAXIT = 3 };
 
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_cg_persistent(const PcgArgs a)
+__global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
 {
     cgr::grid_group grid = cgr::this_grid();
     const long t_start = wall_clock64();
@@ -125,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_persistent(const PcgArgs a)
     // Jacobi scaling for this block's groups (the same rows the start pass
     // below writes, so no barrier is needed in between)
     if (D) {
-        for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
+        for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kPW) {
             const Group gd =
                 load_group(a.groups, __builtin_amdgcn_readfirstlane(g));
             const int lt = gd.width_lt >> 24, width = gd.width_lt & 0xffffff;
@@ -163,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_persistent(const PcgArgs a)
     int status = P_RUNNING, it = 0, repl = 0;
     if (bb == 0.0) {
         // b = 0: x = 0 is the solution
-        for (int i = r0 + int(threadIdx.x); i < r1; i += kBlock) a.x[i] = 0.0;
+        for (int i = r0 + int(threadIdx.x); i < r1; i += kPB) a.x[i] = 0.0;
         status = P_CONVERGED;
         rr_true = 0.0;
     } else if (rr <= tol2) {
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_persistent(const PcgArgs a)
     while (status == P_RUNNING) {
         // q = A p, p.q
         double v1[1] = {0.0};
-        for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
+        for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kPW) {
             const Group gd =
                 load_group(a.groups, __builtin_amdgcn_readfirstlane(g));
             const int lt = gd.width_lt >> 24;
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_persistent(const PcgArgs a)
         const double alpha = rho / gamma;
         // x, r update; z = D^-1 r; r.z, r.r
         double v2[2] = {0.0, 0.0};
-        for (int i = r0 + int(threadIdx.x); i < r1; i += kBlock) {
+        for (int i = r0 + int(threadIdx.x); i < r1; i += kPB) {
             const double ri = a.r[i] - alpha * a.q[i];
             a.x[i] += alpha * a.p[i];
             a.r[i] = ri;
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_persistent(const PcgArgs a)
         }
         // p = z + beta p (rows of this block; r of these rows was written
         // by this block, or before the last barrier)
-        for (int i = r0 + int(threadIdx.x); i < r1; i += kBlock) {
+        for (int i = r0 + int(threadIdx.x); i < r1; i += kPB) {
             const double zi = D ? D[i] * a.r[i] : a.r[i];
             a.p[i] = zi + beta * a.p[i];
         }
@@ -291,7 +297,7 @@ template <int V> int max_coresident(int device)
     if (cached[device] == 0) {
         int per_cu = 0, cus = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, k_cg_persistent<V>, kBlock, 0) != hipSuccess ||
+                &per_cu, k_cg_persistent<V>, kPB, 0) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                   device) != hipSuccess)
             return 0;
@@ -304,8 +310,8 @@ template <int V> int max_coresident(int device)
 
 int32_t persistent_blocks(const fs_csr *A)
 {
-    const int want = std::max((A->n_groups + kWavesPerBlock - 1) / kWavesPerBlock,
-                              (A->n_rows + kBlock - 1) / kBlock);
+    const int want = std::max((A->n_groups + kPW - 1) / kPW,
+                              (A->n_rows + kPB - 1) / kPB);
     const int cap = A->host.vec == 1 ? max_coresident<1>(A->device)
                                      : max_coresident<2>(A->device);
     return std::max(1, std::min({want, cap, kPersistMaxBlocks}));
@@ -344,10 +350,10 @@ hipError_t launch_cg_persistent(const fs_csr *A, int32_t nblocks,
     if (A->host.vec == 1)
         return hipLaunchCooperativeKernel(
             reinterpret_cast<const void *>(k_cg_persistent<1>), dim3(nblocks),
-            dim3(kBlock), args, 0, s);
+            dim3(kPB), args, 0, s);
     return hipLaunchCooperativeKernel(
         reinterpret_cast<const void *>(k_cg_persistent<2>), dim3(nblocks),
-        dim3(kBlock), args, 0, s);
+        dim3(kPB), args, 0, s);
 }
 
 }  // namespace fs
