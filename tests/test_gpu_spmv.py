@@ -64,11 +64,18 @@ def test_elasticity_layouts(fs, orc, li):
     run_spmv(fs, orc, A, LAYOUTS[li], li, "ela12")
 
 
-@pytest.mark.parametrize("i", [0, 3, 6, 9])
+@pytest.mark.parametrize("i", [0, 3, 6, 9, 12])
 @pytest.mark.parametrize("permuted", [False, True])
 def test_sweep_small(fs, orc, i, permuted):
     A = W.sweep_matrix(i, permuted)
     run_spmv(fs, orc, A, {}, 100 + i, A.meta["name"])
+
+
+@pytest.mark.parametrize("li", [0, 1, 3, 7, 9, 12])
+def test_graded_layouts(fs, orc, li):
+    """Skewed row lengths (3 .. 199 entries) under several layouts."""
+    A = W.graded_2d_p1(60, seed=(52, 0), permute=True, hubs=None)
+    run_spmv(fs, orc, A, LAYOUTS[li], li, "graded60")
 
 
 @pytest.mark.parametrize("nr,nc", [(1, 1), (63, 63), (65, 65), (1000, 1000),

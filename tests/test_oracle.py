@@ -43,6 +43,8 @@ def tiny_meshes():
     for c in (1, 2):
         out.append(W.tet_p2(c, "laplace", seed=(93, c)))
         out.append(W.tet_p2(c, "elastic", seed=(93, c), permute=True))
+    out.append(W.graded_2d_p1(12, seed=(94, 0), hubs=[12 * 5 + 5]))
+    out.append(W.graded_2d_p1(16, seed=(94, 1), permute=True))
     return out
 
 
@@ -94,7 +96,7 @@ def test_spmv_random_nonsymmetric_vs_dense(orc, case):
         assert y[i] == s
 
 
-@pytest.mark.parametrize("idx", range(20))
+@pytest.mark.parametrize("idx", range(22))
 def test_spmv_fem_vs_dense(orc, idx):
     A = tiny_meshes()[idx]
     x = W.random_vector(A.n_cols, 90, W.XVEC, idx)
@@ -105,7 +107,7 @@ def test_spmv_fem_vs_dense(orc, idx):
     assert np.all(np.abs(y - D @ x) <= 1e-14 * scale)
 
 
-@pytest.mark.parametrize("idx", range(20))
+@pytest.mark.parametrize("idx", range(22))
 def test_spmv_symmetry(orc, idx):
     """x^T (A y) = y^T (A x) for the symmetric stiffness matrices."""
     A = tiny_meshes()[idx]

@@ -81,3 +81,63 @@ def test_random_vectors_are_seeded_uniform():
     c = W.random_vector(1000, 1, W.BVEC)
     assert np.array_equal(a, b) and not np.array_equal(a, c)
     assert a.min() >= -1 and a.max() <= 1
+
+
+# ------------------------------------------------------ graded 2-D meshes
+def graded_cases():
+    return [W.graded_2d_p1(30, seed=(9, 0)),
+            W.graded_2d_p1(30, seed=(9, 1), permute=True),
+            W.graded_2d_p1(24, seed=(9, 2), hubs=[24 * 8 + 8, 24 * 15 + 15])]
+
+
+@pytest.mark.parametrize("ci", range(3))
+def test_graded_mesh_is_a_conforming_cover(ci):
+    """Triangle areas add up to the unit square and every interior edge is
+    shared by exactly two triangles, boundary edges by one (no gaps, no
+    overlaps, no hanging nodes)."""
+    A = graded_cases()[ci]
+    X, T = A.meta["coords"], A.meta["triangles"]
+    P = X[T]
+    e1, e2 = P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]
+    det = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+    assert np.all(det > 0)
+    assert abs(0.5 * det.sum() - 1.0) < 1e-12
+    E = np.sort(np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]]),
+                axis=1)
+    _, cnt = np.unique(E, axis=0, return_counts=True)
+    assert set(np.unique(cnt)) <= {1, 2}
+    ue, cnt = np.unique(E, axis=0, return_counts=True)
+    mid = X[ue].mean(axis=1)
+    on_bd = np.any((np.abs(mid) < 1e-12) | (np.abs(mid - 1) < 1e-12), axis=1)
+    assert np.all(on_bd == (cnt == 1))
+
+
+@pytest.mark.parametrize("ci", range(3))
+def test_graded_laplacian_patch_test(ci):
+    """P1 Laplacian: zero row sums (Neumann), symmetry, and A u = 0 at
+    every interior node for a linear u -- fails for a non-conforming or
+    mis-assembled mesh."""
+    A = graded_cases()[ci]
+    S = A.to_scipy()
+    X = A.meta["coords"]
+    assert np.max(np.abs(S @ np.ones(A.n_rows))) < 1e-12
+    assert abs(S - S.T).max() < 1e-14
+    u = 0.3 + 1.7 * X[:, 0] - 2.9 * X[:, 1]
+    r = S @ u
+    interior = np.all((X > 1e-12) & (X < 1 - 1e-12), axis=1)
+    assert np.max(np.abs(r[interior])) < 1e-11
+    assert np.max(np.abs(r[~interior])) > 1e-3    # boundary flux is not 0
+
+
+def test_graded_row_lengths():
+    """Hub rows have 1 + 6 m entries; the distribution is skewed."""
+    A = W.graded_2d_p1(24, seed=(9, 2), hubs=[24 * 8 + 8, 24 * 15 + 15],
+                       max_row=200)
+    L = A.row_lengths()
+    assert L.max() == 1 + 6 * 33
+    assert np.sum(L == L.max()) == 2
+    B = W.sweep_matrix(13, permuted=False)
+    LB = B.row_lengths()
+    assert np.median(LB) == 7 and LB.max() > 100 and LB.min() >= 3
+    C = W.sweep_matrix(13, permuted=False)
+    assert np.array_equal(B.val, C.val)           # seeded: reproducible

@@ -461,18 +461,19 @@ def laplace_1d_p1(n_el):
             np.full(m, h))
 
 
-def graded_2d_p1(n, hubs=None, seed=None, jitter=0.2, max_row=200):
+def graded_2d_p1(n, hubs=None, seed=None, jitter=0.2, max_row=200,
+                 permute=False):
     """Graded 2-D triangle mesh with a skewed row-length distribution.
 
     Start from the n x n structured P1 triangle mesh.  A seeded set of hub
-    nodes (at least 3 grid hops apart) is refined: for hub v with fan factor
-    m (geometric law, capped so the hub row stays near ``max_row``), every
+    nodes (at least 4 grid steps apart) is refined: for hub v with fan factor
+    m (geometric law, capped so the hub row stays within ``max_row``), every
     edge of v's 1-ring is subdivided into m pieces and each incident
     triangle is re-fanned from v through the new points; the neighbouring
     triangle across that ring edge is re-fanned from its opposite vertex so
     the mesh stays conforming.  Hub rows get up to ``max_row`` entries,
-    ordinary rows keep 7.
+    ordinary rows keep 7.  P1 Laplacian, Neumann (singular, SpMV only).
     """
     from .graded import build_graded
     return build_graded(n, hubs=hubs, seed=seed, jitter=jitter,
-                        max_row=max_row)
+                        max_row=max_row, permute=permute)
