@@ -5,7 +5,9 @@ benchmark may import this package.  The product library never does, and this
 package never imports the product library: the two share no code.
 
 The arithmetic lives in ``oracle.c`` (plain C, FP64, single thread, built
-with ``gcc -O2 -ffp-contract=off``); this module only marshals numpy arrays.
+with ``gcc -O2 -ffp-contract=off``; one row-parallel OpenMP copy of the
+product exists only to time the oracle on all host cores); this module only
+marshals numpy arrays.
 ``build()`` compiles it; ``load()`` builds on first use when the shared
 object is missing.
 """
@@ -31,7 +33,8 @@ def build(force=True):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC",
-                           "-shared", "-std=c11", SRC, "-o", tmp, "-lm"])
+                           "-fopenmp", "-shared", "-std=c11", SRC, "-o", tmp,
+                           "-lm"])
     os.replace(tmp, LIB)
     return LIB
 
@@ -57,6 +60,8 @@ def _declare(L):
     i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
     P = C.POINTER
     L.or_spmv.argtypes = [i32, _i32p, _i32p, _f64p, _f64p, _f64p]
+    L.or_spmv_par.argtypes = [i32, _i32p, _i32p, _f64p, _f64p, _f64p]
+    L.or_spmv_par.restype = C.c_int
     L.or_spmv_abs.argtypes = [i32, _i32p, _i32p, _f64p, _f64p, _f64p]
     L.or_spmm.argtypes = [i32, _i32p, _i32p, _f64p, i32, _f64p, i64, _f64p,
                           i64]
@@ -105,6 +110,18 @@ def spmv(A, x):
     y = np.empty(A.n_rows)
     L.or_spmv(A.n_rows, rp, c, v, x, y)
     return y
+
+
+def spmv_par(A, x):
+    """spmv with rows split over OpenMP threads (bitwise the same result);
+    returns (y, threads used)."""
+    L = load()
+    rp, c, v = _csr(A)
+    x = _f64(x)
+    assert x.shape == (A.n_cols,)
+    y = np.empty(A.n_rows)
+    used = L.or_spmv_par(A.n_rows, rp, c, v, x, y)
+    return y, int(used)
 
 
 def spmv_abs(A, x):

@@ -14,6 +14,7 @@
  * diagonal entry with the Jacobi preconditioner).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -37,6 +38,29 @@ void or_spmv(int32_t n_rows, const int32_t *rowptr, const int32_t *col,
             s += val[k] * x[col[k]];
         y[i] = s;
     }
+}
+
+/* The same row sums with the rows split over OpenMP threads (each row is
+ * still summed by one thread in storage order, so the result is bitwise
+ * that of or_spmv).  Used only to time the oracle on all host cores.
+ * Returns the number of threads used. */
+int or_spmv_par(int32_t n_rows, const int32_t *rowptr, const int32_t *col,
+                const double *val, const double *x, double *y)
+{
+    int used = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+#pragma omp for schedule(static)
+        for (int32_t i = 0; i < n_rows; ++i) {
+            double s = 0.0;
+            for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                s += val[k] * x[col[k]];
+            y[i] = s;
+        }
+    }
+    return used;
 }
 
 /* Componentwise magnitude bound (|A| |x|)_i, the scale of the rounding error

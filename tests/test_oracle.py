@@ -442,3 +442,13 @@ def test_ir_cg_reaches_fp64_residual(orc, kind):
     xs = np.linalg.solve(D, b)
     kappa = np.linalg.cond(D)
     assert np.linalg.norm(x - xs) <= 2e-8 * kappa * np.linalg.norm(xs)
+
+
+def test_spmv_par_is_bitwise_spmv(orc):
+    """The all-cores timing copy of the product returns bitwise the serial
+    row sums."""
+    A = W.tet_p1(12, "elastic", seed=(95, 0), permute=True)
+    x = W.random_vector(A.n_cols, 95, W.XVEC)
+    y, used = orc.spmv_par(A, x)
+    assert used >= 1
+    assert np.array_equal(y, orc.spmv(A, x))
