@@ -396,6 +396,17 @@ def run_sweep(fs, W, oracle, torch, d, steps, warmup, stream):
                                   stream, cold=False)
             del M
             r.update(matrix=name, permuted=permuted, t_generate_s=tg)
+            # the oracle on the host: one thread, then all cores
+            xh = W.random_vector(A.n_cols, 1, W.XVEC)
+            bytes_alg = 12 * A.nnz + 8 * A.n_cols + 8 * A.n_rows
+            t0 = time.perf_counter()
+            oracle.spmv(A, xh)
+            t1 = time.perf_counter()
+            _, used = oracle.spmv_par(A, xh)
+            t2 = time.perf_counter()
+            r["cpu_oracle_gbs"] = bytes_alg / (t1 - t0) / 1e9
+            r["cpu_oracle_all_cores_gbs"] = bytes_alg / (t2 - t1) / 1e9
+            r["cpu_cores"] = used
             rows.append(r)
             log("sweep %s %s: %.1f GB/s (%.1f%% of peak), csr %.1f GB/s, "
                 "parity %s" % (name, "perm" if permuted else "nat", r["gbs"],
@@ -473,6 +484,19 @@ def main():
         "CSR %.2f us; parity %s" % (us, gbs, prod["cold_us"]["median"],
                                     prod["csr_plain"]["us"],
                                     prod["parity_all_rows"]))
+
+    # achievable streaming read rate (project kernel, 2 GiB, best of three
+    # grid sizes): the practical ceiling the product is compared with
+    buf = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+    sink = torch.empty(16384, dtype=torch.float64, device=dev)
+    stream_gbs = 0.0
+    for blocks in (2048, 4096, 16384):
+        t_rd = back_to_back_us(torch, lambda: fs.probe_read_bandwidth(
+            buf, sink, blocks), 20, 3, stream)
+        stream_gbs = max(stream_gbs, buf.numel() * 8 / (t_rd * 1e-6) / 1e9)
+    del buf, sink
+    log("streaming read probe: %.1f GB/s; product at %.1f%% of it"
+        % (stream_gbs, 100 * gbs / stream_gbs))
 
     # caller numbering (gather of x + fused scatter of y)
     x = W.random_vector(A.n_cols, 1, W.XVEC)
@@ -627,6 +651,8 @@ def main():
                    "op": "spmv_perm (layout numbering, as inside CG)",
                    "bytes_per_spmv": bytes_alg},
         "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
+        "stream_read_gbs": round(stream_gbs, 1),
+        "pct_of_stream_read": round(100.0 * gbs / stream_gbs, 2),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),

@@ -198,6 +198,15 @@ fs_status spmv_csr(int32_t n_rows, int32_t n_cols, int64_t nnz,
                    const double *vals, const double *x, double *y,
                    hipStream_t s);
 
+/* Measurement aid, not part of the method: stream n doubles of buf (device,
+ * 16-byte aligned; an odd last element is skipped) with `blocks`
+ * workgroups of 256 threads, writing one partial sum per block to
+ * sink[0 .. blocks-1] (device).  Timing it gives the achievable streaming
+ * read rate of the device, the practical ceiling for the products above.
+ * Asynchronous on s; FS_E_ARG on bad sizes or alignment. */
+fs_status probe_read_bandwidth(const double *buf, int64_t n, double *sink,
+                               int32_t blocks, hipStream_t s);
+
 /* m independent products y_i = A_i x_i in the caller's numbering, the
  * batch form of spmv (same statement of the problem; each result is bitwise
  * the spmv result).  A, x and y are HOST arrays of m entries holding handles

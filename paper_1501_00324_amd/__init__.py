@@ -85,6 +85,7 @@ EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "csr_layout_host",
            "csr_update_values", "csr_add_dtype", "csr_info", "csr_get_perm",
            "csr_destroy", "spmv", "spmv_csr", "spmv_batch", "spmv_perm",
+           "probe_read_bandwidth",
            "csr_permute",
            "spmm",
            "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_async",
@@ -126,6 +127,7 @@ def load(build_if_missing=True):
         "spmv": [vp, vp, vp, vp],
         "spmv_batch": [i32, vp, vp, vp, vp],
         "spmv_csr": [i32, i32, i64, vp, vp, vp, vp, vp, vp],
+        "probe_read_bandwidth": [vp, i64, vp, i32, vp],
         "spmv_perm": [vp, vp, vp, vp],
         "csr_permute": [vp, i32, vp, vp, vp],
         "spmm": [vp, i32, vp, i64, vp, i64, vp],
@@ -319,6 +321,16 @@ def spmv_csr(rowptr, col, val, n_rows, n_cols, x, y=None, stream=None):
                            _ptr(y, torch.float64, n_rows, "y"),
                            _stream(stream)))
     return y
+
+
+def probe_read_bandwidth(buf, sink, blocks, stream=None):
+    """Stream the float64 device tensor buf once (measurement aid)."""
+    import torch
+    if sink.numel() < blocks:
+        raise FsError(FS_E_ARG, "sink needs one entry per block")
+    _check(load().probe_read_bandwidth(_ptr(buf, torch.float64), buf.numel(),
+                                       _ptr(sink, torch.float64, None, "sink"),
+                                       int(blocks), _stream(stream)))
 
 
 def spmv_batch(mats, xs, ys=None, stream=None):

@@ -535,6 +535,19 @@ fs_status spmv_csr(int32_t n_rows, int32_t n_cols, int64_t nnz,
     return FS_OK;
 }
 
+fs_status probe_read_bandwidth(const double *buf, int64_t n, double *sink,
+                               int32_t blocks, hipStream_t s)
+{
+    if (n < 0 || blocks < 1 || blocks > (1 << 20))
+        return set_error(FS_E_ARG, "n must be >= 0 and blocks in [1, 2^20]");
+    if (n >= 2 && (!buf || !sink))
+        return set_error(FS_E_ARG, "NULL buffer");
+    if (reinterpret_cast<uintptr_t>(buf) % 16 != 0)
+        return set_error(FS_E_ARG, "buffer must be 16-byte aligned");
+    FS_HIP_TRY(launch_read_probe(buf, n, sink, blocks, s));
+    return FS_OK;
+}
+
 fs_status spmv_batch(int32_t m, const fs_csr_t *A, const double *const *x,
                      double *const *y, hipStream_t s)
 {

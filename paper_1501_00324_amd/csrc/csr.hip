@@ -76,3 +76,44 @@ hipError_t launch_spmv_csr(int32_t n_rows, int32_t n_cols, int64_t nnz,
 }
 
 }  // namespace fs
+
+// ---------------------------------------------------------------------
+// Read-bandwidth probe: every lane streams 16-byte non-temporal loads
+// over the buffer and folds them into one value per block (written to
+// sink, so the loads cannot be dropped).  The achievable streaming rate
+// against which the products' rates can be read.
+namespace fs {
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_read_probe(
+    const dv2 *__restrict__ p, long n2, double *__restrict__ sink)
+{
+    double s = 0.0;
+    for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < n2;
+         i += long(gridDim.x) * kBlock) {
+        const dv2 v = __builtin_nontemporal_load(p + i);
+        s += v.x + v.y;
+    }
+    s = wave_sum(s);
+    __shared__ double sh[kWavesPerBlock];
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kWavesPerBlock; ++w) t += sh[w];
+        sink[blockIdx.x] = t;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_read_probe(const double *buf, int64_t n, double *sink,
+                             int32_t blocks, hipStream_t s)
+{
+    if (n < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_read_probe, dim3(blocks), dim3(kBlock), 0, s,
+                       reinterpret_cast<const dv2 *>(buf), long(n / 2), sink);
+    return hipGetLastError();
+}
+
+}  // namespace fs

@@ -257,6 +257,10 @@ hipError_t launch_spmv_csr(int32_t n_rows, int32_t n_cols, int64_t nnz,
                            const int32_t *rowptr, const int32_t *col,
                            const double *val, const double *x, double *y,
                            hipStream_t s);
+// Streaming read of n doubles (n even, 16-byte aligned) by `blocks`
+// workgroups; one partial sum per block into sink.
+hipError_t launch_read_probe(const double *buf, int64_t n, double *sink,
+                             int32_t blocks, hipStream_t s);
 // Low-precision product in layout numbering: y = A_lo x (float vectors,
 // float accumulation), A_lo the FP32 or BF16 copy.
 hipError_t launch_spmv_lowp(const fs_csr *A, int32_t dtype, const float *x,
