@@ -11,15 +11,40 @@
 // no texture cache to hide a scrambled x), and each lane loads two adjacent
 // slots per access.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "internal.h"
 
 namespace fs {
 namespace {
+
+// f(c) for every chunk c in [0, nchunks), spread over up to 16 host
+// threads.  Chunks are independent; results must not depend on which
+// thread ran which chunk.
+template <class F> void parallel_chunks(int64_t nchunks, F f)
+{
+    const int64_t hw = std::max<int64_t>(1, std::thread::hardware_concurrency());
+    const int64_t nt = std::min<int64_t>({hw, int64_t(16), nchunks});
+    if (nt <= 1) {
+        for (int64_t c = 0; c < nchunks; ++c) f(c);
+        return;
+    }
+    std::atomic<int64_t> next(0);
+    std::vector<std::thread> th;
+    th.reserve(size_t(nt));
+    for (int64_t t = 0; t < nt; ++t)
+        th.emplace_back([&]() {
+            for (int64_t c = next++; c < nchunks; c = next++) f(c);
+        });
+    for (auto &t : th) t.join();
+}
+
+constexpr int64_t kRowChunk = 16384;
 
 // Pattern of A + A^T without the diagonal, rows sorted.  Only used for the
 // reordering, never for arithmetic.
@@ -44,26 +69,45 @@ Graph symmetric_graph(int32_t n, const int32_t *rowptr, const int32_t *col)
             for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
                 ti[size_t(pos[col[k]]++)] = i;
     }
+    // merge row i of A (sorted copy) with row i of T, dropping i itself:
+    // sizes first, then the rows, both in parallel over row chunks
     Graph g;
     g.n = n;
     g.rp.assign(size_t(n) + 1, 0);
-    g.ci.reserve(size_t(nnz));
-    std::vector<int32_t> row;
-    for (int32_t i = 0; i < n; ++i) {
+    const int64_t nch = (n + kRowChunk - 1) / kRowChunk;
+    auto merge_row = [&](int32_t i, std::vector<int32_t> &row, int32_t *out) {
         row.assign(col + rowptr[i], col + rowptr[i + 1]);
-        std::sort(row.begin(), row.end());
-        // merge row with column i of A (row i of T), dropping i itself
+        if (!std::is_sorted(row.begin(), row.end()))
+            std::sort(row.begin(), row.end());
         size_t a = 0, b = size_t(tp[i]), be = size_t(tp[i + 1]);
         int32_t last = -1;
+        int64_t m = 0;
         while (a < row.size() || b < be) {
             int32_t v;
             if (b >= be || (a < row.size() && row[a] <= ti[b])) v = row[a++];
             else v = ti[b++];
-            if (v != last && v != i) g.ci.push_back(v);
+            if (v != last && v != i) {
+                if (out) out[m] = v;
+                ++m;
+            }
             last = v;
         }
-        g.rp[i + 1] = int64_t(g.ci.size());
-    }
+        return m;
+    };
+    parallel_chunks(nch, [&](int64_t c) {
+        std::vector<int32_t> row;
+        const int32_t i1 = int32_t(std::min<int64_t>(n, (c + 1) * kRowChunk));
+        for (int32_t i = int32_t(c * kRowChunk); i < i1; ++i)
+            g.rp[size_t(i) + 1] = merge_row(i, row, nullptr);
+    });
+    for (int32_t i = 0; i < n; ++i) g.rp[i + 1] += g.rp[i];
+    g.ci.resize(size_t(g.rp[n]));
+    parallel_chunks(nch, [&](int64_t c) {
+        std::vector<int32_t> row;
+        const int32_t i1 = int32_t(std::min<int64_t>(n, (c + 1) * kRowChunk));
+        for (int32_t i = int32_t(c * kRowChunk); i < i1; ++i)
+            merge_row(i, row, g.ci.data() + g.rp[i]);
+    });
     return g;
 }
 
@@ -148,19 +192,29 @@ std::vector<int32_t> rcm_order(const Graph &g)
     return order;
 }
 
+// Mean |row - col| over the entries; partial sums per fixed row chunk added
+// in chunk order, so the value does not depend on the thread count.
 double mean_band(int32_t n, const int32_t *rowptr, const int32_t *col,
                  const int32_t *iperm)
 {
-    double s = 0.0;
     int64_t nnz = rowptr[n];
     if (nnz == 0) return 0.0;
-    for (int32_t i = 0; i < n; ++i) {
-        int64_t ri = iperm ? iperm[i] : i;
-        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            int64_t c = iperm ? iperm[col[k]] : col[k];
-            s += double(ri > c ? ri - c : c - ri);
+    const int64_t nch = (n + kRowChunk - 1) / kRowChunk;
+    std::vector<double> part(size_t(nch), 0.0);
+    parallel_chunks(nch, [&](int64_t c) {
+        double s = 0.0;
+        const int32_t i1 = int32_t(std::min<int64_t>(n, (c + 1) * kRowChunk));
+        for (int32_t i = int32_t(c * kRowChunk); i < i1; ++i) {
+            int64_t ri = iperm ? iperm[i] : i;
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                int64_t cc = iperm ? iperm[col[k]] : col[k];
+                s += double(ri > cc ? ri - cc : cc - ri);
+            }
         }
-    }
+        part[size_t(c)] = s;
+    });
+    double s = 0.0;
+    for (double v : part) s += v;
     return s / double(nnz);
 }
 
@@ -309,37 +363,55 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
                          (long long)slots);
     L.slots = slots;
 
-    // ---- slot columns and the CSR-position -> slot map
+    // ---- slot columns and the CSR-position -> slot map (groups are
+    // independent: parallel over chunks of groups; the first duplicate
+    // column in group order is reported)
     L.slot_col.assign(size_t(slots), -1);
     L.map.assign(size_t(nnz), -1);
-    std::vector<std::pair<int32_t, int32_t>> ent;  // (layout col, local k)
-    for (const Group &g : L.groups) {
-        const int32_t lt = g.width_lt >> 24, T = 1 << lt;
-        const int64_t base = int64_t(g.base64) * kWave;
-        for (int32_t rr = 0; rr < g.nrows; ++rr) {
-            const int32_t orow = L.perm[g.row0 + rr];
-            const int32_t k0 = rowptr[orow], k1 = rowptr[orow + 1];
-            ent.clear();
-            for (int32_t k = k0; k < k1; ++k) {
-                int32_t c = L.symmetric_relabel ? L.iperm[col[k]] : col[k];
-                ent.emplace_back(c, k - k0);
-            }
-            std::sort(ent.begin(), ent.end());
-            for (size_t e = 1; e < ent.size(); ++e)
-                if (ent[e].first == ent[e - 1].first)
-                    return set_error(FS_E_BAD_CSR,
-                                     "duplicate column %d in row %d",
-                                     col[k0 + ent[e].second], orow);
-            for (size_t e = 0; e < ent.size(); ++e) {
-                const int32_t lane = rr * T + int32_t(e) % T;
-                const int32_t s = int32_t(e) / T;
-                const int64_t idx = base + int64_t(s / V) * kWave * V +
-                                    int64_t(lane) * V + s % V;
-                L.slot_col[size_t(idx)] = ent[e].first;
-                L.map[size_t(k0 + ent[e].second)] = int32_t(idx);
+    constexpr int64_t kGroupChunk = 1024;
+    const int64_t ngr = int64_t(L.groups.size());
+    const int64_t gch = (ngr + kGroupChunk - 1) / kGroupChunk;
+    std::vector<int64_t> dup(size_t(gch), -1);   // first bad CSR position
+    parallel_chunks(gch, [&](int64_t c) {
+        std::vector<std::pair<int32_t, int32_t>> ent;  // (layout col, k)
+        const int64_t g1 = std::min(ngr, (c + 1) * kGroupChunk);
+        for (int64_t gi = c * kGroupChunk; gi < g1; ++gi) {
+            const Group &g = L.groups[size_t(gi)];
+            const int32_t lt = g.width_lt >> 24, T = 1 << lt;
+            const int64_t base = int64_t(g.base64) * kWave;
+            for (int32_t rr = 0; rr < g.nrows; ++rr) {
+                const int32_t orow = L.perm[g.row0 + rr];
+                const int32_t k0 = rowptr[orow], k1 = rowptr[orow + 1];
+                ent.clear();
+                for (int32_t k = k0; k < k1; ++k) {
+                    int32_t cc = L.symmetric_relabel ? L.iperm[col[k]] : col[k];
+                    ent.emplace_back(cc, k - k0);
+                }
+                std::sort(ent.begin(), ent.end());
+                for (size_t e = 1; e < ent.size(); ++e)
+                    if (ent[e].first == ent[e - 1].first) {
+                        dup[size_t(c)] = k0 + ent[e].second;
+                        return;
+                    }
+                for (size_t e = 0; e < ent.size(); ++e) {
+                    const int32_t lane = rr * T + int32_t(e) % T;
+                    const int32_t sl = int32_t(e) / T;
+                    const int64_t idx = base + int64_t(sl / V) * kWave * V +
+                                        int64_t(lane) * V + sl % V;
+                    L.slot_col[size_t(idx)] = ent[e].first;
+                    L.map[size_t(k0 + ent[e].second)] = int32_t(idx);
+                }
             }
         }
-    }
+    });
+    for (int64_t c = 0; c < gch; ++c)
+        if (dup[size_t(c)] >= 0) {
+            const int64_t k = dup[size_t(c)];
+            const int32_t row = int32_t(std::upper_bound(rowptr, rowptr + n_rows + 1,
+                                                         int32_t(k)) - rowptr) - 1;
+            return set_error(FS_E_BAD_CSR, "duplicate column %d in row %d",
+                             col[k], row);
+        }
     return FS_OK;
 }
 
