@@ -170,6 +170,8 @@ def bench_serving(fs, W, oracle, d, torch, n_req=32, lam_factors=(1, 2, 4)):
         alone.append(X)
     total_k = sum(k for _, k, _ in reqs)
     mu = n_req / sum(service)                   # requests per second
+    log("serving: %d requests served one at a time in %.1f s"
+        % (n_req, sum(service)))
     out = {"pool_rows": [A.n_rows for A in pool],
            "pool_nnz": [A.nnz for A in pool], "requests": n_req,
            "rhs_total": total_k,
@@ -205,6 +207,7 @@ def bench_serving(fs, W, oracle, d, torch, n_req=32, lam_factors=(1, 2, 4)):
         same = all(torch.equal(xs[dd["req_id"]][1], alone[xs[dd["req_id"]][0]])
                    for dd in done)
         same_all &= same
+        log("serving: lambda = %.2f mu done in %.1f s" % (f, makespan))
         out["by_lambda"].append({
             "lambda_over_mu": f, "lambda_req_per_s": lam,
             "server": {"p50_ms": percentile(lat_s, 50) * 1e3,
@@ -425,6 +428,10 @@ def main():
     ap.add_argument("--no-largest", action="store_true",
                     help="skip the largest sweep matrix (S12, 156M nnz)")
     ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--serving-full", action="store_true",
+                    help="only the serving experiment: 500 requests per "
+                         "arrival rate, lambda/mu in {0.25, 0.5, 0.75, "
+                         "0.9, 1, 1.5, 2}, one JSON line")
     ap.add_argument("--sweep", action="store_true",
                     help="only the sparsity sweep: every sweep matrix, "
                          "natural and random numbering, one JSON line")
@@ -448,6 +455,15 @@ def main():
     dev = torch.device("cuda:0")
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     stream = torch.cuda.current_stream()
+
+    if args.serving_full:
+        srv = bench_serving(fs, W, oracle, d, torch, n_req=500,
+                            lam_factors=(0.25, 0.5, 0.75, 0.9, 1.0, 1.5, 2.0))
+        print(json.dumps({"metric": "served CG solves: p50/p99 latency and "
+                                    "solves/s vs one-at-a-time FP64 CG",
+                          "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                          "serving": srv}), flush=True)
+        return
 
     if args.sweep:
         rows = run_sweep(fs, W, oracle, torch, d, 50, 5, stream)
