@@ -85,7 +85,9 @@ typedef struct fs_csr_opts {
                               FS_REORDER_USER: new row i is old row perm[i] */
     int32_t sort_window;   /* rows are ordered longest-first (stable) inside
                               consecutive windows of this many rows, after
-                              the reordering; 1 disables; 0 = default 256  */
+                              the reordering; 1 disables; 0 = auto: the
+                              narrowest of 256, 1024, 4096, 16384 whose
+                              padded slot count is within 2% of the fewest */
     int32_t threshold;     /* most slots one lane may own before the row is
                               spread over more lanes; 0 = default 48       */
     int32_t lanes_min;     /* lanes per row bounds, powers of two in 1..64; */

@@ -103,7 +103,7 @@ fs_status csr_opts_default(fs_csr_opts *o)
     if (!o) return set_error(FS_E_ARG, "NULL opts");
     std::memset(o, 0, sizeof *o);
     o->reorder = FS_REORDER_AUTO;
-    o->sort_window = 256;
+    o->sort_window = 0;
     o->threshold = 48;
     o->lanes_min = 1;
     o->lanes_max = 64;

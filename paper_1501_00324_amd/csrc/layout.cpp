@@ -407,7 +407,6 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
                              col[k], (long long)k);
 
     const bool square = n_rows == n_cols;
-    int32_t sort_window = o.sort_window > 0 ? o.sort_window : 256;
     int32_t threshold = o.threshold > 0 ? o.threshold : 48;
     int32_t tmin = o.lanes_min > 0 ? o.lanes_min : 1;
     int32_t tmax = o.lanes_max > 0 ? o.lanes_max : 64;
@@ -458,17 +457,75 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
         return set_error(FS_E_ARG, "unknown reorder option %d", o.reorder);
     }
 
-    // ---- longest-first inside windows (stable, keeps locality order)
-    if (sort_window > 1) {
-        for (int64_t w0 = 0; w0 < n_rows; w0 += sort_window) {
-            int64_t w1 = std::min<int64_t>(n_rows, w0 + sort_window);
-            std::stable_sort(L.perm.begin() + w0, L.perm.begin() + w1,
-                             [&](int32_t a, int32_t b) {
-                                 return rowptr[a + 1] - rowptr[a] >
-                                        rowptr[b + 1] - rowptr[b];
-                             });
+    // ---- longest-first inside windows (stable, keeps locality order),
+    // then row groups: one wavefront, T lanes per row, 64/T rows
+    struct Raw { int32_t row0, rows, w, lt; };
+    struct Plan {
+        std::vector<int32_t> perm;
+        std::vector<Raw> raw;
+        int64_t slots1 = 0, slots2 = 0;
+    };
+    auto make_plan = [&](int32_t window, Plan &P) {
+        P.perm = L.perm;
+        if (window > 1) {
+            for (int64_t w0 = 0; w0 < n_rows; w0 += window) {
+                int64_t w1 = std::min<int64_t>(n_rows, w0 + window);
+                std::stable_sort(P.perm.begin() + w0, P.perm.begin() + w1,
+                                 [&](int32_t a, int32_t b) {
+                                     return rowptr[a + 1] - rowptr[a] >
+                                            rowptr[b + 1] - rowptr[b];
+                                 });
+            }
         }
+        auto len = [&](int32_t layout_row) {
+            int32_t r = P.perm[layout_row];
+            return rowptr[r + 1] - rowptr[r];
+        };
+        P.raw.clear();
+        P.slots1 = P.slots2 = 0;
+        for (int32_t i = 0; i < n_rows;) {
+            int32_t T = tmin, rows = 0, w = 0;
+            while (true) {
+                rows = std::min<int32_t>(kWave / T, n_rows - i);
+                int32_t maxlen = 0;
+                for (int32_t j = 0; j < rows; ++j)
+                    maxlen = std::max(maxlen, len(i + j));
+                w = (maxlen + T - 1) / T;
+                if (w <= threshold || T >= tmax) break;
+                T *= 2;
+            }
+            int32_t lt = 0;
+            while ((1 << lt) < T) ++lt;
+            P.raw.push_back(Raw{i, rows, w, lt});
+            P.slots1 += int64_t(w) * kWave;
+            P.slots2 += int64_t((w + 1) / 2 * 2) * kWave;
+            i += rows;
+        }
+    };
+    Plan plan;
+    if (o.sort_window > 0) {
+        make_plan(o.sort_window, plan);
+    } else {
+        // auto window: sorting within wider windows lowers the padding of
+        // matrices whose row lengths vary a lot locally (high-degree
+        // nodes), at some cost in locality; take the narrowest window whose
+        // slot count is within 2% of the fewest
+        const int32_t cand[] = {256, 1024, 4096, 16384};
+        std::vector<Plan> plans(4);
+        int64_t best = INT64_MAX;
+        for (int c = 0; c < 4; ++c) {
+            make_plan(cand[c], plans[size_t(c)]);
+            best = std::min(best, plans[size_t(c)].slots1);
+            if (cand[c] >= n_rows) break;
+        }
+        for (int c = 0; c < 4; ++c)
+            if (!plans[size_t(c)].raw.empty() || n_rows == 0)
+                if (double(plans[size_t(c)].slots1) <= 1.02 * double(best)) {
+                    plan = std::move(plans[size_t(c)]);
+                    break;
+                }
     }
+    L.perm = std::move(plan.perm);
     L.iperm.assign(size_t(n_rows), 0);
     L.identity = true;
     for (int32_t i = 0; i < n_rows; ++i) {
@@ -479,32 +536,8 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
     L.band_before = square ? mean_band(n_rows, rowptr, col, nullptr) : 0.0;
     L.band_after = square ? mean_band(n_rows, rowptr, col, L.iperm.data())
                           : 0.0;
-
-    // ---- row groups: one wavefront, T lanes per row, 64/T rows
-    auto len = [&](int32_t layout_row) {
-        int32_t r = L.perm[layout_row];
-        return rowptr[r + 1] - rowptr[r];
-    };
-    struct Raw { int32_t row0, rows, w, lt; };
-    std::vector<Raw> raw;
-    int64_t slots1 = 0, slots2 = 0;
-    for (int32_t i = 0; i < n_rows;) {
-        int32_t T = tmin, rows = 0, w = 0;
-        while (true) {
-            rows = std::min<int32_t>(kWave / T, n_rows - i);
-            int32_t maxlen = 0;
-            for (int32_t j = 0; j < rows; ++j) maxlen = std::max(maxlen, len(i + j));
-            w = (maxlen + T - 1) / T;
-            if (w <= threshold || T >= tmax) break;
-            T *= 2;
-        }
-        int32_t lt = 0;
-        while ((1 << lt) < T) ++lt;
-        raw.push_back(Raw{i, rows, w, lt});
-        slots1 += int64_t(w) * kWave;
-        slots2 += int64_t((w + 1) / 2 * 2) * kWave;
-        i += rows;
-    }
+    const std::vector<Raw> &raw = plan.raw;
+    const int64_t slots1 = plan.slots1, slots2 = plan.slots2;
     // two slots per load halves the load instructions; one slot per load
     // avoids rounding each lane's slot count up to even.  Auto keeps the
     // wide loads unless they cost more than 6% extra padded slots.
