@@ -553,8 +553,11 @@ def main():
         cg.update(precond="jacobi", rtol=1e-8)
         log("cg fp64: %s" % json.dumps(cg))
         ir = {}
-        for name, prec in (("f32", fs.PREC_IR_F32), ("bf16", fs.PREC_IR_BF16)):
-            xl, r = timed_solve(reps=2, precision=prec, inner_rtol=1e-2)
+        for name, prec, rs in (("f32", fs.PREC_IR_F32, 0),
+                               ("f32_restart", fs.PREC_IR_F32, 1),
+                               ("bf16", fs.PREC_IR_BF16, 0)):
+            xl, r = timed_solve(reps=2, precision=prec, inner_rtol=1e-2,
+                                ir_restart=rs)
             r["forward_err_vs_fp64"] = float(np.linalg.norm(xl - x64) /
                                              np.linalg.norm(x64))
             r["speedup_vs_fp64"] = cg["ms"] / r["ms"]

@@ -259,7 +259,11 @@ typedef struct fs_cg_opts {
     int32_t x0_zero;      /* 1: start from x = 0 and ignore x on input      */
     int32_t use_graph;    /* 1: replay chunks as HIP graphs (default 1)    */
     int32_t max_outer;    /* IR: refinement steps; 0 = default 50           */
-    int32_t reserved[6];  /* must be zero                                    */
+    int32_t ir_restart;   /* IR: 0 (default) keeps the inner search
+                             direction from step to step (the FP64
+                             residual replaces the inner one); 1 restarts
+                             the inner CG from zero at every step           */
+    int32_t reserved[5];  /* must be zero                                    */
 } fs_cg_opts;
 
 fs_status cg_opts_default(fs_cg_opts *o);

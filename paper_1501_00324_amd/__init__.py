@@ -67,7 +67,8 @@ class CgOpts(C.Structure):
                 ("precond", C.c_int32), ("precision", C.c_int32),
                 ("inner_rtol", C.c_double), ("check_every", C.c_int32),
                 ("x0_zero", C.c_int32), ("use_graph", C.c_int32),
-                ("max_outer", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("max_outer", C.c_int32), ("ir_restart", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class CgInfo(C.Structure):

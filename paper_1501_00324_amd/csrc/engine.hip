@@ -457,7 +457,11 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(
 // and b.b.  MODE 0 starts a solve (writes r and p = z, sets the column
 // state); MODE 1 checks the columns whose recurrence residual met the
 // tolerance against the true residual (writes r only for them; residual
-// replacement when the true residual is too large); MODE 2 only measures.
+// replacement when the true residual is too large); MODE 2 only measures;
+// MODE 3 rebases the columns whose recurrence residual met the tolerance
+// on a new right-hand side b (as MODE 1, and the tolerance becomes
+// rtol |b_new|): the search direction is kept, so a refinement step
+// continues the Krylov iteration instead of restarting it.
 template <typename VT, typename ST, int V, int KM, bool XZ, int MODE>
 __global__ __launch_bounds__(kBlock) void k_residual(
     const SysDesc *__restrict__ sys, const int *__restrict__ smap)
@@ -475,7 +479,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(
 #pragma unroll
     for (int c = 0; c < KM; ++c)
         wr[c] = c < k && (MODE == 0 ||
-                          (MODE == 1 && S.cs[c].status == CG_RECURRENCE_MET));
+                          ((MODE == 1 || MODE == 3) &&
+                           S.cs[c].status == CG_RECURRENCE_MET));
     const int g0 = int(long(lb) * S.ngroups / nb);
     const int g1 = int(long(lb + 1) * S.ngroups / nb);
     const int lane = threadIdx.x & (kWave - 1);
@@ -520,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_residual(
     const int2 sc = cmap[blockIdx.x];
     const SysDesc &S = sys[sc.x];
     ColState &cs = S.cs[sc.y];
-    if (MODE == 1 && cs.status != CG_RECURRENCE_MET) {
+    if ((MODE == 1 || MODE == 3) && cs.status != CG_RECURRENCE_MET) {
         if (threadIdx.x == 0) cs.pending = 0;
         return;
     }
@@ -542,8 +547,12 @@ __global__ __launch_bounds__(kBlock) void k_fin_residual(
         if (bb == 0.0 || rr <= cs.tol2) cs.status = CG_CONVERGED;
         else if (!isfinite(rr) || !isfinite(rz)) cs.status = CG_BREAKDOWN;
         else cs.status = CG_RUNNING;
-    } else if (MODE == 1) {
+    } else if (MODE == 1 || MODE == 3) {
         cs.pending = 0;
+        if (MODE == 3) {
+            cs.bnorm2 = bb;
+            cs.tol2 = S.rtol * S.rtol * bb;
+        }
         if (rr <= cs.tol2) {
             cs.status = CG_CONVERGED;
             return;
@@ -709,10 +718,14 @@ static void residual_mode(const EngineLaunch &L, int mode, hipStream_t s)
         hipLaunchKernelGGL((k_residual<VT, ST, V, KM, XZ, 1>), g, b, 0, s,
                            L.sys, L.smap);
         hipLaunchKernelGGL(k_fin_residual<1>, f, b, 0, s, L.sys, L.cmap);
-    } else {
+    } else if (mode == 2) {
         hipLaunchKernelGGL((k_residual<VT, ST, V, KM, XZ, 2>), g, b, 0, s,
                            L.sys, L.smap);
         hipLaunchKernelGGL(k_fin_residual<2>, f, b, 0, s, L.sys, L.cmap);
+    } else {
+        hipLaunchKernelGGL((k_residual<VT, ST, V, KM, XZ, 3>), g, b, 0, s,
+                           L.sys, L.smap);
+        hipLaunchKernelGGL(k_fin_residual<3>, f, b, 0, s, L.sys, L.cmap);
     }
 }
 

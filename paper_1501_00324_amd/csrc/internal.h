@@ -116,7 +116,8 @@ int32_t engine_vec_blocks(int32_t n);
 // Q = A P with p.q, then x/r update with r.z and r.r, then the p update.
 hipError_t engine_iteration(const EngineLaunch &L, hipStream_t s);
 // mode 0 (start: r = b - A x, p = z, sets the per-column state), 1 (true
-// residual check with replacement), 2 (measure |b - A x| only).
+// residual check with replacement), 2 (measure |b - A x| only), 3 (rebase
+// the columns that met their tolerance on a new b, keeping p).
 hipError_t engine_residual(const EngineLaunch &L, int32_t mode,
                            bool x_zero, hipStream_t s);
 // p = z + beta p for the columns whose residual was just replaced.

@@ -456,6 +456,30 @@ fs_status solve_f64(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
     return ret;
 }
 
+// Start a batch's CG from x = 0 without iterating: Jacobi scaling (checked)
+// and the start residual r = b, p = z.
+fs_status start_inner(Batch &B, bool precond, hipStream_t s)
+{
+    FS_TRY(batch_build(B, s));
+    if (precond) {
+        for (CgSys *S : B.members)
+            FS_HIP_TRY(hipMemsetAsync(S->bad, 0, sizeof(int32_t), s));
+        FS_HIP_TRY(engine_diag_inv(B.L, s));
+        for (CgSys *S : B.members) {
+            int32_t bad = 0;
+            FS_HIP_TRY(hipMemcpyAsync(&bad, S->bad, sizeof bad,
+                                      hipMemcpyDeviceToHost, s));
+            FS_HIP_TRY(hipStreamSynchronize(s));
+            if (bad)
+                return set_error(FS_E_ARG,
+                                 "Jacobi preconditioner: %d rows with a zero "
+                                 "or non-finite diagonal", bad);
+        }
+    }
+    FS_HIP_TRY(engine_residual(B.L, 0, true, s));
+    return batch_read_states(B, s);
+}
+
 // Mixed-precision iterative refinement: FP64 residual and update, inner CG
 // on the FP32 / BF16 copy of A with float vectors.
 fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
@@ -528,19 +552,52 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
         for (int32_t c = 0; c < k; ++c) last[size_t(c)] = BO.h_stage[c];
         prev_rr = rr;
         if (done || outer >= o.max_outer || inner_total >= o.maxit) break;
-        // inner solve A_lo d = r in single precision from d = 0
+        // inner solve A_lo d = r in single precision, d from 0
+        if (!o.ir_restart)   // columns done in FP64 get a zero inner b
+            for (int32_t c = 0; c < k; ++c)
+                if (BO.h_stage[c].status == CG_CONVERGED)
+                    FS_HIP_TRY(hipMemset2DAsync(
+                        static_cast<double *>(Out.r) + c,
+                        sizeof(double) * size_t(k), 0, sizeof(double),
+                        size_t(Out.n), s));
         FS_HIP_TRY(to_f32(nk, static_cast<const double *>(Out.r),
                           static_cast<float *>(In.b), s));
         FS_HIP_TRY(hipMemsetAsync(In.x, 0, sizeof(float) * size_t(nk), s));
-        In.maxit = std::max(1, o.maxit - inner_total);
-        FS_TRY(run_batch(BI, o.check_every, o.use_graph != 0, true, s));
         int32_t it = 0;
         inner_bad = false;
-        for (int32_t c = 0; c < k; ++c) {
-            it = std::max(it, BI.h_stage[c].iter);
-            if (BI.h_stage[c].status == CG_BREAKDOWN) inner_bad = true;
+        if (o.ir_restart) {
+            // classic refinement: a fresh inner CG every step
+            In.maxit = std::max(1, o.maxit - inner_total);
+            FS_TRY(run_batch(BI, o.check_every, o.use_graph != 0, true, s));
+            for (int32_t c = 0; c < k; ++c)
+                it = std::max(it, BI.h_stage[c].iter);
+            inner_total += it;
+        } else {
+            // one inner CG across all steps: the first step starts it, later
+            // steps rebase the columns that met the inner tolerance on the
+            // new residual and keep their search directions
+            if (outer == 0) {
+                In.maxit = o.maxit;
+                FS_TRY(start_inner(BI, o.precond != 0, s));
+            } else {
+                FS_HIP_TRY(engine_residual(BI.L, 3, true, s));
+                FS_TRY(batch_read_states(BI, s));
+                bool pend = false;
+                for (int32_t c = 0; c < k; ++c)
+                    pend |= BI.h_stage[c].pending != 0;
+                if (pend) FS_HIP_TRY(engine_pupdate_pending(BI.L, s));
+            }
+            while (any_status(BI, CG_RUNNING)) {
+                FS_TRY(batch_iterations(BI, o.check_every, o.use_graph != 0,
+                                        s));
+                FS_TRY(batch_read_states(BI, s));
+            }
+            for (int32_t c = 0; c < k; ++c)
+                it = std::max(it, BI.h_stage[c].iter);
+            inner_total = it;
         }
-        inner_total += it;
+        for (int32_t c = 0; c < k; ++c)
+            if (BI.h_stage[c].status == CG_BREAKDOWN) inner_bad = true;
         ++outer;
         FS_HIP_TRY(add_f32(nk, 1.0, static_cast<const float *>(In.x),
                            static_cast<double *>(Out.x), s));

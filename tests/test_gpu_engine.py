@@ -197,13 +197,15 @@ IR_CASES = [
 
 @pytest.mark.parametrize("name,gen", IR_CASES, ids=[c[0] for c in IR_CASES])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_ir_reaches_fp64_residual(fs, orc, name, gen, prec):
+@pytest.mark.parametrize("restart", [0, 1])
+def test_ir_reaches_fp64_residual(fs, orc, name, gen, prec, restart):
     A = gen()
     b = W.random_vector(A.n_rows, 46, W.BVEC)
-    note("ir %s %s" % (name, prec))
+    note("ir %s %s restart=%d" % (name, prec, restart))
     M = make(A)
     p = fs.PREC_IR_F32 if prec == "f32" else fs.PREC_IR_BF16
-    x, info = fs.cg_solve(M, dev(b), precond=1, precision=p, inner_rtol=1e-2)
+    x, info = fs.cg_solve(M, dev(b), precond=1, precision=p, inner_rtol=1e-2,
+                          ir_restart=restart)
     xg = host(x)
     assert info["status"] == fs.FS_OK, info
     assert info["outer"] >= 2

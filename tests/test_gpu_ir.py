@@ -43,13 +43,14 @@ def rough_1d(n_el, seed):
                np.array(cols, np.int32), np.array(vals))
 
 
-def test_bf16_refinement_stops_when_it_stalls(fs, orc):
+@pytest.mark.parametrize("restart", [0, 1])
+def test_bf16_refinement_stops_when_it_stalls(fs, orc, restart):
     A = rough_1d(4000, 36)
     b = W.random_vector(A.n_rows, 36, W.BVEC)
-    note("ir bf16 stall")
+    note("ir bf16 stall restart=%d" % restart)
     M = make(A)
     x, info = fs.cg_solve(M, dev(b), precond=1, precision=fs.PREC_IR_BF16,
-                          inner_rtol=1e-2, check=False)
+                          inner_rtol=1e-2, check=False, ir_restart=restart)
     # the BF16 copy of so ill-conditioned a matrix need not even be positive
     # definite: the inner solve may break down (FS_E_BREAKDOWN) or only stall
     assert info["status"] in (fs.FS_E_NOT_CONVERGED, fs.FS_E_BREAKDOWN)
