@@ -523,6 +523,11 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
     // need not be positive definite when A is ill-conditioned); its partial
     // correction is still applied, and the residual test below decides
     bool x_zero = o.x0_zero != 0, inner_bad = false, stalled = false;
+    // fresh: the next step starts a new inner CG (always with ir_restart;
+    // otherwise at the first step, and again after a step with a kept
+    // search direction failed to lower the FP64 residual)
+    bool fresh = true, last_fresh = false;
+    int32_t inner_base = 0;    // inner iterations before the current inner CG
     std::vector<ColState> last(static_cast<size_t>(k));
     double prev_rr = 0.0;
     for (;;) {
@@ -537,67 +542,76 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
             rr += BO.h_stage[c].rr_true;
         }
         if (outer > 0 && !done && !(rr < prev_rr)) {
-            // the last correction did not reduce the FP64 residual: the
+            // the last correction did not reduce the FP64 residual: undo it
+            // and re-measure.  After a fresh inner solve this means the
             // low-precision matrix is too far from A for refinement to
-            // converge (rounding error times condition number >= 1).  Undo
-            // it, re-measure, and stop.
+            // converge (rounding error times condition number >= 1): stop.
+            // After a step that kept the search direction, retry once with
+            // a fresh inner solve.
             FS_HIP_TRY(add_f32(nk, -1.0, static_cast<const float *>(In.x),
                                static_cast<double *>(Out.x), s));
             FS_HIP_TRY(engine_residual(BO.L, 0, false, s));
             FS_TRY(batch_read_states(BO, s));
             for (int32_t c = 0; c < k; ++c) last[size_t(c)] = BO.h_stage[c];
-            stalled = true;
-            break;
+            if (o.ir_restart || last_fresh) {
+                stalled = true;
+                break;
+            }
+            fresh = true;
+            done = false;
+        } else {
+            for (int32_t c = 0; c < k; ++c) last[size_t(c)] = BO.h_stage[c];
+            prev_rr = rr;
         }
-        for (int32_t c = 0; c < k; ++c) last[size_t(c)] = BO.h_stage[c];
-        prev_rr = rr;
         if (done || outer >= o.max_outer || inner_total >= o.maxit) break;
-        // inner solve A_lo d = r in single precision, d from 0
-        if (!o.ir_restart)   // columns done in FP64 get a zero inner b
-            for (int32_t c = 0; c < k; ++c)
-                if (BO.h_stage[c].status == CG_CONVERGED)
-                    FS_HIP_TRY(hipMemset2DAsync(
-                        static_cast<double *>(Out.r) + c,
-                        sizeof(double) * size_t(k), 0, sizeof(double),
-                        size_t(Out.n), s));
+        // inner solve A_lo d = r in single precision, d from 0; columns done
+        // in FP64 get a zero inner b (their inner CG stops at once)
+        for (int32_t c = 0; c < k; ++c)
+            if (BO.h_stage[c].status == CG_CONVERGED)
+                FS_HIP_TRY(hipMemset2DAsync(
+                    static_cast<double *>(Out.r) + c,
+                    sizeof(double) * size_t(k), 0, sizeof(double),
+                    size_t(Out.n), s));
         FS_HIP_TRY(to_f32(nk, static_cast<const double *>(Out.r),
                           static_cast<float *>(In.b), s));
         FS_HIP_TRY(hipMemsetAsync(In.x, 0, sizeof(float) * size_t(nk), s));
-        int32_t it = 0;
         inner_bad = false;
-        if (o.ir_restart) {
-            // classic refinement: a fresh inner CG every step
-            In.maxit = std::max(1, o.maxit - inner_total);
-            FS_TRY(run_batch(BI, o.check_every, o.use_graph != 0, true, s));
-            for (int32_t c = 0; c < k; ++c)
-                it = std::max(it, BI.h_stage[c].iter);
-            inner_total += it;
+        if (fresh || o.ir_restart) {
+            inner_base = inner_total;
+            In.maxit = std::max(1, o.maxit - inner_base);
+            FS_TRY(start_inner(BI, o.precond != 0, s));
+            fresh = false;
+            last_fresh = true;
         } else {
-            // one inner CG across all steps: the first step starts it, later
-            // steps rebase the columns that met the inner tolerance on the
-            // new residual and keep their search directions
-            if (outer == 0) {
-                In.maxit = o.maxit;
-                FS_TRY(start_inner(BI, o.precond != 0, s));
-            } else {
-                FS_HIP_TRY(engine_residual(BI.L, 3, true, s));
+            // rebase the columns that met the inner tolerance on the new
+            // residual, keeping their search directions
+            FS_HIP_TRY(engine_residual(BI.L, 3, true, s));
+            FS_TRY(batch_read_states(BI, s));
+            bool pend = false;
+            for (int32_t c = 0; c < k; ++c) pend |= BI.h_stage[c].pending != 0;
+            if (pend) FS_HIP_TRY(engine_pupdate_pending(BI.L, s));
+            last_fresh = false;
+        }
+        while (any_status(BI, CG_RUNNING)) {
+            FS_TRY(batch_iterations(BI, o.check_every, o.use_graph != 0, s));
+            FS_TRY(batch_read_states(BI, s));
+            if (o.ir_restart && any_status(BI, CG_RECURRENCE_MET)) {
+                // classic refinement confirms the inner solve against its own
+                // true residual (with replacement) like a plain solve
+                FS_HIP_TRY(engine_residual(BI.L, 1, false, s));
                 FS_TRY(batch_read_states(BI, s));
                 bool pend = false;
                 for (int32_t c = 0; c < k; ++c)
                     pend |= BI.h_stage[c].pending != 0;
                 if (pend) FS_HIP_TRY(engine_pupdate_pending(BI.L, s));
             }
-            while (any_status(BI, CG_RUNNING)) {
-                FS_TRY(batch_iterations(BI, o.check_every, o.use_graph != 0,
-                                        s));
-                FS_TRY(batch_read_states(BI, s));
-            }
-            for (int32_t c = 0; c < k; ++c)
-                it = std::max(it, BI.h_stage[c].iter);
-            inner_total = it;
         }
-        for (int32_t c = 0; c < k; ++c)
+        int32_t it = 0;
+        for (int32_t c = 0; c < k; ++c) {
+            it = std::max(it, BI.h_stage[c].iter);
             if (BI.h_stage[c].status == CG_BREAKDOWN) inner_bad = true;
+        }
+        inner_total = inner_base + it;
         ++outer;
         FS_HIP_TRY(add_f32(nk, 1.0, static_cast<const float *>(In.x),
                            static_cast<double *>(Out.x), s));
