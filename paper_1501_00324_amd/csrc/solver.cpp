@@ -528,6 +528,10 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
     // search direction failed to lower the FP64 residual)
     bool fresh = true, last_fresh = false;
     int32_t inner_base = 0;    // inner iterations before the current inner CG
+    // a kept-direction step may take at most twice the iterations of the
+    // last fresh step (and 64); past that it is cut and the next step is
+    // fresh (the low-precision copy may be indefinite, where CG stalls)
+    int32_t fresh_iters = 0;
     std::vector<ColState> last(static_cast<size_t>(k));
     double prev_rr = 0.0;
     for (;;) {
@@ -592,7 +596,19 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
             if (pend) FS_HIP_TRY(engine_pupdate_pending(BI.L, s));
             last_fresh = false;
         }
+        int32_t seg0 = 0;
+        for (int32_t c = 0; c < k; ++c)
+            seg0 = std::max(seg0, BI.h_stage[c].iter);
         while (any_status(BI, CG_RUNNING)) {
+            if (!last_fresh) {
+                int32_t itn = 0;
+                for (int32_t c = 0; c < k; ++c)
+                    itn = std::max(itn, BI.h_stage[c].iter);
+                if (itn - seg0 >= std::max(64, 2 * fresh_iters)) {
+                    fresh = true;      // cut: restart the inner CG next
+                    break;
+                }
+            }
             FS_TRY(batch_iterations(BI, o.check_every, o.use_graph != 0, s));
             FS_TRY(batch_read_states(BI, s));
             if (o.ir_restart && any_status(BI, CG_RECURRENCE_MET)) {
@@ -612,6 +628,12 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
             if (BI.h_stage[c].status == CG_BREAKDOWN) inner_bad = true;
         }
         inner_total = inner_base + it;
+        if (last_fresh) fresh_iters = it;
+        // columns stopped by the iteration limit cannot be rebased
+        for (int32_t c = 0; c < k; ++c)
+            if (BI.h_stage[c].status == CG_MAXIT ||
+                BI.h_stage[c].status == CG_BREAKDOWN)
+                fresh = true;
         ++outer;
         FS_HIP_TRY(add_f32(nk, 1.0, static_cast<const float *>(In.x),
                            static_cast<double *>(Out.x), s));
