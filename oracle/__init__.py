@@ -85,6 +85,9 @@ def _declare(L):
     L.or_ir_cg.argtypes = [i32, _i32p, _i32p, _f64p, _f32p, _f64p, _f64p,
                            i32, f64, f64, i32, i32, P(i32), P(i32), P(f64)]
     L.or_ir_cg.restype = C.c_int
+    L.or_ir_cg_keep.argtypes = [i32, _i32p, _i32p, _f64p, _f32p, _f64p, _f64p,
+                           i32, f64, f64, i32, i32, P(i32), P(i32), P(f64)]
+    L.or_ir_cg_keep.restype = C.c_int
 
 
 def _csr(A):
@@ -239,9 +242,10 @@ def pcg(A, b, x0=None, precond=1, rtol=1e-8, maxit=20000):
 
 
 def ir_cg(A, a_lo, b, x0=None, precond=1, rtol=1e-8, inner_rtol=1e-3,
-          max_outer=100, max_inner=20000):
+          max_outer=100, max_inner=20000, keep=False):
     """FP64-outer / FP32-inner refinement; returns
-    (x, status, outer, inner, relres)."""
+    (x, status, outer, inner, relres).  keep=True: one inner CG kept across
+    the steps (its residual replaced by the FP64 one at each step)."""
     L = load()
     rp, c, v = _csr(A)
     b = _f64(b)
@@ -250,7 +254,8 @@ def ir_cg(A, a_lo, b, x0=None, precond=1, rtol=1e-8, inner_rtol=1e-3,
     o = C.c_int32(0)
     i = C.c_int32(0)
     rr = C.c_double(0.0)
-    st = L.or_ir_cg(A.n_rows, rp, c, v, a, b, x, int(precond), float(rtol),
-                    float(inner_rtol), int(max_outer), int(max_inner),
-                    C.byref(o), C.byref(i), C.byref(rr))
+    fn = L.or_ir_cg_keep if keep else L.or_ir_cg
+    st = fn(A.n_rows, rp, c, v, a, b, x, int(precond), float(rtol),
+            float(inner_rtol), int(max_outer), int(max_inner),
+            C.byref(o), C.byref(i), C.byref(rr))
     return x, st, o.value, i.value, rr.value

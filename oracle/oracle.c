@@ -459,3 +459,99 @@ done:
     free(dinv);
     return status;
 }
+
+/* Refinement with a kept inner search direction: one FP32 CG runs across
+ * the refinement steps.  When its residual has fallen by inner_rtol, the
+ * correction d is added to x in FP64, the FP64 residual r = b - A x is
+ * taken, and the inner CG continues from d = 0 with its residual replaced
+ * by float(r): rho and beta are recomputed from the new residual and the
+ * search direction p = z + beta p is kept. */
+int or_ir_cg_keep(int32_t n, const int32_t *rowptr, const int32_t *col,
+                  const double *val, const float *a_lo, const double *b,
+                  double *x, int32_t precond, double rtol, double inner_rtol,
+                  int32_t max_outer, int32_t max_inner, int32_t *outer,
+                  int32_t *inner, double *relres)
+{
+    *outer = 0;
+    *inner = 0;
+    *relres = 0.0;
+    double bnorm = sqrt(dot(n, b, b));
+    if (bnorm == 0.0) {
+        for (int32_t i = 0; i < n; ++i)
+            x[i] = 0.0;
+        return OR_OK;
+    }
+    double *r64 = malloc(sizeof(double) * n);
+    float *d = malloc(sizeof(float) * n), *r = malloc(sizeof(float) * n);
+    float *z = malloc(sizeof(float) * n), *p = malloc(sizeof(float) * n);
+    float *q = malloc(sizeof(float) * n), *dinv = malloc(sizeof(float) * n);
+    int status = OR_NOT_CONVERGED;
+    for (int32_t i = 0; i < n; ++i) {
+        float dd = 0.0f;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (col[k] == i)
+                dd += a_lo[k];
+        if (precond && (dd == 0.0f || !isfinite(dd))) {
+            status = OR_ARG;
+            goto done;
+        }
+        dinv[i] = precond ? 1.0f / dd : 1.0f;
+    }
+    true_residual(n, rowptr, col, val, b, x, r64);
+    if (sqrt(dot(n, r64, r64)) <= rtol * bnorm) {
+        status = OR_OK;
+        goto done;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        d[i] = 0.0f;
+        r[i] = (float)r64[i];
+        z[i] = dinv[i] * r[i];
+        p[i] = z[i];
+    }
+    float rho = dotf(n, r, z);
+    float tol = (float)inner_rtol * sqrtf(dotf(n, r, r));
+    while (*inner < max_inner) {
+        or_spmv_f32(n, rowptr, col, a_lo, p, q);
+        *inner += 1;
+        float gamma = dotf(n, p, q);
+        if (!(gamma > 0.0f) || !isfinite(gamma)) {
+            status = OR_BREAKDOWN;
+            break;
+        }
+        float alpha = rho / gamma;
+        for (int32_t i = 0; i < n; ++i) {
+            d[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        if (sqrtf(dotf(n, r, r)) <= tol) {
+            /* FP64 steps: update and residual; then rebase the inner CG */
+            for (int32_t i = 0; i < n; ++i)
+                x[i] += (double)d[i];
+            *outer += 1;
+            true_residual(n, rowptr, col, val, b, x, r64);
+            if (sqrt(dot(n, r64, r64)) <= rtol * bnorm) {
+                status = OR_OK;
+                break;
+            }
+            if (*outer >= max_outer)
+                break;
+            for (int32_t i = 0; i < n; ++i) {
+                d[i] = 0.0f;
+                r[i] = (float)r64[i];
+            }
+            tol = (float)inner_rtol * sqrtf(dotf(n, r, r));
+        }
+        for (int32_t i = 0; i < n; ++i)
+            z[i] = dinv[i] * r[i];
+        float rho_new = dotf(n, r, z);
+        float beta = rho_new / rho;
+        rho = rho_new;
+        for (int32_t i = 0; i < n; ++i)
+            p[i] = z[i] + beta * p[i];
+    }
+done:
+    true_residual(n, rowptr, col, val, b, x, r64);
+    *relres = sqrt(dot(n, r64, r64)) / bnorm;
+    free(r64); free(d); free(r); free(z); free(p); free(q); free(dinv);
+    return status;
+}

@@ -427,7 +427,10 @@ def test_cg_warm_start_resume(orc):
 
 
 @pytest.mark.parametrize("kind", ["f32", "bf16"])
-def test_ir_cg_reaches_fp64_residual(orc, kind):
+@pytest.mark.parametrize("keep", [False, True])
+def test_ir_cg_reaches_fp64_residual(orc, kind, keep):
+    if keep and kind == "bf16":
+        pytest.skip("kept direction with BF16 values: see the stall test")
     A = W.tet_p1(6, "elastic", seed=(84, 0), bc="x0", permute=True)
     b = W.random_vector(A.n_rows, 84, W.BVEC)
     if kind == "f32":
@@ -435,13 +438,44 @@ def test_ir_cg_reaches_fp64_residual(orc, kind):
     else:
         a = orc.bf16_bits_to_f32(orc.round_bf16(A.val))
     x, st, outer, inner, rr = orc.ir_cg(A, a, b, precond=1, rtol=1e-8,
-                                        inner_rtol=1e-2)
+                                        inner_rtol=1e-2, keep=keep)
     assert st == orc.OK and rr <= 1e-8
     assert outer >= 2          # one low-precision solve cannot reach 1e-8
     D = A.to_dense()
     xs = np.linalg.solve(D, b)
     kappa = np.linalg.cond(D)
     assert np.linalg.norm(x - xs) <= 2e-8 * kappa * np.linalg.norm(xs)
+
+
+def test_ir_keep_direction_needs_about_the_fp64_iterations(orc):
+    """Keeping the inner search direction across refinement steps keeps the
+    Krylov space: FP32 refinement then needs about the iterations of the
+    FP64 solve, while restarting every step needs clearly more."""
+    A = W.tet_p1(10, "elastic", seed=(85, 0), bc="x0", permute=True)
+    b = W.random_vector(A.n_rows, 85, W.BVEC)
+    a = orc.round_f32(A.val)
+    _, st64, it64, _ = orc.pcg(A, b, precond=1)
+    _, stk, outk, ink, rrk = orc.ir_cg(A, a, b, inner_rtol=1e-2, keep=True)
+    _, str_, outr, inr, rrr = orc.ir_cg(A, a, b, inner_rtol=1e-2)
+    assert st64 == stk == str_ == orc.OK and rrk <= 1e-8 and rrr <= 1e-8
+    assert outk >= 3 and outr >= 3
+    assert ink <= 1.1 * it64 + 5
+    assert inr >= 1.2 * it64
+
+
+def test_ir_keep_direction_stalls_on_bf16(orc):
+    """With BF16 values the inner operator is too far from A for a search
+    direction kept across steps: the plain kept-direction method stagnates
+    (the library restarts the inner CG when a step fails), while restarted
+    refinement converges."""
+    A = W.tet_p1(6, "elastic", seed=(84, 0), bc="x0", permute=True)
+    b = W.random_vector(A.n_rows, 84, W.BVEC)
+    a = orc.bf16_bits_to_f32(orc.round_bf16(A.val))
+    _, stk, _, ink, rrk = orc.ir_cg(A, a, b, inner_rtol=1e-2, keep=True,
+                                    max_inner=3000)
+    _, str_, _, _, rrr = orc.ir_cg(A, a, b, inner_rtol=1e-2)
+    assert stk == orc.NOT_CONVERGED and rrk > 1e-8 and ink == 3000
+    assert str_ == orc.OK and rrr <= 1e-8
 
 
 def test_spmv_par_is_bitwise_spmv(orc):
