@@ -95,12 +95,16 @@ typedef struct fs_csr_opts {
     int32_t dtypes;        /* extra low-precision copies (FS_DT_F32/BF16)   */
     int32_t vec;           /* slots each lane loads at once: 1 or 2; 0 =
                               auto (2 unless it adds > 6% padded slots)    */
+    int32_t index_bits;    /* column indices in the slot stream: 0 = auto
+                              (16-bit offsets from a per-group base when
+                              every row group's columns span fewer than
+                              65535, else 32-bit); 32 = always 32-bit      */
     int32_t autotune;      /* 1: time the product for several lanes-per-row
                               and slots-per-load shapes on this matrix and
                               keep the fastest (results cached per matrix
                               signature for the process); lanes_min/max and
                               vec are then ignored                          */
-    int32_t reserved[6];   /* must be zero                                   */
+    int32_t reserved[5];   /* must be zero                                   */
 } fs_csr_opts;
 
 /* Fill *o with the defaults (AUTO reorder, window 256, threshold 48,
@@ -137,7 +141,8 @@ typedef struct fs_csr_stats {
     double padding;           /* (slots - nnz) / slots                      */
     int64_t bytes_algorithmic;/* 12 nnz + 8 n_cols + 8 n_rows: compulsory
                                  traffic of one FP64 product                */
-    int64_t bytes_layout;     /* 12 slots + 16 n_groups + 8 n_cols + 8 n_rows */
+    int64_t bytes_layout;     /* (8 + index bytes) slots + (16 or 20)
+                                 n_groups + 8 n_cols + 8 n_rows              */
     int32_t groups_by_lanes[7];/* groups with 1,2,4,...,64 lanes per row    */
     int32_t dtypes;           /* FS_DT_* copies held                        */
     int32_t vec;              /* slots per lane per load (1 or 2)           */
@@ -148,6 +153,8 @@ typedef struct fs_csr_stats {
     int32_t tuned;            /* 0 no, 1 tuned now, 2 from the tuning cache */
     int32_t tune_candidates;  /* layouts timed                              */
     double tune_best_us;      /* product time of the kept layout            */
+    int32_t index_bits;       /* 16 or 32: column index width in the slots  */
+    int32_t pad_;
 } fs_csr_stats;
 
 fs_status csr_info(fs_csr_t A, fs_csr_stats *st);
@@ -214,7 +221,7 @@ fs_status probe_read_bandwidth(const double *buf, int64_t n, double *sink,
  * the spmv result).  A, x and y are HOST arrays of m entries holding handles
  * and DEVICE vector pointers; all handles live on one device.  The y_i are
  * distinct and no x_i is any y_j; a handle may appear more than once.  The products of
- * up to 64 matrices share each launch (per-matrix descriptors are passed as
+ * up to 56 matrices share each launch (per-matrix descriptors are passed as
  * kernel arguments: nothing is allocated or copied to the device), so many
  * small matrices cost one launch latency instead of m.  m = 0 is a no-op.
  * Asynchronous on s; errors: FS_E_ARG (NULL entries, aliasing, mixed

@@ -38,7 +38,8 @@ class CsrOpts(C.Structure):
                 ("sort_window", C.c_int32), ("threshold", C.c_int32),
                 ("lanes_min", C.c_int32), ("lanes_max", C.c_int32),
                 ("dtypes", C.c_int32), ("vec", C.c_int32),
-                ("autotune", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("index_bits", C.c_int32), ("autotune", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class CsrStats(C.Structure):
@@ -52,7 +53,8 @@ class CsrStats(C.Structure):
                 ("mean_band_after", C.c_double),
                 ("t_build_ms", C.c_double), ("device_bytes", C.c_int64),
                 ("tuned", C.c_int32), ("tune_candidates", C.c_int32),
-                ("tune_best_us", C.c_double)]
+                ("tune_best_us", C.c_double), ("index_bits", C.c_int32),
+                ("pad_", C.c_int32)]
 
     def as_dict(self):
         d = {}

@@ -66,6 +66,7 @@ void free_handle(fs_csr *A)
     free_solver_state(A);
     dfree(A->d_groups); dfree(A->d_val); dfree(A->d_val_f32);
     dfree(A->d_val_bf16); dfree(A->d_col); dfree(A->d_map);
+    dfree(A->d_col16); dfree(A->d_gbase);
     dfree(A->d_perm); dfree(A->d_iperm); dfree(A->d_xtmp); dfree(A->d_Xtmp);
 }
 
@@ -167,6 +168,10 @@ fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
         (st = dalloc(&A->d_iperm, n_rows, acct)) ||
         (st = dalloc(&A->d_xtmp, n_cols, acct)))
         return fail(st);
+    if (L.index_bits == 16)
+        if ((st = dalloc(&A->d_col16, A->slots, acct)) ||
+            (st = dalloc(&A->d_gbase, A->n_groups, acct)))
+            return fail(st);
     if (o.dtypes & FS_DT_F32)
         if ((st = dalloc(&A->d_val_f32, A->slots, acct))) return fail(st);
     if (o.dtypes & FS_DT_BF16)
@@ -186,6 +191,14 @@ fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
                                      hipMemcpyHostToDevice, s));
         FS_CREATE_HIP(hipMemsetAsync(A->d_val, 0,
                                      sizeof(double) * size_t(A->slots), s));
+        if (A->d_col16) {
+            FS_CREATE_HIP(hipMemcpyAsync(A->d_col16, L.slot_c16.data(),
+                                         sizeof(uint16_t) * size_t(A->slots),
+                                         hipMemcpyHostToDevice, s));
+            FS_CREATE_HIP(hipMemcpyAsync(A->d_gbase, L.gbase.data(),
+                                         sizeof(int32_t) * L.gbase.size(),
+                                         hipMemcpyHostToDevice, s));
+        }
         if (A->d_val_f32)
             FS_CREATE_HIP(hipMemsetAsync(A->d_val_f32, 0,
                                          sizeof(float) * size_t(A->slots), s));
@@ -216,6 +229,7 @@ fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
     // info / permutation queries need on the host
     std::vector<int32_t>().swap(L.slot_col);
     std::vector<int32_t>().swap(L.map);
+    std::vector<uint16_t>().swap(L.slot_c16);
     *out = A;
     return FS_OK;
 }
@@ -463,8 +477,11 @@ fs_status csr_info(fs_csr_t A, fs_csr_stats *st)
     st->padding = A->slots ? double(A->slots - A->nnz) / double(A->slots) : 0.0;
     st->bytes_algorithmic = 12 * A->nnz + 8 * int64_t(A->n_cols) +
                             8 * int64_t(A->n_rows);
-    st->bytes_layout = 12 * A->slots + int64_t(sizeof(Group)) * A->n_groups +
+    const bool narrow = A->d_col16 != nullptr;
+    st->bytes_layout = (narrow ? 10 : 12) * A->slots +
+                       int64_t(sizeof(Group) + (narrow ? 4 : 0)) * A->n_groups +
                        8 * int64_t(A->n_cols) + 8 * int64_t(A->n_rows);
+    st->index_bits = narrow ? 16 : 32;
     for (int i = 0; i < 7; ++i) st->groups_by_lanes[i] = A->host.groups_by_lanes[i];
     st->dtypes = A->dtypes;
     st->vec = A->host.vec;

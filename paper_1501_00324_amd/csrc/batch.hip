@@ -1,5 +1,5 @@
 // Batched FP64 products: m independent y_i = A_i x_i (caller numbering),
-// a gather launch and a product launch per 64 matrices.  Small FEM
+// a gather launch and a product launch per 56 matrices.  Small FEM
 // matrices cannot fill 256 CUs on their own and pay the launch latency once
 // per product; here every matrix owns a contiguous range of workgroups of
 // one launch.  The per-matrix
@@ -26,7 +26,8 @@ struct GatherDesc {
 struct ProdDesc {
     const Group *groups;
     const double *val;
-    const int32_t *col;
+    const void *col;                   // 32-bit columns or 16-bit offsets
+    const int32_t *gbase;              // group bases of 16-bit offsets, or NULL
     const double *x;
     double *y;
     const int32_t *yperm;              // NULL: y in layout order
@@ -74,7 +75,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_batch(
     const Group gd = load_group(p.groups, g);
     const int lt = gd.width_lt >> 24;
     const double acc =
-        row_reduce(group_lane_sum<V>(gd, lane, p.val, p.col, p.x), lt);
+        p.gbase ? row_reduce(group_lane_sum<V, true>(gd, lane, p.val, p.col,
+                                                     load_gbase(p.gbase, g),
+                                                     p.x), lt)
+                : row_reduce(group_lane_sum<V, false>(gd, lane, p.val, p.col,
+                                                      0, p.x), lt);
     const int r = lane >> lt;
     if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
         const int row = gd.row0 + r;
@@ -132,7 +137,9 @@ hipError_t launch_spmv_batch(int32_t m, const fs_csr *const *A,
                 ProdDesc &d = pa.d[pa.m++];
                 d.groups = M->d_groups;
                 d.val = M->d_val;
-                d.col = M->d_col;
+                d.col = M->d_col16 ? static_cast<const void *>(M->d_col16)
+                                   : static_cast<const void *>(M->d_col);
+                d.gbase = M->d_col16 ? M->d_gbase : nullptr;
                 d.x = gathered(M) ? M->d_xtmp : x[i];
                 d.y = y[i];
                 d.yperm = M->host.identity ? nullptr : M->d_perm;

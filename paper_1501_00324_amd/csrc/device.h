@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -13,6 +14,7 @@ namespace {
 typedef double dv2 __attribute__((ext_vector_type(2)));
 typedef int iv2 __attribute__((ext_vector_type(2)));
 typedef float fv2 __attribute__((ext_vector_type(2)));
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kVecBlocks = 1024;   // max workgroups of the vector kernels
@@ -34,9 +36,41 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Slot element types for V slots per load: values, 32-bit columns, 16-bit
+// column offsets.
 template <int V> struct Slots;
-template <> struct Slots<1> { typedef double D; typedef int I; };
-template <> struct Slots<2> { typedef dv2 D; typedef iv2 I; };
+template <> struct Slots<1> { typedef double D; typedef int I; typedef uint16_t H; };
+template <> struct Slots<2> { typedef dv2 D; typedef iv2 I; typedef us2 H; };
+
+// Column index stream of a group: 32-bit layout columns (NARROW = false)
+// or 16-bit offsets from the group's base column gb, 0xffff marking
+// padding (NARROW = true).  Both decode to a layout column, -1 = padding.
+template <int V, bool NARROW> struct ColStream {
+    typedef typename std::conditional<NARROW, typename Slots<V>::H,
+                                      typename Slots<V>::I>::type P;
+    typedef typename std::conditional<NARROW, uint16_t, int32_t>::type E;
+    const P *p;
+    int gb;
+    __device__ __forceinline__ ColStream(const void *col, long base, int lane,
+                                         int gbase)
+        : p(reinterpret_cast<const P *>(static_cast<const E *>(col) + base) +
+            lane),
+          gb(gbase)
+    {
+    }
+    __device__ __forceinline__ P load(int j) const
+    {
+        return __builtin_nontemporal_load(p + long(j) * kWave);
+    }
+    __device__ __forceinline__ int get(const P &c, int t) const
+    {
+        int v;
+        if constexpr (V == 1) v = int(c);
+        else v = t ? int(c.y) : int(c.x);
+        if constexpr (NARROW) return v == 0xffff ? -1 : gb + v;
+        else return v;
+    }
+};
 
 // Padded slots (column -1) read x[0] (always in bounds: a matrix with
 // slots has at least one column) and the select drops the product, so an
@@ -52,49 +86,49 @@ __device__ __forceinline__ void slot_fma(int c, double a, const double *x,
 // matrix stream is loaded in batches of 8 slots (all column and value
 // loads of a batch issued before any gather) so that each wavefront keeps
 // ~12 KiB of the stream plus 512 gathers in flight.
-template <int V>
+template <int V, bool NARROW>
 __device__ __forceinline__ double group_lane_sum(const Group &g, int lane,
                                                  const double *__restrict__ val,
-                                                 const int *__restrict__ col,
+                                                 const void *__restrict__ col,
+                                                 int gb,
                                                  const double *__restrict__ x)
 {
     typedef typename Slots<V>::D D;
-    typedef typename Slots<V>::I I;
+    typedef ColStream<V, NARROW> CS;
     constexpr int U = 8 / V;
     const int width = g.width_lt & 0xffffff;
     const long base = long(g.base64) * kWave;
     const D *pv = reinterpret_cast<const D *>(val + base) + lane;
-    const I *pc = reinterpret_cast<const I *>(col + base) + lane;
+    const CS cs(col, base, lane, gb);
     const int nch = width / V;
     double acc0 = 0.0, acc1 = 0.0;
     int j = 0;
     for (; j + U <= nch; j += U) {
-        I c[U];
+        typename CS::P c[U];
         D a[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            c[u] = __builtin_nontemporal_load(pc + (j + u) * kWave);
+        for (int u = 0; u < U; ++u) c[u] = cs.load(j + u);
 #pragma unroll
         for (int u = 0; u < U; ++u)
             a[u] = __builtin_nontemporal_load(pv + (j + u) * kWave);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if constexpr (V == 1) {
-                slot_fma(c[u], a[u], x, (u & 1) ? acc1 : acc0);
+                slot_fma(cs.get(c[u], 0), a[u], x, (u & 1) ? acc1 : acc0);
             } else {
-                slot_fma(c[u].x, a[u].x, x, acc0);
-                slot_fma(c[u].y, a[u].y, x, acc1);
+                slot_fma(cs.get(c[u], 0), a[u].x, x, acc0);
+                slot_fma(cs.get(c[u], 1), a[u].y, x, acc1);
             }
         }
     }
     for (; j < nch; ++j) {
-        const I c = __builtin_nontemporal_load(pc + j * kWave);
+        const typename CS::P c = cs.load(j);
         const D a = __builtin_nontemporal_load(pv + j * kWave);
         if constexpr (V == 1) {
-            slot_fma(c, a, x, (j & 1) ? acc1 : acc0);
+            slot_fma(cs.get(c, 0), a, x, (j & 1) ? acc1 : acc0);
         } else {
-            slot_fma(c.x, a.x, x, acc0);
-            slot_fma(c.y, a.y, x, acc1);
+            slot_fma(cs.get(c, 0), a.x, x, acc0);
+            slot_fma(cs.get(c, 1), a.y, x, acc1);
         }
     }
     return acc0 + acc1;
@@ -116,6 +150,12 @@ __device__ __forceinline__ Group load_group(const Group *groups, int g)
     d.nrows = __builtin_amdgcn_readfirstlane(d.nrows);
     d.width_lt = __builtin_amdgcn_readfirstlane(d.width_lt);
     return d;
+}
+
+// Column base of group g for 16-bit column offsets (0 when there are none).
+__device__ __forceinline__ int load_gbase(const int32_t *gbase, int g)
+{
+    return gbase ? __builtin_amdgcn_readfirstlane(gbase[g]) : 0;
 }
 
 inline int vec_blocks(long n)

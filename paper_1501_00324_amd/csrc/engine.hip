@@ -37,8 +37,6 @@
 namespace fs {
 namespace {
 
-typedef unsigned short us2 __attribute__((ext_vector_type(2)));
-
 // Group-shaped grids give each wavefront one row group (as the plain
 // product does) up to this many blocks; larger matrices give a block a
 // contiguous run of groups.  A static split with several groups per
@@ -71,36 +69,26 @@ __device__ __forceinline__ void unpack(typename Pack<VT, V>::T a, ST (&o)[V])
     }
 }
 
-template <int V> __device__ __forceinline__ void unpack_col(
-    typename Slots<V>::I c, int (&o)[V])
-{
-    if constexpr (V == 1) {
-        o[0] = c;
-    } else {
-        o[0] = c.x;
-        o[1] = c.y;
-    }
-}
-
 // acc{0,1}[c] += a * X[col, c] over this lane's slots, even slots into
 // acc0, odd slots into acc1.  Padded slots (col -1) read row 0 of X and
 // drop the product through a select.
-template <typename VT, typename ST, int V, int KM>
+template <typename VT, typename ST, int V, int KM, bool N>
 __device__ __forceinline__ void lane_sums(const Group &g, int lane,
                                           const VT *__restrict__ val,
-                                          const int *__restrict__ col,
+                                          const void *__restrict__ col, int gb,
                                           const ST *__restrict__ X, int k,
                                           long ldx, ST (&acc0)[KM],
                                           ST (&acc1)[KM])
 {
     typedef typename Pack<VT, V>::T PV;
-    typedef typename Slots<V>::I PI;
+    typedef ColStream<V, N> CS;
+    typedef typename CS::P PI;
     constexpr int U0 = KM == 1 ? 8 : (KM == 2 ? 4 : 2);
     constexpr int U = U0 / V > 0 ? U0 / V : 1;
     const int width = g.width_lt & 0xffffff;
     const long base = long(g.base64) * kWave;
     const PV *pv = reinterpret_cast<const PV *>(val + base) + lane;
-    const PI *pc = reinterpret_cast<const PI *>(col + base) + lane;
+    const CS cs(col, base, lane, gb);
     const int nch = width / V;
     auto slot = [&](int c, ST a, bool odd) {
         const ST *xr = X + long(c < 0 ? 0 : c) * ldx;
@@ -118,30 +106,35 @@ __device__ __forceinline__ void lane_sums(const Group &g, int lane,
         PI c[U];
         PV a[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            c[u] = __builtin_nontemporal_load(pc + (j + u) * kWave);
+        for (int u = 0; u < U; ++u) c[u] = cs.load(j + u);
 #pragma unroll
         for (int u = 0; u < U; ++u)
             a[u] = __builtin_nontemporal_load(pv + (j + u) * kWave);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int cc[V];
             ST aa[V];
-            unpack_col<V>(c[u], cc);
             unpack<VT, ST, V>(a[u], aa);
 #pragma unroll
             for (int t = 0; t < V; ++t)
-                slot(cc[t], aa[t], ((j + u) * V + t) & 1);
+                slot(cs.get(c[u], t), aa[t], ((j + u) * V + t) & 1);
         }
     }
     for (; j < nch; ++j) {
-        int cc[V];
         ST aa[V];
-        unpack_col<V>(__builtin_nontemporal_load(pc + j * kWave), cc);
+        const PI c = cs.load(j);
         unpack<VT, ST, V>(__builtin_nontemporal_load(pv + j * kWave), aa);
 #pragma unroll
-        for (int t = 0; t < V; ++t) slot(cc[t], aa[t], (j * V + t) & 1);
+        for (int t = 0; t < V; ++t) slot(cs.get(c, t), aa[t], (j * V + t) & 1);
     }
+}
+
+// f(std::true_type) for 16-bit column offsets, else f(std::false_type);
+// the flag is uniform over a system, so the branch is too.
+template <class F>
+__device__ __forceinline__ void with_narrow(bool narrow, F &&f)
+{
+    if (narrow) f(std::true_type());
+    else f(std::false_type());
 }
 
 __device__ __forceinline__ bool any_running(const SysDesc &S)
@@ -235,22 +228,22 @@ __device__ __forceinline__ void store_col_partials(double (&v)[NVPC], int k,
 // X are read per instruction, each a contiguous run of KM values.  (A lane
 // gathering its own row of X would touch 64 cache lines per instruction.)
 // emit(row_in_group, q, value) is called once per (row, column < k).
-template <typename VT, typename ST, int V, int KM, class Emit>
+template <typename VT, typename ST, int V, int KM, bool N, class Emit>
 __device__ __forceinline__ void coop_group(const Group &g, int lane,
                                            const VT *__restrict__ val,
-                                           const int *__restrict__ col,
-                                           const ST *__restrict__ X, int k,
-                                           long ldx, Emit emit)
+                                           const void *__restrict__ col,
+                                           int gb, const ST *__restrict__ X,
+                                           int k, long ldx, Emit emit)
 {
     static_assert(KM > 1, "single-column products use lane_sums");
     typedef typename Pack<VT, V>::T PV;
-    typedef typename Slots<V>::I PI;
+    typedef ColStream<V, N> CS;
     constexpr int R = kWave / KM;
     const int q = lane % KM, m = lane / KM;
     const int width = g.width_lt & 0xffffff;
     const long base = long(g.base64) * kWave;
     const PV *pv = reinterpret_cast<const PV *>(val + base) + lane;
-    const PI *pc = reinterpret_cast<const PI *>(col + base) + lane;
+    const CS cs(col, base, lane, gb);
     ST acc[KM];
 #pragma unroll
     for (int r = 0; r < KM; ++r) acc[r] = ST(0);
@@ -258,7 +251,9 @@ __device__ __forceinline__ void coop_group(const Group &g, int lane,
     for (int j = 0; j < nch; ++j) {
         int cc[V];
         ST aa[V];
-        unpack_col<V>(__builtin_nontemporal_load(pc + j * kWave), cc);
+        const typename CS::P cv = cs.load(j);
+#pragma unroll
+        for (int t = 0; t < V; ++t) cc[t] = cs.get(cv, t);
         unpack<VT, ST, V>(__builtin_nontemporal_load(pv + j * kWave), aa);
 #pragma unroll
         for (int t = 0; t < V; ++t) {
@@ -325,27 +320,34 @@ __global__ __launch_bounds__(kBlock) void k_spmm_dot(
     const int g1 = int(long(lb + 1) * S.ngroups / nb);
     const int lane = threadIdx.x & (kWave - 1);
     double dot[1] = {0.0};
-    for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
-        const Group gd = load_group(S.groups, __builtin_amdgcn_readfirstlane(g));
-        if constexpr (KM == 1) {
-            ST a0[1] = {ST(0)}, a1[1] = {ST(0)};
-            lane_sums<VT, ST, V, 1>(gd, lane, val, S.col, P, 1, 1, a0, a1);
-            const int lt = gd.width_lt >> 24, r = lane >> lt;
-            const ST v = row_reduce(a0[0] + a1[0], lt);
-            if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
-                const long row = gd.row0 + r;
-                Q[row] = v;
-                dot[0] += double(P[row]) * double(v);
+    with_narrow(S.gbase != nullptr, [&](auto nt) {
+        constexpr bool N = decltype(nt)::value;
+        for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
+            const Group gd =
+                load_group(S.groups, __builtin_amdgcn_readfirstlane(g));
+            const int gb = N ? load_gbase(S.gbase, g) : 0;
+            if constexpr (KM == 1) {
+                ST a0[1] = {ST(0)}, a1[1] = {ST(0)};
+                lane_sums<VT, ST, V, 1, N>(gd, lane, val, S.cstream, gb, P, 1,
+                                           1, a0, a1);
+                const int lt = gd.width_lt >> 24, r = lane >> lt;
+                const ST v = row_reduce(a0[0] + a1[0], lt);
+                if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
+                    const long row = gd.row0 + r;
+                    Q[row] = v;
+                    dot[0] += double(P[row]) * double(v);
+                }
+            } else {
+                coop_group<VT, ST, V, KM, N>(
+                    gd, lane, val, S.cstream, gb, P, k, k,
+                    [&](int rg, int q, ST v) {
+                        const long e = long(gd.row0 + rg) * k + q;
+                        Q[e] = v;
+                        dot[0] += double(P[e]) * double(v);
+                    });
             }
-        } else {
-            coop_group<VT, ST, V, KM>(
-                gd, lane, val, S.col, P, k, k, [&](int rg, int q, ST v) {
-                    const long e = long(gd.row0 + rg) * k + q;
-                    Q[e] = v;
-                    dot[0] += double(P[e]) * double(v);
-                });
         }
-    }
+    });
     store_col_partials<1, KM>(dot, k, S.partials, nb, lb);
 }
 
@@ -492,8 +494,15 @@ __global__ __launch_bounds__(kBlock) void k_residual(
         ST a0[KM], a1[KM];
 #pragma unroll
         for (int c = 0; c < KM; ++c) a0[c] = a1[c] = ST(0);
-        if (!XZ)
-            lane_sums<VT, ST, V, KM>(gd, lane, val, S.col, X, k, k, a0, a1);
+        if (!XZ) {
+            if (S.gbase)
+                lane_sums<VT, ST, V, KM, true>(gd, lane, val, S.cstream,
+                                               load_gbase(S.gbase, g), X, k,
+                                               k, a0, a1);
+            else
+                lane_sums<VT, ST, V, KM, false>(gd, lane, val, S.cstream, 0,
+                                                X, k, k, a0, a1);
+        }
         const int lt = gd.width_lt >> 24, r = lane >> lt;
         const bool owner = (lane & ((1 << lt) - 1)) == 0 && r < gd.nrows;
         const long row = gd.row0 + r;
@@ -613,11 +622,12 @@ __global__ __launch_bounds__(kBlock) void k_diag(
 // Y[row or yperm[row], :] = (A X)[row, :] for k <= KM columns; one group per
 // wavefront, XCD-aware block order.  With KM = 1 and a float / bf16 value
 // array this is the low-precision product (float vectors and sums).
-template <typename VT, typename ST, int V, int KM, bool SCATTER>
+template <typename VT, typename ST, int V, int KM, bool SCATTER, bool N>
 __global__ __launch_bounds__(kBlock) void k_spmm(
     const Group *__restrict__ groups, int ngroups, const VT *__restrict__ val,
-    const int *__restrict__ col, const ST *__restrict__ X, long ldx,
-    ST *__restrict__ Y, long ldy, int k, const int *__restrict__ yperm)
+    const void *__restrict__ col, const int *__restrict__ gbase,
+    const ST *__restrict__ X, long ldx, ST *__restrict__ Y, long ldy, int k,
+    const int *__restrict__ yperm)
 {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int g = __builtin_amdgcn_readfirstlane(
@@ -625,9 +635,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
     if (g >= ngroups) return;
     const int lane = threadIdx.x & (kWave - 1);
     const Group gd = load_group(groups, g);
+    const int gb = N ? load_gbase(gbase, g) : 0;
     if constexpr (KM == 1) {
         ST a0[1] = {ST(0)}, a1[1] = {ST(0)};
-        lane_sums<VT, ST, V, 1>(gd, lane, val, col, X, 1, ldx, a0, a1);
+        lane_sums<VT, ST, V, 1, N>(gd, lane, val, col, gb, X, 1, ldx, a0, a1);
         const int lt = gd.width_lt >> 24, r = lane >> lt;
         const ST v = row_reduce(a0[0] + a1[0], lt);
         if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
@@ -635,8 +646,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
             Y[(SCATTER ? long(yperm[row]) : long(row)) * ldy] = v;
         }
     } else {
-        coop_group<VT, ST, V, KM>(
-            gd, lane, val, col, X, k, ldx, [&](int rg, int q, ST v) {
+        coop_group<VT, ST, V, KM, N>(
+            gd, lane, val, col, gb, X, k, ldx, [&](int rg, int q, ST v) {
                 const int row = gd.row0 + rg;
                 Y[(SCATTER ? long(yperm[row]) : long(row)) * ldy + q] = v;
             });
@@ -923,10 +934,17 @@ hipError_t launch_spmm_f64(const fs_csr *A, int32_t k, const double *X,
         auto go = [&](auto vtag, auto stag) {
             constexpr int V = decltype(vtag)::value;
             constexpr bool SC = decltype(stag)::value;
-            hipLaunchKernelGGL((k_spmm<double, double, V, KM, SC>), grid,
-                               dim3(kBlock), 0, s, A->d_groups, A->n_groups,
-                               A->d_val, A->d_col, X, long(ldx), Y, long(ldy),
-                               k, yperm);
+            if (A->d_col16)
+                hipLaunchKernelGGL((k_spmm<double, double, V, KM, SC, true>),
+                                   grid, dim3(kBlock), 0, s, A->d_groups,
+                                   A->n_groups, A->d_val, A->d_col16,
+                                   A->d_gbase, X, long(ldx), Y, long(ldy), k,
+                                   yperm);
+            else
+                hipLaunchKernelGGL((k_spmm<double, double, V, KM, SC, false>),
+                                   grid, dim3(kBlock), 0, s, A->d_groups,
+                                   A->n_groups, A->d_val, A->d_col, nullptr,
+                                   X, long(ldx), Y, long(ldy), k, yperm);
         };
         if (A->host.vec == 1) {
             if (yperm) go(KmTag<1>(), std::true_type());
@@ -950,9 +968,16 @@ hipError_t launch_spmv_lowp(const fs_csr *A, int32_t dtype, const float *x,
         const VT *val = dtype == FS_DT_F32
                             ? reinterpret_cast<const VT *>(A->d_val_f32)
                             : reinterpret_cast<const VT *>(A->d_val_bf16);
-        hipLaunchKernelGGL((k_spmm<VT, float, V, 1, false>), grid,
-                           dim3(kBlock), 0, s, A->d_groups, A->n_groups, val,
-                           A->d_col, x, 1L, y, 1L, 1, nullptr);
+        if (A->d_col16)
+            hipLaunchKernelGGL((k_spmm<VT, float, V, 1, false, true>), grid,
+                               dim3(kBlock), 0, s, A->d_groups, A->n_groups,
+                               val, A->d_col16, A->d_gbase, x, 1L, y, 1L, 1,
+                               nullptr);
+        else
+            hipLaunchKernelGGL((k_spmm<VT, float, V, 1, false, false>), grid,
+                               dim3(kBlock), 0, s, A->d_groups, A->n_groups,
+                               val, A->d_col, nullptr, x, 1L, y, 1L, 1,
+                               nullptr);
     };
     if (dtype == FS_DT_F32) {
         if (A->host.vec == 1) go(TypeTag<float, float>(), KmTag<1>());

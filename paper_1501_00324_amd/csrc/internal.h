@@ -46,6 +46,11 @@ struct HostLayout {
     double band_before = 0.0, band_after = 0.0;
     bool symmetric_relabel = false;  // columns relabelled by iperm
     bool identity = true;            // perm is the identity
+    // 16-bit column indices: slot_c16[s] = column - gbase[group], 0xffff
+    // for padding; empty when index_bits == 32
+    int32_t index_bits = 32;
+    std::vector<uint16_t> slot_c16;
+    std::vector<int32_t> gbase;
 };
 
 fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
@@ -71,7 +76,9 @@ struct ColState {                // one right-hand side, device resident
 struct SysDesc {
     const Group *groups;
     const void *val;             // slot values: double, float or bf16 bits
-    const int32_t *col;
+    const int32_t *col;          // 32-bit slot columns
+    const void *cstream;         // column stream of the products: col, or
+    const int32_t *gbase;        //   16-bit offsets from gbase[group]
     int32_t n, ngroups, k, maxit;
     int32_t sb0, snb;            // blocks in the group-shaped grid
     int32_t vb0, vnb;            // blocks in the row-shaped grid
@@ -196,6 +203,8 @@ struct fs_csr {
     float *d_val_f32 = nullptr;
     uint16_t *d_val_bf16 = nullptr;
     int32_t *d_col = nullptr;
+    uint16_t *d_col16 = nullptr;   // 16-bit offsets (index_bits 16), or NULL
+    int32_t *d_gbase = nullptr;    // per-group column base for d_col16
     int32_t *d_map = nullptr;
     int32_t *d_perm = nullptr;
     int32_t *d_iperm = nullptr;
@@ -238,7 +247,7 @@ hipError_t launch_spmm_f64(const fs_csr *A, int32_t k, const double *X,
                            const int32_t *yperm, hipStream_t s);
 // m products y_i = A_i x_i in caller numbering, descriptors passed as
 // kernel arguments (kBatchPerLaunch matrices per launch).
-constexpr int kBatchPerLaunch = 64;
+constexpr int kBatchPerLaunch = 56;
 hipError_t launch_spmv_batch(int32_t m, const fs_csr *const *A,
                              const double *const *x, double *const *y,
                              hipStream_t s);

@@ -415,6 +415,8 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
                          "two with 1 <= min <= max <= 64");
     if (o.vec < 0 || o.vec > 2)
         return set_error(FS_E_ARG, "vec must be 0 (auto), 1 or 2");
+    if (o.index_bits != 0 && o.index_bits != 32)
+        return set_error(FS_E_ARG, "index_bits must be 0 (auto) or 32");
 
     // ---- locality permutation
     L.perm.resize(size_t(n_rows));
@@ -610,6 +612,55 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
             return set_error(FS_E_BAD_CSR, "duplicate column %d in row %d",
                              col[k], row);
         }
+
+    // ---- 16-bit column offsets when every group's columns fit: the index
+    // stream shrinks from 4 to 2 bytes per slot
+    L.index_bits = 32;
+    L.slot_c16.clear();
+    L.gbase.clear();
+    if (o.index_bits == 0 && ngr > 0) {
+        std::vector<int32_t> lo(size_t(ngr), 0), hi(size_t(ngr), -1);
+        parallel_chunks(gch, [&](int64_t c) {
+            const int64_t g1 = std::min(ngr, (c + 1) * kGroupChunk);
+            for (int64_t gi = c * kGroupChunk; gi < g1; ++gi) {
+                const Group &g = L.groups[size_t(gi)];
+                const int64_t b0 = int64_t(g.base64) * kWave;
+                const int64_t b1 = b0 + int64_t(g.width_lt & 0xffffff) * kWave;
+                int32_t mn = INT32_MAX, mx = -1;
+                for (int64_t e = b0; e < b1; ++e) {
+                    const int32_t cc = L.slot_col[size_t(e)];
+                    if (cc < 0) continue;
+                    mn = std::min(mn, cc);
+                    mx = std::max(mx, cc);
+                }
+                lo[size_t(gi)] = mx < 0 ? 0 : mn;
+                hi[size_t(gi)] = mx;
+            }
+        });
+        bool fits = true;
+        for (int64_t gi = 0; gi < ngr && fits; ++gi)
+            fits = hi[size_t(gi)] - lo[size_t(gi)] < 0xffff;
+        if (fits) {
+            L.index_bits = 16;
+            L.gbase = lo;
+            L.slot_c16.assign(size_t(slots), 0xffff);
+            parallel_chunks(gch, [&](int64_t c) {
+                const int64_t g1 = std::min(ngr, (c + 1) * kGroupChunk);
+                for (int64_t gi = c * kGroupChunk; gi < g1; ++gi) {
+                    const Group &g = L.groups[size_t(gi)];
+                    const int64_t b0 = int64_t(g.base64) * kWave;
+                    const int64_t b1 =
+                        b0 + int64_t(g.width_lt & 0xffffff) * kWave;
+                    for (int64_t e = b0; e < b1; ++e) {
+                        const int32_t cc = L.slot_col[size_t(e)];
+                        if (cc >= 0)
+                            L.slot_c16[size_t(e)] =
+                                uint16_t(cc - lo[size_t(gi)]);
+                    }
+                }
+            });
+        }
+    }
     return FS_OK;
 }
 

@@ -35,7 +35,9 @@ constexpr int kPW = kPB / kWave;
 struct PcgArgs {
     const Group *groups;
     const double *val;
-    const int32_t *col;
+    const int32_t *col;            // 32-bit columns (diagonal search)
+    const void *cstream;           // column stream of the products
+    const int32_t *gbase;          // group bases of 16-bit offsets, or NULL
     int32_t n, ngroups;
     const double *b;               // layout numbering
     double *x, *r, *p, *q, *dinv;  // dinv NULL: no preconditioner
@@ -94,7 +96,7 @@ __device__ __forceinline__ void get_sums(double *part, int nb,
 
 // b - A x for the rows of this block's groups (A x skipped when XZ); calls
 // f(row, r_row) on the owner lane of every row.
-template <int V, bool XZ, class F>
+template <int V, bool N, bool XZ, class F>
 __device__ __forceinline__ void residual_rows(const PcgArgs &a, int g0, int g1,
                                               F f)
 {
@@ -104,7 +106,9 @@ __device__ __forceinline__ void residual_rows(const PcgArgs &a, int g0, int g1,
         const int lt = gd.width_lt >> 24;
         double ax = 0.0;
         if (!XZ)
-            ax = row_reduce(group_lane_sum<V>(gd, lane, a.val, a.col, a.x), lt);
+            ax = row_reduce(group_lane_sum<V, N>(gd, lane, a.val, a.cstream,
+                                                N ? load_gbase(a.gbase, g) : 0,
+                                                a.x), lt);
         const int r = lane >> lt;
         if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
             const int row = gd.row0 + r;
@@ -115,7 +119,7 @@ __device__ __forceinline__ void residual_rows(const PcgArgs &a, int g0, int g1,
 
 enum { P_RUNNING = 0, P_CONVERGED = 1, P_BREAKDOWN = 2, P_MAXIT = 3 };
 
-template <int V>
+template <int V, bool N>
 __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
 {
     cgr::grid_group grid = cgr::this_grid();
@@ -158,8 +162,8 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
         v3[1] += ri * zi;
         v3[2] += bi * bi;
     };
-    if (a.x_zero) residual_rows<V, true>(a, g0, g1, start);
-    else residual_rows<V, false>(a, g0, g1, start);
+    if (a.x_zero) residual_rows<V, N, true>(a, g0, g1, start);
+    else residual_rows<V, N, false>(a, g0, g1, start);
     put_partials<3>(v3, a.part, nb, lb);
     grid.sync();
     double s3[3];
@@ -185,7 +189,9 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
                 load_group(a.groups, __builtin_amdgcn_readfirstlane(g));
             const int lt = gd.width_lt >> 24;
             const double qv =
-                row_reduce(group_lane_sum<V>(gd, lane, a.val, a.col, a.p), lt);
+                row_reduce(group_lane_sum<V, N>(gd, lane, a.val, a.cstream,
+                                                N ? load_gbase(a.gbase, g) : 0,
+                                                a.p), lt);
             const int r = lane >> lt;
             if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
                 const int row = gd.row0 + r;
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
         if (rr <= tol2) {
             // confirm against the true residual; replace r if it misses
             double w2[2] = {0.0, 0.0};
-            residual_rows<V, false>(a, g0, g1, [&](int row, double ri) {
+            residual_rows<V, N, false>(a, g0, g1, [&](int row, double ri) {
                 a.r[row] = ri;
                 const double zi = D ? D[row] * ri : ri;
                 w2[0] += ri * zi;
@@ -266,7 +272,7 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
         // report the true residual of the returned x
         grid.sync();
         double w1[1] = {0.0};
-        residual_rows<V, false>(a, g0, g1,
+        residual_rows<V, N, false>(a, g0, g1,
                                 [&](int, double ri) { w1[0] += ri * ri; });
         put_partials<1>(w1, a.part, nb, lb);
         grid.sync();
@@ -290,14 +296,14 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
     }
 }
 
-template <int V> int max_coresident(int device)
+template <int V, bool N> int max_coresident(int device)
 {
     static int cached[64];
     if (device < 0 || device >= 64) return 0;
     if (cached[device] == 0) {
         int per_cu = 0, cus = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, k_cg_persistent<V>, kPB, 0) != hipSuccess ||
+                &per_cu, k_cg_persistent<V, N>, kPB, 0) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                   device) != hipSuccess)
             return 0;
@@ -312,8 +318,12 @@ int32_t persistent_blocks(const fs_csr *A)
 {
     const int want = std::max((A->n_groups + kPW - 1) / kPW,
                               (A->n_rows + kPB - 1) / kPB);
-    const int cap = A->host.vec == 1 ? max_coresident<1>(A->device)
-                                     : max_coresident<2>(A->device);
+    const bool n = A->d_col16 != nullptr;
+    const int cap = A->host.vec == 1
+                        ? (n ? max_coresident<1, true>(A->device)
+                             : max_coresident<1, false>(A->device))
+                        : (n ? max_coresident<2, true>(A->device)
+                             : max_coresident<2, false>(A->device));
     return std::max(1, std::min({want, cap, kPersistMaxBlocks}));
 }
 
@@ -331,6 +341,9 @@ hipError_t launch_cg_persistent(const fs_csr *A, int32_t nblocks,
     a.groups = A->d_groups;
     a.val = A->d_val;
     a.col = A->d_col;
+    a.cstream = A->d_col16 ? static_cast<const void *>(A->d_col16)
+                           : static_cast<const void *>(A->d_col);
+    a.gbase = A->d_col16 ? A->d_gbase : nullptr;
     a.n = A->n_rows;
     a.ngroups = A->n_groups;
     a.b = b;
@@ -347,13 +360,15 @@ hipError_t launch_cg_persistent(const fs_csr *A, int32_t nblocks,
     a.maxit = maxit;
     a.x_zero = x_zero ? 1 : 0;
     void *args[] = {&a};
-    if (A->host.vec == 1)
-        return hipLaunchCooperativeKernel(
-            reinterpret_cast<const void *>(k_cg_persistent<1>), dim3(nblocks),
-            dim3(kPB), args, 0, s);
-    return hipLaunchCooperativeKernel(
-        reinterpret_cast<const void *>(k_cg_persistent<2>), dim3(nblocks),
-        dim3(kPB), args, 0, s);
+    const bool n = A->d_col16 != nullptr;
+    const void *fn =
+        A->host.vec == 1
+            ? (n ? reinterpret_cast<const void *>(k_cg_persistent<1, true>)
+                 : reinterpret_cast<const void *>(k_cg_persistent<1, false>))
+            : (n ? reinterpret_cast<const void *>(k_cg_persistent<2, true>)
+                 : reinterpret_cast<const void *>(k_cg_persistent<2, false>));
+    return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kPB), args, 0,
+                                      s);
 }
 
 }  // namespace fs

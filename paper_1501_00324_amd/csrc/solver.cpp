@@ -137,6 +137,9 @@ fs_status batch_build(Batch &B, hipStream_t s)
         d.groups = A->d_groups;
         d.val = values_of(A, S.vt);
         d.col = A->d_col;
+        d.cstream = A->d_col16 ? static_cast<const void *>(A->d_col16)
+                               : static_cast<const void *>(A->d_col);
+        d.gbase = A->d_col16 ? A->d_gbase : nullptr;
         d.n = S.n;
         d.ngroups = A->n_groups;
         d.k = S.k;

@@ -34,6 +34,8 @@ MATS = [
                                   permute=True), {}),
     ("ela_v1_t4", lambda: W.tet_p1(7, "elastic", seed=(40, 1)),
      dict(vec=1, lanes_min=4, lanes_max=4)),
+    ("ela_wide_idx", lambda: W.tet_p1(9, "elastic", seed=(40, 2),
+                                      permute=True), dict(index_bits=32)),
     ("ragged_rect", lambda: ragged(700, 333, seed=5), {}),
 ]
 

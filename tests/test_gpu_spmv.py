@@ -23,6 +23,8 @@ def fs():
 def run_spmv(fs, orc, A, opts, seed, what):
     note("spmv %s n=%d nnz=%d opts=%s" % (what, A.n_rows, A.nnz, opts))
     M = make(A, **opts)
+    if opts.get("index_bits") == 32:
+        assert fs.csr_info(M)["index_bits"] == 32
     x = W.random_vector(A.n_cols, 50, W.XVEC, seed)
     y = host(fs.spmv(M, dev(x)))
     assert_spmv_close(y, orc.spmv(A, x), orc.spmv_abs(A, x), what)
@@ -50,6 +52,9 @@ LAYOUTS = [
     dict(vec=1),
     dict(vec=1, lanes_min=4, lanes_max=4),
     dict(vec=2, lanes_min=1, lanes_max=1, sort_window=1),
+    dict(index_bits=32),
+    dict(index_bits=32, vec=1),
+    dict(index_bits=32, lanes_min=8, lanes_max=8),
 ]
 
 
@@ -148,6 +153,9 @@ def test_config1_full_size(fs, orc):
     info = fs.csr_info(M)
     assert info["nnz"] == 33967818 and info["reorder"] == fs.REORDER_RCM
     assert info["padding"] < 0.15
+    assert info["index_bits"] == 16      # the timed configuration
+    M32 = run_spmv(fs, orc, A, dict(index_bits=32), 2, "cfg1 32-bit")
+    assert fs.csr_info(M32)["slots"] == info["slots"]
 
 
 # ------------------------------------------------------------ batched
