@@ -301,13 +301,28 @@ fs_status create_tuned(int32_t n_rows, int32_t n_cols, int64_t nnz,
     }
     // the first candidate is the default shape; it fixes the permutation
     fs_csr *best = nullptr;
-    fs_csr_opts o0 = o;
-    if (cached && chosen.first > 0) {
-        o0.lanes_min = o0.lanes_max = chosen.first;
-        o0.vec = chosen.second;
-    }
-    FS_TRY(create_from_host(n_rows, n_cols, nnz, h_rp, h_col, vals, o0, s,
+    FS_TRY(create_from_host(n_rows, n_cols, nnz, h_rp, h_col, vals, o, s,
                             dev, &best));
+    if (cached && chosen.first > 0) {
+        // rebuild the cached shape exactly as the tuning run built it: the
+        // default build's permutation, no further window sort
+        const std::vector<int32_t> perm = best->host.perm;
+        const int32_t reorder0 = best->host.reorder;
+        fs_csr_opts oc = o;
+        oc.reorder = FS_REORDER_USER;
+        oc.perm = perm.data();
+        oc.sort_window = 1;
+        oc.lanes_min = oc.lanes_max = chosen.first;
+        oc.vec = chosen.second;
+        fs_csr *A = nullptr;
+        const fs_status st = create_from_host(n_rows, n_cols, nnz, h_rp,
+                                              h_col, vals, oc, s, dev, &A);
+        free_handle(best);
+        delete best;
+        if (st != FS_OK) return st;
+        best = A;
+        best->host.reorder = reorder0;
+    }
     if (cached || n_rows != n_cols || n_rows == 0) {
         best->tuned = cached ? 2 : 0;
         *out = best;
