@@ -676,6 +676,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     "dram_gbs": (round(traffic / (us * 1e-6) / 1e9, 1)
+                                  if traffic else None),
                      "bytes_algorithmic": bytes_alg,
                      "kernel": "k_spmv_f64"},
         "cpu_baseline": cpu,
