@@ -648,6 +648,27 @@ def main():
                              "rows split over %d OpenMP threads"
                              % (reps_p, used)}
         log("cpu oracle, all cores: %s" % json.dumps(cpu_all))
+    cpu_cg = None
+    if reps and not args.no_cg:
+        # the oracle's Jacobi-PCG on the host: config 0 to 1e-8, and a
+        # bounded run of config-1 iterations scaled to the GPU's count
+        A0 = W.config0_poisson2d()
+        b0 = W.random_vector(A0.n_rows, 0, W.BVEC)
+        t0 = time.perf_counter()
+        _, st0, it0, _ = oracle.pcg(A0, b0, precond=1)
+        t_c0 = time.perf_counter() - t0
+        b1 = W.random_vector(A.n_rows, 1, W.BVEC)
+        t0 = time.perf_counter()
+        _, _, it1, _ = oracle.pcg(A, b1, precond=1, maxit=40)
+        per_it = (time.perf_counter() - t0) / max(1, it1)
+        cpu_cg = {"config0_ms": t_c0 * 1e3, "config0_iters": it0,
+                  "config1_ms_per_iter": per_it * 1e3,
+                  "config1_est_ms": per_it * 1e3 * (cg["iters"] if cg
+                                                     else 0),
+                  "cores": 1, "kind": "oracle",
+                  "sample": "config 0 solved to 1e-8; 40 config-1 "
+                            "iterations, scaled to the GPU iteration count"}
+        log("cpu oracle CG: %s" % json.dumps(cpu_cg))
     traffic = measured_traffic()
 
     out = {
@@ -682,6 +703,7 @@ def main():
                      "kernel": "k_spmv_f64"},
         "cpu_baseline": cpu,
         "cpu_oracle_all_cores": cpu_all,
+        "cpu_oracle_cg": cpu_cg,
         "spmv": prod,
         "spmv_caller_numbering_gbs": round(gbs_caller, 2),
         "paper_model_gbs": round(20 * A.nnz / (us * 1e-6) / 1e9, 2),
