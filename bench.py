@@ -380,6 +380,47 @@ def bench_spmv_batch(fs, W, oracle, d, torch, stream, m=64):
             "speedup": t_one / t_bat, "parity_all_rows": bool(ok)}
 
 
+def bench_newton(fs, oracle, torch, A, d, stream, steps=4):
+    """Repeated solves on one pattern (the paper's use: the assembler hands
+    new values each Newton step, the pattern and the layout stay): per step
+    the device-side value refresh through the stored CSR -> slot map, then a
+    Jacobi-PCG solve warm-started from the previous step's solution."""
+    import workloads as W
+    diag = A.col == np.repeat(np.arange(A.n_rows), A.row_lengths())
+    vals = []
+    for st in range(1, steps + 1):
+        v = A.val * (1.0 + 0.1 * st)
+        v[diag] += 0.05 * st * np.abs(A.val[diag])
+        vals.append(d(v))
+    b = W.random_vector(A.n_rows, 1, W.BVEC)
+    bd = d(b)
+    M = fs.csr_create(d(A.rowptr), d(A.col), d(A.val), A.n_rows, A.n_cols)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    out = []
+    for st, vd in enumerate(vals, 1):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fs.csr_update_values(M, vd)
+        e1.record(stream)
+        e1.synchronize()
+        t0 = time.perf_counter()
+        x, info = fs.cg_solve(M, bd, x=x, precond=fs.PC_JACOBI, x0_zero=0)
+        ts = time.perf_counter() - t0
+        _, cold = fs.cg_solve(M, bd, precond=fs.PC_JACOBI)
+        out.append({"step": st, "refresh_us": e0.elapsed_time(e1) * 1e3,
+                    "solve_ms": ts * 1e3, "iters_warm": info["iters"],
+                    "iters_cold": cold["iters"], "status": info["status"]})
+    Ah_vals = vals[-1].cpu().numpy()
+    from workloads.meshes import CSR
+    B = CSR(A.n_rows, A.n_cols, A.rowptr, A.col, Ah_vals)
+    rel = float(np.linalg.norm(b - oracle.spmv(B, x.cpu().numpy())) /
+                np.linalg.norm(b))
+    return {"steps": out, "relres_oracle_last": rel,
+            "refresh_gbs": (20.0 * A.nnz) / (out[-1]["refresh_us"] * 1e-6)
+            / 1e9}
+
+
 def run_sweep(fs, W, oracle, torch, d, steps, warmup, stream):
     """Every sweep matrix in natural and random numbering: layout, parity,
     product GB/s, the plain CSR product, build time."""
@@ -524,7 +565,7 @@ def main():
     log("spmv (caller numbering): %.2f us, %.1f GB/s" % (us_caller,
                                                          gbs_caller))
 
-    cg = ir = multi = batch = asy = asy_small = sbatch = None
+    cg = ir = multi = batch = asy = asy_small = sbatch = newton = None
     if not args.no_cg:
         b = W.random_vector(A.n_rows, 1, W.BVEC)
         bd = d(b)
@@ -594,6 +635,8 @@ def main():
                                      for i in infos),
                 "relres_oracle_worst": worst}
             log("cg multi-rhs k=%d: %s" % (k, json.dumps(multi[str(k)])))
+        newton = bench_newton(fs, oracle, torch, A, d, stream)
+        log("newton steps: %s" % json.dumps(newton))
         batch = bench_small_batch(fs, W, oracle, d, torch)
         log("batched small systems: %s" % json.dumps(batch))
         sbatch = bench_spmv_batch(fs, W, oracle, d, torch, stream)
@@ -713,6 +756,7 @@ def main():
         "cg_mixed_precision": ir,
         "cg_stream_ordered": {"config1": asy, "config0": asy_small},
         "cg_multi_rhs": multi,
+        "newton_repeated_solves": newton,
         "cg_batched_small": batch,
         "spmv_batched_small": sbatch,
         "serving": serving,

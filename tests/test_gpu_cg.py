@@ -144,3 +144,43 @@ def test_cg_warm_start_and_determinism(fs, orc):
     xr, ir = fs.cg_solve(M, dev(b), x=xh.clone(), precond=1)
     assert ir["status"] == fs.FS_OK
     assert true_relres(orc, A, host(xr), b) <= 1.001e-8
+
+
+def newton_values(A, step):
+    """Values of Newton step `step`: same pattern, stiffness scaled and the
+    diagonal raised (stays SPD)."""
+    v = A.val * (1.0 + 0.1 * step)
+    diag = A.col == np.repeat(np.arange(A.n_rows), A.row_lengths())
+    v = v.copy()
+    v[diag] += 0.05 * step * np.abs(A.val[diag])
+    return v
+
+
+def test_newton_steps_update_values(fs, orc):
+    """Repeated solves on one pattern with new values per step (the
+    per-Newton-step refresh): after csr_update_values the solve is bitwise
+    the solve on a freshly built handle, in FP64 and in FP32 refinement."""
+    A = W.tet_p1(9, "elastic", seed=(57, 0), bc="x0", permute=True)
+    b = W.random_vector(A.n_rows, 57, W.BVEC)
+    note("newton steps n=%d" % A.n_rows)
+    M = make(A)
+    fs.csr_add_dtype(M, fs.DT_F32)
+    x = None
+    for step in range(1, 4):
+        v = newton_values(A, step)
+        fs.csr_update_values(M, dev(v))
+        B = CSR(A.n_rows, A.n_cols, A.rowptr, A.col, v)
+        F = make(B)
+        x64, i64 = fs.cg_solve(M, dev(b), precond=1)
+        xf, _ = fs.cg_solve(F, dev(b), precond=1)
+        assert np.array_equal(host(x64), host(xf))
+        assert true_relres(orc, B, host(x64), b) <= 1.001e-8
+        x32, i32 = fs.cg_solve(M, dev(b), precond=1,
+                               precision=fs.PREC_IR_F32)
+        assert true_relres(orc, B, host(x32), b) <= 1.001e-8
+        # warm start from the previous step's solution
+        if x is not None:
+            xw, iw = fs.cg_solve(M, dev(b), x=dev(x), precond=1, x0_zero=0)
+            assert iw["status"] == fs.FS_OK
+            assert true_relres(orc, B, host(xw), b) <= 1.001e-8
+        x = host(x64)
