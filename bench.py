@@ -390,7 +390,7 @@ def bench_newton(fs, oracle, torch, A, d, stream, steps=4):
     vals = []
     for st in range(1, steps + 1):
         v = A.val * (1.0 + 0.1 * st)
-        v[diag] += 0.05 * st * np.abs(A.val[diag])
+        v[diag] += 0.002 * st * np.abs(A.val[diag])
         vals.append(d(v))
     b = W.random_vector(A.n_rows, 1, W.BVEC)
     bd = d(b)

@@ -152,7 +152,7 @@ def newton_values(A, step):
     v = A.val * (1.0 + 0.1 * step)
     diag = A.col == np.repeat(np.arange(A.n_rows), A.row_lengths())
     v = v.copy()
-    v[diag] += 0.05 * step * np.abs(A.val[diag])
+    v[diag] += 0.002 * step * np.abs(A.val[diag])
     return v
 
 
