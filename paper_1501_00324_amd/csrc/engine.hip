@@ -9,7 +9,8 @@
 // system with one column.
 //
 // Per iteration (textbook preconditioned CG, the solver the paper runs
-// around its SpMV; M = diag(A) or I):
+// around its SpMV; M = diag(A) or I; with one column the two finalize
+// kernels are folded into the vector kernels, see k_update_fused):
 //   k_spmm_dot   : Q = A P, per-block partials of p_c . q_c
 //   k_fin_dot    : gamma_c, alpha_c = rho_c / gamma_c (breakdown check)
 //   k_update     : x += alpha p, r -= alpha q, z = M^-1 r; partials of r.z
@@ -401,6 +402,99 @@ __global__ __launch_bounds__(kBlock) void k_update(
     store_col_partials<2, KM>(v, k, S.partials, nb, lb);
 }
 
+// Single-column fused forms (KM = 1): the finalize kernels disappear.  Every
+// block sums the system's partials itself, in the same order, so all
+// blocks hold bitwise the same scalars; the system's first block alone
+// writes the column state.  Fields that other blocks of the same kernel
+// read are never written by it: k_update_fused reads rho and writes
+// rho_prev, gamma, alpha (and a breakdown status, which every block
+// derives itself); k_pupdate_fused reads rho_prev and writes rho, beta,
+// rr, iter, status.  The p.q partials stay at partials[0 .. snb), the
+// r.z / r.r partials go to partials[snb .. snb + 2 vnb).
+template <typename ST>
+__global__ __launch_bounds__(kBlock) void k_update_fused(
+    const SysDesc *__restrict__ sys, const int *__restrict__ vmap)
+{
+    const SysDesc &S = sys[vmap[blockIdx.x]];
+    const int lb = blockIdx.x - S.vb0, nb = S.vnb, n = S.n;
+    ColState &cs = S.cs[0];
+    if (cs.status != CG_RUNNING) return;
+    double g1[1];
+    sum_partials<1>(S.partials, S.snb, 0, g1);
+    const double gamma = g1[0], rho = cs.rho;
+    const bool bad = !(gamma > 0.0) || !isfinite(gamma);
+    const double alpha_d = bad ? 0.0 : rho / gamma;
+    if (lb == 0 && threadIdx.x == 0) {
+        cs.gamma = gamma;
+        cs.alpha = alpha_d;
+        cs.rho_prev = rho;
+        if (bad) cs.status = CG_BREAKDOWN;
+    }
+    if (bad) return;
+    ST *X = static_cast<ST *>(S.x);
+    ST *R = static_cast<ST *>(S.r);
+    const ST *P = static_cast<const ST *>(S.p);
+    const ST *Q = static_cast<const ST *>(S.q);
+    const ST *D = static_cast<const ST *>(S.dinv);
+    const ST alpha = ST(alpha_d);
+    double v[2] = {0.0, 0.0};
+    for (long i = long(lb) * kBlock + threadIdx.x; i < n; i += long(nb) * kBlock) {
+        const ST ri = R[i] - alpha * Q[i];
+        X[i] += alpha * P[i];
+        R[i] = ri;
+        const ST zi = D ? D[i] * ri : ri;
+        v[0] += double(ri) * double(zi);
+        v[1] += double(ri) * double(ri);
+    }
+    store_col_partials<2, 1>(v, 1, S.partials + S.snb, nb, lb);
+}
+
+template <typename ST>
+__global__ __launch_bounds__(kBlock) void k_pupdate_fused(
+    const SysDesc *__restrict__ sys, const int *__restrict__ vmap)
+{
+    const SysDesc &S = sys[vmap[blockIdx.x]];
+    const int lb = blockIdx.x - S.vb0, nb = S.vnb, n = S.n;
+    ColState &cs = S.cs[0];
+    if (cs.status != CG_RUNNING) return;
+    double t[2];
+    sum_partials<2>(S.partials + S.snb, nb, 0, t);
+    const double rz = t[0], rr = t[1];
+    const bool lead = lb == 0 && threadIdx.x == 0;
+    if (rr <= cs.tol2) {
+        if (lead) {
+            cs.iter += 1;
+            cs.rr = rr;
+            cs.status = CG_RECURRENCE_MET;
+        }
+        return;
+    }
+    const double beta = rz / cs.rho_prev;
+    if (!isfinite(beta) || !isfinite(rr)) {
+        if (lead) {
+            cs.iter += 1;
+            cs.rr = rr;
+            cs.status = CG_BREAKDOWN;
+        }
+        return;
+    }
+    if (lead) {
+        cs.iter += 1;
+        cs.rr = rr;
+        cs.beta = beta;
+        cs.rho = rz;
+        if (cs.iter >= cs.maxit) cs.status = CG_MAXIT;
+    }
+    ST *P = static_cast<ST *>(S.p);
+    const ST *R = static_cast<const ST *>(S.r);
+    const ST *D = static_cast<const ST *>(S.dinv);
+    const ST b = ST(beta);
+    for (long i = long(lb) * kBlock + threadIdx.x; i < n; i += long(nb) * kBlock) {
+        const ST zi = D ? D[i] * R[i] : R[i];
+        P[i] = zi + b * P[i];
+    }
+}
+
 // One block per (system, column): count the iteration; stop when the
 // recurrence residual meets the tolerance, else beta = rz / rho.
 __global__ __launch_bounds__(kBlock) void k_fin_update(
@@ -704,14 +798,21 @@ hipError_t engine_iteration(const EngineLaunch &L, hipStream_t s)
             else
                 hipLaunchKernelGGL((k_spmm_dot<VT, ST, 2, KM>), dim3(L.sblocks),
                                    dim3(kBlock), 0, s, L.sys, L.smap);
-            hipLaunchKernelGGL(k_fin_dot, dim3(L.ncols), dim3(kBlock), 0, s,
-                               L.sys, L.cmap);
-            hipLaunchKernelGGL((k_update<ST, KM>), dim3(L.vblocks),
-                               dim3(kBlock), 0, s, L.sys, L.vmap);
-            hipLaunchKernelGGL(k_fin_update, dim3(L.ncols), dim3(kBlock), 0, s,
-                               L.sys, L.cmap);
-            hipLaunchKernelGGL((k_pupdate<ST, KM, false>), dim3(L.vblocks),
-                               dim3(kBlock), 0, s, L.sys, L.vmap);
+            if constexpr (KM == 1) {
+                hipLaunchKernelGGL((k_update_fused<ST>), dim3(L.vblocks),
+                                   dim3(kBlock), 0, s, L.sys, L.vmap);
+                hipLaunchKernelGGL((k_pupdate_fused<ST>), dim3(L.vblocks),
+                                   dim3(kBlock), 0, s, L.sys, L.vmap);
+            } else {
+                hipLaunchKernelGGL(k_fin_dot, dim3(L.ncols), dim3(kBlock), 0,
+                                   s, L.sys, L.cmap);
+                hipLaunchKernelGGL((k_update<ST, KM>), dim3(L.vblocks),
+                                   dim3(kBlock), 0, s, L.sys, L.vmap);
+                hipLaunchKernelGGL(k_fin_update, dim3(L.ncols), dim3(kBlock),
+                                   0, s, L.sys, L.cmap);
+                hipLaunchKernelGGL((k_pupdate<ST, KM, false>), dim3(L.vblocks),
+                                   dim3(kBlock), 0, s, L.sys, L.vmap);
+            }
         });
     });
     return hipGetLastError();

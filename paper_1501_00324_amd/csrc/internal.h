@@ -67,6 +67,7 @@ struct ColState {                // one right-hand side, device resident
     double rr;                   // |r|^2 of the recurrence residual
     double rr_true;              // |b - A x|^2 at the last true check
     double bnorm2, tol2;
+    double rho_prev;             // rho of the previous iteration (fused path)
     int32_t iter, status, pending, maxit;
     int32_t replacements, pad[3];
 };
