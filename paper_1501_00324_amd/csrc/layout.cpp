@@ -470,14 +470,16 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
     auto make_plan = [&](int32_t window, Plan &P) {
         P.perm = L.perm;
         if (window > 1) {
-            for (int64_t w0 = 0; w0 < n_rows; w0 += window) {
-                int64_t w1 = std::min<int64_t>(n_rows, w0 + window);
+            const int64_t nw = (n_rows + window - 1) / window;
+            parallel_chunks(nw, [&](int64_t w) {
+                const int64_t w0 = w * window;
+                const int64_t w1 = std::min<int64_t>(n_rows, w0 + window);
                 std::stable_sort(P.perm.begin() + w0, P.perm.begin() + w1,
                                  [&](int32_t a, int32_t b) {
                                      return rowptr[a + 1] - rowptr[a] >
                                             rowptr[b + 1] - rowptr[b];
                                  });
-            }
+            });
         }
         auto len = [&](int32_t layout_row) {
             int32_t r = P.perm[layout_row];
