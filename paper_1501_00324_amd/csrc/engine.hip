@@ -305,9 +305,18 @@ __device__ __forceinline__ void coop_group(const Group &g, int lane,
     }
 }
 
+// Occupancy floor (waves per SIMD) of the products in the CG iteration:
+// the gathers are latency bound, and without a floor KM = 1 / 8 / 16
+// settle at 7 / 5 / 3 waves; 8 / 6 / 4 fit their registers without
+// spilling.
+constexpr int spmm_dot_min_waves(int km)
+{
+    return km == 16 ? 4 : km == 8 ? 6 : km == 1 ? 8 : 1;
+}
+
 // Q = A P for every column with per-block partials of p_c . q_c.
 template <typename VT, typename ST, int V, int KM>
-__global__ __launch_bounds__(kBlock) void k_spmm_dot(
+__global__ __launch_bounds__(kBlock, spmm_dot_min_waves(KM)) void k_spmm_dot(
     const SysDesc *__restrict__ sys, const int *__restrict__ smap)
 {
     const int gb = xcd_remap(blockIdx.x, gridDim.x);
