@@ -320,8 +320,15 @@ def measure_matrix(fs, oracle, torch, A, d, steps, warmup, stream,
     out["csr_plain"] = {"us": t_csr,
                         "gbs": bytes_alg / (t_csr * 1e-6) / 1e9,
                         "parity_all_rows": ok_csr}
-    # products after which building the layout has paid for itself
+    # the paper's alpha: products after which reordering the values into
+    # the layout (per Newton step, through the stored map) has paid for
+    # itself against the plain CSR product
+    t_ref = back_to_back_us(torch, lambda: fs.csr_update_values(M, va), 10,
+                            2, stream)
     gain = t_csr - t_b2b
+    out["value_refresh_us"] = t_ref
+    out["alpha_value_reorder"] = t_ref / gain if gain > 0 else None
+    # the same for the one-time structural build of the layout (host)
     out["break_even_products"] = (info["t_build_ms"] * 1e3 / gain
                                   if gain > 0 else None)
     return M, out
