@@ -428,6 +428,64 @@ def bench_newton(fs, oracle, torch, A, d, stream, steps=4):
             / 1e9}
 
 
+def bench_assembly(fs, oracle, torch, A, d, stream, steps=20):
+    """Finite-element assembly straight into the layout (asm_matrix: the
+    element matrices summed per non-zero, element order) on the 3-D
+    elasticity workload, with both plans (row groups summed in LDS, and
+    per-slot gathers): plan build, kernel time against the algorithmic
+    bytes (element values + their 4-byte positions read, FP64 result
+    written), bitwise parity of every value and load entry against the
+    oracle's element loop, and the value reorder it makes unnecessary."""
+    from workloads.elements import config1_elements
+    t = time.time()
+    E = config1_elements()
+    tg = time.time() - t
+    M = fs.csr_create(d(A.rowptr), d(A.col), d(A.val), A.n_rows, A.n_cols)
+    ked, red = d(E.ke), d(E.re)
+    edd = d(E.edof)
+    t = time.perf_counter()
+    want = oracle.assemble_matrix(A, E.edof, E.ke)
+    t_or = time.perf_counter() - t
+    rwant = oracle.assemble_vector(A.n_rows, E.edof, E.re)
+    out = {"n_elem": E.n_elem, "nde": E.nde, "t_generate_s": tg,
+           "cpu_oracle_assembly_ms": t_or * 1e3}
+    for name, plan in (("rowgroup", fs.ASM_ROWGROUP),
+                       ("gather", fs.ASM_GATHER)):
+        t = time.perf_counter()
+        P = fs.asm_create(M, edd, plan=plan)
+        t_plan = time.perf_counter() - t
+        info = fs.asm_info(P)
+        t_mat = back_to_back_us(torch, lambda: fs.asm_matrix(P, ked, stream),
+                                steps, 3, stream)
+        per = event_times_us(torch, lambda: fs.asm_matrix(P, ked, stream),
+                             steps, stream)
+        got = fs.csr_get_values(M).cpu().numpy()
+        bytes_m = info["bytes_algorithmic_matrix"]
+        out[name] = {
+            "plan_ms": t_plan * 1e3, "contributions": info["contrib_matrix"],
+            "index_entries_per_contribution":
+                info["stored_matrix"] / info["contrib_matrix"],
+            "matrix_us": t_mat, "matrix_us_per_launch": dist(per),
+            "bytes_algorithmic": bytes_m,
+            "gbs": bytes_m / (t_mat * 1e-6) / 1e9,
+            "frac": bytes_m / (t_mat * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "device_bytes": info["device_bytes"],
+            "parity_bitwise_all_values": bool(np.array_equal(
+                got.view(np.int64), want.view(np.int64)))}
+        if name == "rowgroup":
+            r = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+            out["vector_us"] = back_to_back_us(
+                torch, lambda: fs.asm_vector(P, red, r, stream), steps, 3,
+                stream)
+            out["parity_bitwise_all_loads"] = bool(np.array_equal(
+                r.cpu().numpy().view(np.int64), rwant.view(np.int64)))
+        del P
+    va = d(A.val)
+    out["reorder_avoided_us"] = back_to_back_us(
+        torch, lambda: fs.csr_update_values(M, va, stream), 10, 2, stream)
+    return out
+
+
 def run_sweep(fs, W, oracle, torch, d, steps, warmup, stream):
     """Every sweep matrix in natural and random numbering: layout, parity,
     product GB/s, the plain CSR product, build time."""
@@ -476,6 +534,8 @@ def main():
     ap.add_argument("--no-largest", action="store_true",
                     help="skip the largest sweep matrix (S12, 156M nnz)")
     ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--no-asm", action="store_true",
+                    help="skip the finite-element assembly measurement")
     ap.add_argument("--serving-full", action="store_true",
                     help="only the serving experiment: 500 requests per "
                          "arrival rate, lambda/mu in {0.25, 0.5, 0.75, "
@@ -648,6 +708,10 @@ def main():
         log("batched small systems: %s" % json.dumps(batch))
         sbatch = bench_spmv_batch(fs, W, oracle, d, torch, stream)
         log("batched small products: %s" % json.dumps(sbatch))
+    assembly = None
+    if not args.no_asm:
+        assembly = bench_assembly(fs, oracle, torch, A, d, stream)
+        log("assembly: %s" % json.dumps(assembly))
     serving = None
     if args.serving_requests > 0:
         serving = bench_serving(fs, W, oracle, d, torch,
@@ -764,6 +828,7 @@ def main():
         "cg_stream_ordered": {"config1": asy, "config0": asy_small},
         "cg_multi_rhs": multi,
         "newton_repeated_solves": newton,
+        "fe_assembly": assembly,
         "cg_batched_small": batch,
         "spmv_batched_small": sbatch,
         "serving": serving,

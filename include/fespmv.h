@@ -410,6 +410,133 @@ fs_status server_stats(fs_server_t S, fs_server_stats *st);
 /* Finish every queued and running request, then free the server. */
 fs_status server_destroy(fs_server_t S);
 
+/* ------------------------------------------------------------- assembly
+ * Finite-element assembly as a sum-only SpMV (paper: section "Description of
+ * Current GPU Methods", the assembly of the global tangent matrix and
+ * residual: one row per global non-zero whose entries are the element
+ * contributions to it, multiplied by a vector of ones, so the product is a
+ * plain race-free sum; section "Cost of Reordering Matrix Values" and the
+ * conclusion: when assembly writes its result straight into the solver's
+ * layout, the value reorder disappears).
+ *
+ * The element data use this layout (row-major, device memory):
+ *   edof[e * nde + a]            row/column of A of local DOF a of element e,
+ *                                or -1 for a DOF that is not in A (e.g.
+ *                                removed by a Dirichlet condition);
+ *   ke[(e * nde + a) * nde + b]  element matrix entry (a, b), FP64;
+ *   re[e * nde + a]              element vector entry a, FP64.
+ * Assembled entry (I, J) of K is the sum over e = 0, 1, ..., n_elem - 1 and,
+ * inside an element, over (a, b) in row-major order, of ke[e][a][b] for every
+ * (a, b) with edof[e][a] = I and edof[e][b] = J, added left to right from
+ * 0.0 in exactly that order (so the result is bitwise reproducible and
+ * equals a sequential element-by-element assembly); entries of A that no
+ * element touches become 0.  R_I is the same sum of re[e][a] over
+ * edof[e][a] = I. */
+typedef struct fs_asm *fs_asm_t;
+
+enum {  /* asm_create(plan): how asm_matrix finds the element values */
+    FS_ASM_AUTO = 0,      /* ROWGROUP when it applies, else GATHER         */
+    FS_ASM_GATHER = 1,    /* one lane per value slot, gathering its element
+                             values through a stored 4-byte position list */
+    FS_ASM_ROWGROUP = 2   /* one workgroup per row group of the layout,
+                             summing in LDS; the nde lanes of a row read an
+                             element row's nde consecutive values; needs
+                             nde <= 64, no kept DOF twice in one element,
+                             every row group within 6144 slots            */
+};
+
+/* Build an assembly plan for square A from the element-to-DOF map edof
+ * (n_elem x nde int32, device).  Every pair of kept DOFs of an element must
+ * be a structural non-zero of A (FS_E_BAD_CSR names the first element that
+ * is not); entries of edof must be -1 or in [0, n_rows).  plan: FS_ASM_*;
+ * both kinds give bitwise the same values.  The plan keeps a reference to
+ * A: A must outlive it.  Synchronises s; the caller may free edof when the
+ * call returns.  The work runs on the host (multi-threaded), once per mesh.
+ * Errors: FS_E_ARG, FS_E_NOT_SQUARE, FS_E_BAD_CSR, FS_E_UNSUPPORTED
+ * (n_elem * nde * nde >= 2^31, or FS_ASM_ROWGROUP where it does not apply),
+ * FS_E_OOM, FS_E_HIP. */
+fs_status asm_create(fs_csr_t A, int32_t n_elem, int32_t nde,
+                     const int32_t *edof, int32_t plan, hipStream_t s,
+                     fs_asm_t *out);
+
+/* Host-only dry run of asm_create on HOST arrays (no device memory is
+ * touched, no GPU needed): builds the layout csr_layout_host would build
+ * for the square CSR pattern (rowptr, colind) and opts, then the plan for
+ * the matrix (which = 0) or the vector (which = 1).  Outputs: *ntasks
+ * tasks, *nwaves waves of 64 tasks, *stored index entries; waves (2 int32
+ * per wave: first index row, number of index rows), tpos (ntasks: output
+ * position of each task -- a layout value slot for the matrix, a row for
+ * the vector -- or -1 for a filler task that completes a wave) and aidx (stored: at (waves[2w] + j) * 64 + t % 64,
+ * entry j of task t's list of flat element-array indices, ascending, -1
+ * after the last).  Pass NULL arrays to learn the sizes first. */
+fs_status asm_plan_host(int32_t n_rows, int64_t nnz, const int32_t *rowptr,
+                        const int32_t *colind, const fs_csr_opts *opts,
+                        int32_t n_elem, int32_t nde, const int32_t *edof,
+                        int32_t which, int64_t *ntasks, int32_t *nwaves,
+                        int64_t *stored, int32_t *waves, int32_t *tpos,
+                        int32_t *aidx);
+
+/* Host-only dry run of the FS_ASM_ROWGROUP matrix plan on HOST arrays
+ * (same inputs as asm_plan_host).  *built = 0 when that plan does not
+ * apply.  Outputs: *ngroups row groups, *nbatch batches, *nrec records,
+ * *rows rows per batch (64 / nde); gdesc (4 int32 per group: first slot /
+ * 64, slots per lane, first batch, batches), bdesc (2 int32 per batch:
+ * first record, steps), ea (rows int32 per record: element row e*nde + a
+ * that batch row adds at that step, -1 none) and off (64 uint16 per record:
+ * for lane q*nde + b, the offset from the group's first slot of the slot
+ * that receives element value (ea[q]*nde + b), 0xffff none).  Pass NULL
+ * arrays to learn the sizes first. */
+fs_status asm_plan_host_groups(int32_t n_rows, int64_t nnz,
+                               const int32_t *rowptr, const int32_t *colind,
+                               const fs_csr_opts *opts, int32_t n_elem,
+                               int32_t nde, const int32_t *edof,
+                               int32_t *built, int32_t *ngroups,
+                               int64_t *nbatch, int64_t *nrec, int32_t *rows,
+                               int32_t *gdesc, int32_t *bdesc, int32_t *ea,
+                               uint16_t *off);
+
+/* Assemble the element matrices ke (n_elem x nde x nde FP64, device)
+ * straight into A's layout values, replacing them, and refresh A's FP32 /
+ * BF16 copies if it holds any (rounded as csr_update_values rounds).  Same
+ * effect as assembling K in CSR order and calling csr_update_values, without
+ * the CSR intermediate.  Asynchronous on s; ke must stay valid until the
+ * stream reaches the call. */
+fs_status asm_matrix(fs_asm_t P, const double *ke, hipStream_t s);
+
+/* Assemble the element vectors re (n_elem x nde FP64, device) into r
+ * (n_rows FP64, device, the caller's row numbering of A): every entry of r
+ * is written.  r must not overlap re.  Asynchronous on s. */
+fs_status asm_vector(fs_asm_t P, const double *re, double *r, hipStream_t s);
+
+typedef struct fs_asm_stats {
+    int32_t n_elem, nde;
+    int64_t contrib_matrix;   /* element entries that land in K             */
+    int64_t contrib_vector;   /* element entries that land in R             */
+    int64_t stored_matrix;    /* index entries stored for K, with padding
+                                 (4-byte positions, or 2-byte LDS offsets
+                                 for the row-group plan)                   */
+    int64_t stored_vector;    /* same for R                                 */
+    int64_t bytes_algorithmic_matrix; /* 12 contrib_matrix + 8 nnz: element
+                                 values and their 4-byte positions read,
+                                 the FP64 result written                    */
+    int64_t bytes_algorithmic_vector; /* 12 contrib_vector + 8 n_rows        */
+    int64_t device_bytes;     /* device memory held by the plan             */
+    double t_build_ms;        /* wall time of asm_create                    */
+    int32_t plan;             /* FS_ASM_GATHER or FS_ASM_ROWGROUP in use    */
+    int32_t reserved[7];
+} fs_asm_stats;
+
+fs_status asm_info(fs_asm_t P, fs_asm_stats *st);
+
+/* Free the plan (after synchronising the device).  NULL is a no-op. */
+fs_status asm_destroy(fs_asm_t P);
+
+/* Copy A's FP64 values back in the CSR order csr_create saw: vals[k] is the
+ * value at CSR position k (device array of nnz doubles).  The inverse of
+ * csr_update_values; use it to read what asm_matrix assembled.
+ * Asynchronous on s. */
+fs_status csr_get_values(fs_csr_t A, double *vals, hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

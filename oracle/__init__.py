@@ -79,6 +79,10 @@ def _declare(L):
     L.or_bf16_to_f32.restype = C.c_float
     L.or_round_array_f32.argtypes = [i64, _f64p, _f32p]
     L.or_round_array_bf16.argtypes = [i64, _f64p, _u16p]
+    L.or_assemble_matrix.argtypes = [i32, _i32p, _i32p, i32, i32, _i32p,
+                                     _f64p, _f64p]
+    L.or_assemble_matrix.restype = i64
+    L.or_assemble_vector.argtypes = [i32, i32, i32, _i32p, _f64p, _f64p]
     L.or_pcg.argtypes = [i32, _i32p, _i32p, _f64p, _f64p, _f64p, i32, f64,
                          i32, P(i32), P(f64)]
     L.or_pcg.restype = C.c_int
@@ -259,3 +263,33 @@ def ir_cg(A, a_lo, b, x0=None, precond=1, rtol=1e-8, inner_rtol=1e-3,
             float(inner_rtol), int(max_outer), int(max_inner),
             C.byref(o), C.byref(i), C.byref(rr))
     return x, st, o.value, i.value, rr.value
+
+
+def assemble_matrix(A, edof, ke):
+    """Values of the pattern of A (CSR: rowptr, col) assembled from element
+    matrices ke (n_elem x nde x nde) through edof (n_elem x nde, -1 = not
+    assembled), elements in order.  Raises ValueError naming the first
+    element whose coupling is missing from the pattern."""
+    L = load()
+    edof = np.ascontiguousarray(edof, dtype=np.int32)
+    ne, nde = edof.shape
+    ke = np.ascontiguousarray(ke, dtype=np.float64).reshape(ne, nde, nde)
+    rp = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+    c = np.ascontiguousarray(A.col, dtype=np.int32)
+    val = np.empty(len(c))
+    bad = L.or_assemble_matrix(A.n_rows, rp, c, ne, nde, edof, ke, val)
+    if bad:
+        raise ValueError("element %d couples DOFs outside the pattern"
+                         % (bad - 1))
+    return val
+
+
+def assemble_vector(n_rows, edof, re):
+    """r[I] = sum of re[e, a] over edof[e, a] == I, elements in order."""
+    L = load()
+    edof = np.ascontiguousarray(edof, dtype=np.int32)
+    ne, nde = edof.shape
+    re = np.ascontiguousarray(re, dtype=np.float64).reshape(ne, nde)
+    r = np.empty(n_rows)
+    L.or_assemble_vector(n_rows, ne, nde, edof, re, r)
+    return r

@@ -555,3 +555,58 @@ done:
     free(r64); free(d); free(r); free(z); free(p); free(q); free(dinv);
     return status;
 }
+
+/* ------------------------------------------------------------------------
+ * Finite-element assembly (section "Description of Current GPU Methods":
+ * every global non-zero K_IJ is the sum of the element contributions
+ * Ke_ab with I, J the global DOFs of local DOFs a, b; the residual R_I the
+ * sum of the element entries Re_a).  Written as the classic sequential
+ * element loop: entries start at 0.0 and every contribution is added when
+ * its element is visited, elements in increasing order, local (a, b) in
+ * row-major order.  edof[e*nde + a] < 0 marks a DOF that is not assembled.
+ * The CSR position of (I, J) is found by scanning row I.
+ * Returns 0, or 1 + e for the first element e that couples two DOFs whose
+ * entry is missing from the pattern.
+ * ---------------------------------------------------------------------- */
+int64_t or_assemble_matrix(int32_t n_rows, const int32_t *rowptr,
+                           const int32_t *col, int32_t n_elem, int32_t nde,
+                           const int32_t *edof, const double *ke,
+                           double *val)
+{
+    for (int32_t k = 0; k < rowptr[n_rows]; ++k)
+        val[k] = 0.0;
+    for (int32_t e = 0; e < n_elem; ++e) {
+        const int32_t *ed = edof + (int64_t)e * nde;
+        const double *K = ke + (int64_t)e * nde * nde;
+        for (int32_t a = 0; a < nde; ++a) {
+            const int32_t I = ed[a];
+            if (I < 0)
+                continue;
+            for (int32_t b = 0; b < nde; ++b) {
+                const int32_t J = ed[b];
+                if (J < 0)
+                    continue;
+                int32_t k = rowptr[I];
+                while (k < rowptr[I + 1] && col[k] != J)
+                    ++k;
+                if (k == rowptr[I + 1])
+                    return 1 + (int64_t)e;
+                val[k] += K[a * nde + b];
+            }
+        }
+    }
+    return 0;
+}
+
+void or_assemble_vector(int32_t n_rows, int32_t n_elem, int32_t nde,
+                        const int32_t *edof, const double *re, double *r)
+{
+    for (int32_t i = 0; i < n_rows; ++i)
+        r[i] = 0.0;
+    for (int32_t e = 0; e < n_elem; ++e)
+        for (int32_t a = 0; a < nde; ++a) {
+            const int32_t I = edof[(int64_t)e * nde + a];
+            if (I >= 0)
+                r[I] += re[(int64_t)e * nde + a];
+        }
+}

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "FS_OK", 1: "FS_E_ARG", 2: "FS_E_BAD_CSR",
                 9: "FS_E_UNSUPPORTED"}
 REORDER_AUTO, REORDER_NONE, REORDER_RCM, REORDER_USER = range(4)
 DT_F64, DT_F32, DT_BF16 = 1, 2, 4
+ASM_AUTO, ASM_GATHER, ASM_ROWGROUP = 0, 1, 2
 PC_NONE, PC_JACOBI = 0, 1
 PREC_F64, PREC_IR_F32, PREC_IR_BF16 = 0, 1, 2
 TO_LAYOUT, FROM_LAYOUT = 0, 1
@@ -83,6 +84,20 @@ class CgInfo(C.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class AsmStats(C.Structure):
+    _fields_ = [("n_elem", C.c_int32), ("nde", C.c_int32),
+                ("contrib_matrix", C.c_int64), ("contrib_vector", C.c_int64),
+                ("stored_matrix", C.c_int64), ("stored_vector", C.c_int64),
+                ("bytes_algorithmic_matrix", C.c_int64),
+                ("bytes_algorithmic_vector", C.c_int64),
+                ("device_bytes", C.c_int64), ("t_build_ms", C.c_double),
+                ("plan", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_
+                if n != "reserved"}
+
+
 # every symbol include/fespmv.h declares
 EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "csr_layout_host",
@@ -94,7 +109,11 @@ EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_async",
            "cg_solve_multi",
            "cg_solve_batch", "server_opts_default", "server_create",
-           "server_submit", "server_poll", "server_stats", "server_destroy"]
+           "server_submit", "server_poll", "server_stats", "server_destroy",
+           "asm_create", "asm_plan_host", "asm_plan_host_groups",
+           "asm_matrix", "asm_vector",
+           "asm_info",
+           "asm_destroy", "csr_get_values"]
 
 _lib = None
 
@@ -141,6 +160,17 @@ def load(build_if_missing=True):
         "cg_solve_multi": [vp, i32, vp, i64, vp, i64, P(CgOpts), P(CgInfo),
                            vp],
         "cg_solve_batch": [i32, vp, vp, vp, vp, P(CgOpts), P(CgInfo), vp],
+        "asm_create": [vp, i32, i32, vp, i32, vp, P(vp)],
+        "asm_plan_host_groups": [i32, i64, vp, vp, P(CsrOpts), i32, i32, vp,
+                                 P(i32), P(i32), P(i64), P(i64), P(i32), vp,
+                                 vp, vp, vp],
+        "asm_plan_host": [i32, i64, vp, vp, P(CsrOpts), i32, i32, vp, i32,
+                          P(i64), P(i32), P(i64), vp, vp, vp],
+        "asm_matrix": [vp, vp, vp],
+        "asm_vector": [vp, vp, vp, vp],
+        "asm_info": [vp, P(AsmStats)],
+        "asm_destroy": [vp],
+        "csr_get_values": [vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -277,6 +307,16 @@ def csr_update_values(A, val, stream=None):
     import torch
     _check(load().csr_update_values(A._h, _ptr(val, torch.float64, A.nnz,
                                                  "val"), _stream(stream)))
+
+
+def csr_get_values(A, out=None, stream=None):
+    """A's FP64 values in the CSR order csr_create saw (device tensor)."""
+    import torch
+    if out is None:
+        out = torch.empty(A.nnz, dtype=torch.float64, device="cuda")
+    _check(load().csr_get_values(A._h, _ptr(out, torch.float64, A.nnz,
+                                              "out"), _stream(stream)))
+    return out
 
 
 def csr_add_dtype(A, dtype, stream=None):
@@ -629,3 +669,127 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Assembly:
+    """Owning wrapper of an fs_asm_t plan; keeps its matrix alive."""
+
+    def __init__(self, handle, A, n_elem, nde):
+        self.handle, self.A = handle, A
+        self.n_elem, self.nde = n_elem, nde
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        if self.handle:
+            load().asm_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def _h(self):
+        if not self.handle:
+            raise FsError(FS_E_ARG, "assembly plan already destroyed")
+        return self.handle
+
+
+def asm_create(A, edof, plan=0, stream=None):
+    """Assembly plan for A from the n_elem x nde int32 device tensor edof
+    (-1 = DOF not in A); plan is ASM_AUTO, ASM_GATHER or ASM_ROWGROUP."""
+    import torch
+    if edof.dim() != 2:
+        raise FsError(FS_E_ARG, "edof must be n_elem x nde")
+    ne, nde = edof.shape
+    h = C.c_void_p()
+    _check(load().asm_create(A._h, ne, nde,
+                             _ptr(edof, torch.int32, ne * nde, "edof"),
+                             int(plan), _stream(stream), C.byref(h)))
+    return Assembly(h.value, A, ne, nde)
+
+
+def asm_plan_host(rowptr, col, edof, which=0, **opts):
+    """Host-only dry run of asm_create (numpy arrays); returns dict(waves
+    (nwaves x 2), tpos, aidx) of the matrix (which=0) or vector plan."""
+    import numpy as np
+    L = load()
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    edof = np.ascontiguousarray(edof, dtype=np.int32)
+    ne, nde = edof.shape
+    n = len(rowptr) - 1
+    o = csr_opts(**opts)
+    nt, nw, ns = C.c_int64(), C.c_int32(), C.c_int64()
+    args = [n, len(col), rowptr.ctypes.data, col.ctypes.data, C.byref(o),
+            ne, nde, edof.ctypes.data if edof.size else None, which,
+            C.byref(nt), C.byref(nw), C.byref(ns)]
+    _check(L.asm_plan_host(*args, None, None, None))
+    waves = np.zeros((nw.value, 2), np.int32)
+    tpos = np.zeros(nt.value, np.int32)
+    aidx = np.zeros(ns.value, np.int32)
+    _check(L.asm_plan_host(*args, waves.ctypes.data, tpos.ctypes.data,
+                           aidx.ctypes.data))
+    return dict(waves=waves, tpos=tpos, aidx=aidx)
+
+
+def asm_plan_host_groups(rowptr, col, edof, **opts):
+    """Host-only dry run of the row-group matrix plan; None when it does
+    not apply, else dict(gdesc (ngroups x 4), bdesc (nbatch x 2), ea
+    (nrec x rows), off (nrec x 64 uint16), rows)."""
+    import numpy as np
+    L = load()
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    edof = np.ascontiguousarray(edof, dtype=np.int32)
+    ne, nde = edof.shape
+    n = len(rowptr) - 1
+    o = csr_opts(**opts)
+    b, ng, nr = C.c_int32(), C.c_int32(), C.c_int32()
+    nb, nrec = C.c_int64(), C.c_int64()
+    args = [n, len(col), rowptr.ctypes.data, col.ctypes.data, C.byref(o),
+            ne, nde, edof.ctypes.data if edof.size else None, C.byref(b),
+            C.byref(ng), C.byref(nb), C.byref(nrec), C.byref(nr)]
+    _check(L.asm_plan_host_groups(*args, None, None, None, None))
+    if not b.value:
+        return None
+    gdesc = np.zeros((ng.value, 4), np.int32)
+    bdesc = np.zeros((nb.value, 2), np.int32)
+    ea = np.zeros((nrec.value, nr.value), np.int32)
+    off = np.zeros((nrec.value, 64), np.uint16)
+    _check(L.asm_plan_host_groups(*args, gdesc.ctypes.data, bdesc.ctypes.data,
+                                  ea.ctypes.data, off.ctypes.data))
+    return dict(gdesc=gdesc, bdesc=bdesc, ea=ea, off=off, rows=nr.value)
+
+
+def asm_matrix(P, ke, stream=None):
+    """Assemble the element matrices ke (n_elem x nde x nde float64, device)
+    into the values of P's matrix."""
+    import torch
+    _check(load().asm_matrix(P._h, _ptr(ke, torch.float64,
+                                        P.n_elem * P.nde * P.nde, "ke"),
+                             _stream(stream)))
+
+
+def asm_vector(P, re, r=None, stream=None):
+    """r = assembled element vectors re (n_elem x nde float64, device), in
+    the caller's row numbering; returns r."""
+    import torch
+    if r is None:
+        r = torch.empty(P.A.n_rows, dtype=torch.float64, device="cuda")
+    _check(load().asm_vector(P._h, _ptr(re, torch.float64, P.n_elem * P.nde,
+                                        "re"),
+                             _ptr(r, torch.float64, P.A.n_rows, "r"),
+                             _stream(stream)))
+    return r
+
+
+def asm_info(P):
+    st = AsmStats()
+    _check(load().asm_info(P._h, C.byref(st)))
+    return st.as_dict()
+
+
+def asm_destroy(P):
+    P.close()

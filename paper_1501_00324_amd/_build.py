@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfespmv.so")
 SOURCES = ["api.cpp", "layout.cpp", "solver.cpp", "server.cpp", "kernels.hip",
-           "engine.hip", "batch.hip", "persist.hip", "csr.hip"]
+           "engine.hip", "batch.hip", "persist.hip", "csr.hip", "asm.cpp",
+           "asm.hip"]
 ARCH = os.environ.get("FESPMV_ARCH", "gfx950")
 
 FLAGS = [

@@ -9,57 +9,12 @@
 #include <mutex>
 #include <tuple>
 
-#include "internal.h"
+#include "host.h"
 
 namespace fs {
 
 namespace {
 thread_local std::string g_last_error;
-
-double now_ms()
-{
-    using namespace std::chrono;
-    return duration<double, std::milli>(
-               steady_clock::now().time_since_epoch()).count();
-}
-
-struct DeviceGuard {
-    int prev = -1, want;
-    explicit DeviceGuard(int d) : want(d)
-    {
-        if (hipGetDevice(&prev) == hipSuccess && prev != want)
-            (void)hipSetDevice(want);
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
-    }
-};
-
-template <class T>
-fs_status dalloc(T **p, int64_t count, int64_t &acct)
-{
-    *p = nullptr;
-    if (count <= 0) return FS_OK;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(p),
-                             size_t(count) * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return set_error(e == hipErrorOutOfMemory ? FS_E_OOM : FS_E_HIP,
-                         "hipMalloc(%lld bytes): %s",
-                         (long long)(count * int64_t(sizeof(T))),
-                         hipGetErrorString(e));
-    }
-    acct += count * int64_t(sizeof(T));
-    return FS_OK;
-}
-
-template <class T> void dfree(T *&p)
-{
-    if (p) (void)hipFree(p);
-    p = nullptr;
-}
 
 void free_handle(fs_csr *A)
 {
@@ -475,6 +430,15 @@ fs_status csr_update_values(fs_csr_t A, const double *vals, hipStream_t s)
     DeviceGuard g(A->device);
     FS_HIP_TRY(launch_value_scatter(vals, A->d_map, A->nnz, A->d_val,
                                     A->d_val_f32, A->d_val_bf16, s));
+    return FS_OK;
+}
+
+fs_status csr_get_values(fs_csr_t A, double *vals, hipStream_t s)
+{
+    FS_TRY(check_handle(A));
+    if (!vals && A->nnz > 0) return set_error(FS_E_ARG, "NULL values");
+    DeviceGuard g(A->device);
+    FS_HIP_TRY(launch_value_gather(A->d_val, A->d_map, A->nnz, vals, s));
     return FS_OK;
 }
 

@@ -158,6 +158,16 @@ __device__ __forceinline__ int load_gbase(const int32_t *gbase, int g)
     return gbase ? __builtin_amdgcn_readfirstlane(gbase[g]) : 0;
 }
 
+// float -> bfloat16, round to nearest even; NaN stays a (quiet) NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return uint16_t((u >> 16) | 0x0040u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
 inline int vec_blocks(long n)
 {
     long b = (n + kBlock - 1) / kBlock;

@@ -948,15 +948,6 @@ __global__ __launch_bounds__(kBlock) void k_add_f32(long n, double alpha,
         x[e] += alpha * double(d[e]);
 }
 
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
-        return uint16_t((u >> 16) | 0x0040u);        // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);                   // nearest, ties even
-    return uint16_t(u >> 16);
-}
-
 // Low-precision copies of the slot values (padding stays 0).
 __global__ __launch_bounds__(kBlock) void k_cast_slots(
     long n, const double *__restrict__ v, float *__restrict__ f32,
@@ -966,7 +957,7 @@ __global__ __launch_bounds__(kBlock) void k_cast_slots(
          e += long(gridDim.x) * kBlock) {
         const float f = float(v[e]);
         if (f32) f32[e] = f;
-        if (bf16) bf16[e] = f32_to_bf16_bits(f);
+        if (bf16) bf16[e] = f32_to_bf16_rne(f);
     }
 }
 

@@ -276,4 +276,57 @@ hipError_t launch_read_probe(const double *buf, int64_t n, double *sink,
 // float accumulation), A_lo the FP32 or BF16 copy.
 hipError_t launch_spmv_lowp(const fs_csr *A, int32_t dtype, const float *x,
                             float *y, hipStream_t s);
+// vals[k] = slot_val[map[k]]: the FP64 values back in CSR order.
+hipError_t launch_value_gather(const double *slot_val, const int32_t *map,
+                               int64_t nnz, double *vals, hipStream_t s);
+
+// ------------------------------------------------------------- assembly
+// Device plan of one sum-only product out[tpos[t]] = sum_j in[idx_t(j)]
+// (tpos[t] = -1: a filler task, nothing written): tasks t are cut into
+// waves of 64; wave w stores its tasks' index lists
+// column-interleaved, idx_t(j) = aidx[(base64 + j) * 64 + t % 64] for
+// j < width (-1 after a task's last entry), base64 and width = waves[w].
+struct AsmPlan {
+    int64_t ntasks = 0;
+    int32_t nwaves = 0;
+    int64_t stored = 0;          // aidx entries, padding included
+    int64_t contrib = 0;         // entries that are not padding
+    int32_t *d_waves = nullptr;  // 2 per wave: base64, width
+    int32_t *d_tpos = nullptr;
+    int32_t *d_aidx = nullptr;
+};
+// f32 / bf16 (may be NULL) receive the rounded result at the same place.
+hipError_t launch_assemble(const AsmPlan &P, const double *in, double *out,
+                           float *f32, uint16_t *bf16, hipStream_t s);
+// Row-group plan of the matrix assembly (accumulation in LDS): one
+// workgroup per row group of the layout zeroes the group's slot region in
+// LDS, adds the element values of its rows into it and writes the region
+// out.  The rows of a group are taken `rows` (= 64 / nde) at a time by one
+// wavefront (a batch); step k of a batch gives every row of the batch its
+// k-th element row e*nde + a (ascending) and lane q*nde + b adds element
+// value (e*nde + a)*nde + b at its LDS offset.
+constexpr int kAsmLdsMax = 6144;  // doubles of LDS per group region (48 KiB)
+struct AsmLdsPlan {
+    int32_t ngroups = 0, nde = 0, rows = 0;
+    int32_t region_max = 0;      // doubles of the widest group region
+    int64_t nbatch = 0, nrec = 0, contrib = 0;
+    int32_t *d_gdesc = nullptr;  // 4 per group: base64, width, batch0, nbatch
+    int32_t *d_bdesc = nullptr;  // 2 per batch: first record, steps
+    int32_t *d_ea = nullptr;     // `rows` per record: e*nde + a, -1 = none
+    uint16_t *d_off = nullptr;   // 64 per record: LDS offset, 0xffff = none
+};
+hipError_t launch_assemble_lds(const AsmLdsPlan &P, const double *ke,
+                               double *val, float *f32, uint16_t *bf16,
+                               hipStream_t s);
 }  // namespace fs
+
+struct fs_asm {
+    fs_csr *A = nullptr;
+    int device = 0;
+    int32_t n_elem = 0, nde = 0;
+    bool lds = false;            // matrix by the row-group plan kl
+    fs::AsmPlan km, rv;          // matrix (into A's slots), vector (rows)
+    fs::AsmLdsPlan kl;
+    double t_build_ms = 0.0;
+    int64_t device_bytes = 0;
+};

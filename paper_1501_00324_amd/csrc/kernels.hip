@@ -55,15 +55,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_f64(
 }
 
 // ---------------------------------------------------------- data movement
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
-        return uint16_t((u >> 16) | 0x0040u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return uint16_t(u >> 16);
-}
-
 __global__ __launch_bounds__(kBlock) void k_value_scatter(
     const double *__restrict__ vals, const int *__restrict__ map, long nnz,
     double *__restrict__ out, float *__restrict__ f32,
@@ -78,6 +69,15 @@ __global__ __launch_bounds__(kBlock) void k_value_scatter(
         if (f32) f32[s] = f;
         if (bf16) bf16[s] = f32_to_bf16_rne(f);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_value_gather(
+    const double *__restrict__ slot_val, const int *__restrict__ map,
+    long nnz, double *__restrict__ vals)
+{
+    for (long k = long(blockIdx.x) * kBlock + threadIdx.x; k < nnz;
+         k += long(gridDim.x) * kBlock)
+        vals[k] = slot_val[map[k]];
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather(
@@ -110,6 +110,17 @@ hipError_t launch_value_scatter(const double *vals, const int32_t *map,
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_value_scatter, dim3(unsigned(blocks)), dim3(kBlock),
                        0, s, vals, map, long(nnz), slot_val, f32, bf16);
+    return hipGetLastError();
+}
+
+hipError_t launch_value_gather(const double *slot_val, const int32_t *map,
+                               int64_t nnz, double *vals, hipStream_t s)
+{
+    if (nnz == 0) return hipSuccess;
+    long blocks = (nnz + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_value_gather, dim3(unsigned(blocks)), dim3(kBlock),
+                       0, s, slot_val, map, long(nnz), vals);
     return hipGetLastError();
 }
 

@@ -18,31 +18,10 @@
 #include <numeric>
 #include <thread>
 
-#include "internal.h"
+#include "host.h"
 
 namespace fs {
 namespace {
-
-// f(c) for every chunk c in [0, nchunks), spread over up to 16 host
-// threads.  Chunks are independent; results must not depend on which
-// thread ran which chunk.
-template <class F> void parallel_chunks(int64_t nchunks, F f)
-{
-    const int64_t hw = std::max<int64_t>(1, std::thread::hardware_concurrency());
-    const int64_t nt = std::min<int64_t>({hw, int64_t(16), nchunks});
-    if (nt <= 1) {
-        for (int64_t c = 0; c < nchunks; ++c) f(c);
-        return;
-    }
-    std::atomic<int64_t> next(0);
-    std::vector<std::thread> th;
-    th.reserve(size_t(nt));
-    for (int64_t t = 0; t < nt; ++t)
-        th.emplace_back([&]() {
-            for (int64_t c = next++; c < nchunks; c = next++) f(c);
-        });
-    for (auto &t : th) t.join();
-}
 
 constexpr int64_t kRowChunk = 16384;
 

@@ -8,17 +8,10 @@
 #include <cmath>
 #include <cstring>
 
-#include "internal.h"
+#include "host.h"
 
 namespace fs {
 namespace {
-
-double now_ms()
-{
-    using namespace std::chrono;
-    return duration<double, std::milli>(
-               steady_clock::now().time_since_epoch()).count();
-}
 
 size_t st_size(int32_t st) { return st == ST_F64 ? 8 : 4; }
 
@@ -36,12 +29,6 @@ fs_status dmalloc(void **p, size_t bytes, int64_t &acct)
     }
     acct += int64_t(bytes);
     return FS_OK;
-}
-
-template <class T> void dfree(T *&p)
-{
-    if (p) (void)hipFree(p);
-    p = nullptr;
 }
 
 const void *values_of(const fs_csr *A, int32_t vt)
@@ -356,19 +343,6 @@ fs_status normalise_opts(const fs_cg_opts *in, fs_cg_opts &o)
         return set_error(FS_E_ARG, "unknown precision %d", o.precision);
     return FS_OK;
 }
-
-struct DeviceGuard {
-    int prev = -1, want;
-    explicit DeviceGuard(int d) : want(d)
-    {
-        if (hipGetDevice(&prev) == hipSuccess && prev != want)
-            (void)hipSetDevice(want);
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
-    }
-};
 
 fs_status ensure_stream(fs_csr *A)
 {
