@@ -72,14 +72,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv_batch(
         (b - p.b0) * kWavesPerBlock + int(threadIdx.x >> 6));
     if (g >= p.ngroups) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const Group gd = load_group(p.groups, g);
+    const Group gd = load_group(gbl(p.groups), g);
     const int lt = gd.width_lt >> 24;
     const double acc =
-        p.gbase ? row_reduce(group_lane_sum<V, true>(gd, lane, p.val, p.col,
-                                                     load_gbase(p.gbase, g),
-                                                     p.x), lt)
-                : row_reduce(group_lane_sum<V, false>(gd, lane, p.val, p.col,
-                                                      0, p.x), lt);
+        p.gbase ? row_reduce(group_lane_sum<V, true>(
+                                 gd, lane, gbl(p.val), gbl(p.col),
+                                 load_gbase(gbl(p.gbase), g), gbl(p.x)),
+                             lt)
+                : row_reduce(group_lane_sum<V, false>(gd, lane, gbl(p.val),
+                                                      gbl(p.col), 0,
+                                                      gbl(p.x)),
+                             lt);
     const int r = lane >> lt;
     if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
         const int row = gd.row0 + r;

@@ -17,6 +17,24 @@ typedef float fv2 __attribute__((ext_vector_type(2)));
 typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 
 constexpr int kWavesPerBlock = kBlock / kWave;
+
+// Pointers into global memory.  Most kernels find their pointers inside
+// descriptor structs, where the compiler cannot tell that they address
+// global memory and emits flat accesses (which also count against the LDS
+// counter, so they serialise with cross-lane shuffles, and rule out scalar
+// loads of uniform data); casting them to the global address space gives
+// plain global and scalar loads.
+#define FS_GLOBAL __attribute__((address_space(1)))
+template <class T> using gptr = const FS_GLOBAL T *;
+template <class T> using gmut = FS_GLOBAL T *;
+template <class T> __device__ __forceinline__ gptr<T> gbl(const T *p)
+{
+    return (gptr<T>)p;
+}
+template <class T> __device__ __forceinline__ gmut<T> gblw(T *p)
+{
+    return (gmut<T>)p;
+}
 constexpr int kVecBlocks = 1024;   // max workgroups of the vector kernels
 
 // Workgroups are dispatched round-robin over the 8 XCDs; renumber so XCD k
@@ -49,11 +67,11 @@ template <int V, bool NARROW> struct ColStream {
     typedef typename std::conditional<NARROW, typename Slots<V>::H,
                                       typename Slots<V>::I>::type P;
     typedef typename std::conditional<NARROW, uint16_t, int32_t>::type E;
-    const P *p;
+    gptr<P> p;
     int gb;
-    __device__ __forceinline__ ColStream(const void *col, long base, int lane,
+    __device__ __forceinline__ ColStream(gptr<void> col, long base, int lane,
                                          int gbase)
-        : p(reinterpret_cast<const P *>(static_cast<const E *>(col) + base) +
+        : p(reinterpret_cast<gptr<P>>(static_cast<gptr<E>>(col) + base) +
             lane),
           gb(gbase)
     {
@@ -75,7 +93,7 @@ template <int V, bool NARROW> struct ColStream {
 // Padded slots (column -1) read x[0] (always in bounds: a matrix with
 // slots has at least one column) and the select drops the product, so an
 // Inf/NaN there never reaches the sum.
-__device__ __forceinline__ void slot_fma(int c, double a, const double *x,
+__device__ __forceinline__ void slot_fma(int c, double a, gptr<double> x,
                                          double &acc)
 {
     const double xv = x[c < 0 ? 0 : c];
@@ -88,17 +106,16 @@ __device__ __forceinline__ void slot_fma(int c, double a, const double *x,
 // ~12 KiB of the stream plus 512 gathers in flight.
 template <int V, bool NARROW>
 __device__ __forceinline__ double group_lane_sum(const Group &g, int lane,
-                                                 const double *__restrict__ val,
-                                                 const void *__restrict__ col,
-                                                 int gb,
-                                                 const double *__restrict__ x)
+                                                 gptr<double> val,
+                                                 gptr<void> col, int gb,
+                                                 gptr<double> x)
 {
     typedef typename Slots<V>::D D;
     typedef ColStream<V, NARROW> CS;
     constexpr int U = 8 / V;
     const int width = g.width_lt & 0xffffff;
     const long base = long(g.base64) * kWave;
-    const D *pv = reinterpret_cast<const D *>(val + base) + lane;
+    gptr<D> pv = reinterpret_cast<gptr<D>>(val + base) + lane;
     const CS cs(col, base, lane, gb);
     const int nch = width / V;
     double acc0 = 0.0, acc1 = 0.0;
@@ -142,18 +159,18 @@ __device__ __forceinline__ T row_reduce(T acc, int lt)
     return acc;
 }
 
-__device__ __forceinline__ Group load_group(const Group *groups, int g)
+__device__ __forceinline__ Group load_group(gptr<Group> groups, int g)
 {
-    Group d = groups[g];
-    d.base64 = __builtin_amdgcn_readfirstlane(d.base64);
-    d.row0 = __builtin_amdgcn_readfirstlane(d.row0);
-    d.nrows = __builtin_amdgcn_readfirstlane(d.nrows);
-    d.width_lt = __builtin_amdgcn_readfirstlane(d.width_lt);
+    Group d;
+    d.base64 = __builtin_amdgcn_readfirstlane(groups[g].base64);
+    d.row0 = __builtin_amdgcn_readfirstlane(groups[g].row0);
+    d.nrows = __builtin_amdgcn_readfirstlane(groups[g].nrows);
+    d.width_lt = __builtin_amdgcn_readfirstlane(groups[g].width_lt);
     return d;
 }
 
 // Column base of group g for 16-bit column offsets (0 when there are none).
-__device__ __forceinline__ int load_gbase(const int32_t *gbase, int g)
+__device__ __forceinline__ int load_gbase(gptr<int32_t> gbase, int g)
 {
     return gbase ? __builtin_amdgcn_readfirstlane(gbase[g]) : 0;
 }

@@ -75,11 +75,9 @@ __device__ __forceinline__ void unpack(typename Pack<VT, V>::T a, ST (&o)[V])
 // drop the product through a select.
 template <typename VT, typename ST, int V, int KM, bool N>
 __device__ __forceinline__ void lane_sums(const Group &g, int lane,
-                                          const VT *__restrict__ val,
-                                          const void *__restrict__ col, int gb,
-                                          const ST *__restrict__ X, int k,
-                                          long ldx, ST (&acc0)[KM],
-                                          ST (&acc1)[KM])
+                                          gptr<VT> val, gptr<void> col,
+                                          int gb, gptr<ST> X, int k, long ldx,
+                                          ST (&acc0)[KM], ST (&acc1)[KM])
 {
     typedef typename Pack<VT, V>::T PV;
     typedef ColStream<V, N> CS;
@@ -88,11 +86,11 @@ __device__ __forceinline__ void lane_sums(const Group &g, int lane,
     constexpr int U = U0 / V > 0 ? U0 / V : 1;
     const int width = g.width_lt & 0xffffff;
     const long base = long(g.base64) * kWave;
-    const PV *pv = reinterpret_cast<const PV *>(val + base) + lane;
+    gptr<PV> pv = reinterpret_cast<gptr<PV>>(val + base) + lane;
     const CS cs(col, base, lane, gb);
     const int nch = width / V;
     auto slot = [&](int c, ST a, bool odd) {
-        const ST *xr = X + long(c < 0 ? 0 : c) * ldx;
+        gptr<ST> xr = X + long(c < 0 ? 0 : c) * ldx;
 #pragma unroll
         for (int q = 0; q < KM; ++q) {
             if (KM == 1 || q < k) {
@@ -231,10 +229,9 @@ __device__ __forceinline__ void store_col_partials(double (&v)[NVPC], int k,
 // emit(row_in_group, q, value) is called once per (row, column < k).
 template <typename VT, typename ST, int V, int KM, bool N, class Emit>
 __device__ __forceinline__ void coop_group(const Group &g, int lane,
-                                           const VT *__restrict__ val,
-                                           const void *__restrict__ col,
-                                           int gb, const ST *__restrict__ X,
-                                           int k, long ldx, Emit emit)
+                                           gptr<VT> val, gptr<void> col,
+                                           int gb, gptr<ST> X, int k,
+                                           long ldx, Emit emit)
 {
     static_assert(KM > 1, "single-column products use lane_sums");
     typedef typename Pack<VT, V>::T PV;
@@ -243,11 +240,16 @@ __device__ __forceinline__ void coop_group(const Group &g, int lane,
     const int q = lane % KM, m = lane / KM;
     const int width = g.width_lt & 0xffffff;
     const long base = long(g.base64) * kWave;
-    const PV *pv = reinterpret_cast<const PV *>(val + base) + lane;
+    gptr<PV> pv = reinterpret_cast<gptr<PV>>(val + base) + lane;
     const CS cs(col, base, lane, gb);
     ST acc[KM];
 #pragma unroll
     for (int r = 0; r < KM; ++r) acc[r] = ST(0);
+    // columns q >= k read column 0 and drop it, so no load sits behind a
+    // branch and a round's gathers are all in flight together
+    const bool qok = q < k;
+    const int qc = qok ? q : 0;
+    constexpr int RB = KM < 8 ? KM : 8;      // rounds per batch of gathers
     const int nch = width / V;
     for (int j = 0; j < nch; ++j) {
         int cc[V];
@@ -259,14 +261,25 @@ __device__ __forceinline__ void coop_group(const Group &g, int lane,
 #pragma unroll
         for (int t = 0; t < V; ++t) {
 #pragma unroll
-            for (int r = 0; r < KM; ++r) {
-                const int src = r * R + m;
-                const int cs = __shfl(cc[t], src, kWave);
-                const ST as = __shfl(aa[t], src, kWave);
-                if (q < k) {
-                    const ST xv = X[long(cs < 0 ? 0 : cs) * ldx + q];
-                    acc[r] = fma(as, cs >= 0 ? xv : ST(0), acc[r]);
+            for (int r0 = 0; r0 < KM; r0 += RB) {
+                int sc[RB];
+                ST sa[RB], xv[RB];
+#pragma unroll
+                for (int u = 0; u < RB; ++u) {
+                    const int src = (r0 + u) * R + m;
+                    sc[u] = __shfl(cc[t], src, kWave);
+                    sa[u] = __shfl(aa[t], src, kWave);
                 }
+#pragma unroll
+                for (int u = 0; u < RB; ++u)
+                    xv[u] = X[long(sc[u] < 0 ? 0 : sc[u]) * ldx + qc];
+#pragma unroll
+                for (int u = 0; u < RB; ++u)
+                    acc[r0 + u] = fma(sa[u], (qok && sc[u] >= 0) ? xv[u] : ST(0),
+                                      acc[r0 + u]);
+                // keep the scheduler from hoisting the next batch's gathers
+                // above this one (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
@@ -306,26 +319,28 @@ __device__ __forceinline__ void coop_group(const Group &g, int lane,
 }
 
 // Occupancy floor (waves per SIMD) of the products in the CG iteration:
-// the gathers are latency bound, and without a floor KM = 1 / 8 / 16
-// settle at 7 / 5 / 3 waves; 8 / 6 / 4 fit their registers without
-// spilling.
-constexpr int spmm_dot_min_waves(int km)
+// the gathers are latency bound; KM = 1 holds 7 waves (at 8 the FP64
+// product spills a register and the solve slows by 13%), KM = 8 and 16
+// hold 4 (128 registers), except the float KM = 16 product, which needs
+// more registers and keeps 3.
+constexpr int spmm_dot_min_waves(int km, int st_bytes)
 {
-    return km == 16 ? 4 : km == 8 ? 6 : km == 1 ? 8 : 1;
+    return km == 16 && st_bytes == 4 ? 3 : km >= 8 ? 4 : km == 1 ? 7 : 1;
 }
 
 // Q = A P for every column with per-block partials of p_c . q_c.
 template <typename VT, typename ST, int V, int KM>
-__global__ __launch_bounds__(kBlock, spmm_dot_min_waves(KM)) void k_spmm_dot(
+__global__ __launch_bounds__(kBlock, spmm_dot_min_waves(KM, int(sizeof(ST)))) void k_spmm_dot(
     const SysDesc *__restrict__ sys, const int *__restrict__ smap)
 {
     const int gb = xcd_remap(blockIdx.x, gridDim.x);
     const SysDesc &S = sys[smap[gb]];
     if (!any_running(S)) return;
     const int lb = gb - S.sb0, nb = S.snb, k = S.k;
-    const VT *val = static_cast<const VT *>(S.val);
-    const ST *P = static_cast<const ST *>(S.p);
-    ST *Q = static_cast<ST *>(S.q);
+    const auto val = gbl(static_cast<const VT *>(S.val));
+    const auto P = gbl(static_cast<const ST *>(S.p));
+    const auto Q = gblw(static_cast<ST *>(S.q));
+    const auto cst = gbl(S.cstream);
     const int g0 = int(long(lb) * S.ngroups / nb);
     const int g1 = int(long(lb + 1) * S.ngroups / nb);
     const int lane = threadIdx.x & (kWave - 1);
@@ -334,12 +349,12 @@ __global__ __launch_bounds__(kBlock, spmm_dot_min_waves(KM)) void k_spmm_dot(
         constexpr bool N = decltype(nt)::value;
         for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
             const Group gd =
-                load_group(S.groups, __builtin_amdgcn_readfirstlane(g));
-            const int gb = N ? load_gbase(S.gbase, g) : 0;
+                load_group(gbl(S.groups), __builtin_amdgcn_readfirstlane(g));
+            const int gb = N ? load_gbase(gbl(S.gbase), g) : 0;
             if constexpr (KM == 1) {
                 ST a0[1] = {ST(0)}, a1[1] = {ST(0)};
-                lane_sums<VT, ST, V, 1, N>(gd, lane, val, S.cstream, gb, P, 1,
-                                           1, a0, a1);
+                lane_sums<VT, ST, V, 1, N>(gd, lane, val, cst, gb, P, 1, 1,
+                                           a0, a1);
                 const int lt = gd.width_lt >> 24, r = lane >> lt;
                 const ST v = row_reduce(a0[0] + a1[0], lt);
                 if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
@@ -349,7 +364,7 @@ __global__ __launch_bounds__(kBlock, spmm_dot_min_waves(KM)) void k_spmm_dot(
                 }
             } else {
                 coop_group<VT, ST, V, KM, N>(
-                    gd, lane, val, S.cstream, gb, P, k, k,
+                    gd, lane, val, cst, gb, P, k, k,
                     [&](int rg, int q, ST v) {
                         const long e = long(gd.row0 + rg) * k + q;
                         Q[e] = v;
@@ -574,12 +589,13 @@ __global__ __launch_bounds__(kBlock) void k_residual(
     const int gb = xcd_remap(blockIdx.x, gridDim.x);
     const SysDesc &S = sys[smap[gb]];
     const int lb = gb - S.sb0, nb = S.snb, k = S.k;
-    const VT *val = static_cast<const VT *>(S.val);
-    const ST *X = static_cast<const ST *>(S.x);
-    const ST *B = static_cast<const ST *>(S.b);
-    const ST *D = static_cast<const ST *>(S.dinv);
-    ST *R = static_cast<ST *>(S.r);
-    ST *P = static_cast<ST *>(S.p);
+    const auto val = gbl(static_cast<const VT *>(S.val));
+    const auto X = gbl(static_cast<const ST *>(S.x));
+    const auto B = gbl(static_cast<const ST *>(S.b));
+    const auto D = gbl(static_cast<const ST *>(S.dinv));
+    const auto R = gblw(static_cast<ST *>(S.r));
+    const auto P = gblw(static_cast<ST *>(S.p));
+    const auto cst = gbl(S.cstream);
     bool wr[KM];
 #pragma unroll
     for (int c = 0; c < KM; ++c)
@@ -593,18 +609,19 @@ __global__ __launch_bounds__(kBlock) void k_residual(
 #pragma unroll
     for (int c = 0; c < 3 * KM; ++c) v[c] = 0.0;
     for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
-        const Group gd = load_group(S.groups, __builtin_amdgcn_readfirstlane(g));
+        const Group gd =
+            load_group(gbl(S.groups), __builtin_amdgcn_readfirstlane(g));
         ST a0[KM], a1[KM];
 #pragma unroll
         for (int c = 0; c < KM; ++c) a0[c] = a1[c] = ST(0);
         if (!XZ) {
             if (S.gbase)
-                lane_sums<VT, ST, V, KM, true>(gd, lane, val, S.cstream,
-                                               load_gbase(S.gbase, g), X, k,
-                                               k, a0, a1);
+                lane_sums<VT, ST, V, KM, true>(gd, lane, val, cst,
+                                               load_gbase(gbl(S.gbase), g), X,
+                                               k, k, a0, a1);
             else
-                lane_sums<VT, ST, V, KM, false>(gd, lane, val, S.cstream, 0,
-                                                X, k, k, a0, a1);
+                lane_sums<VT, ST, V, KM, false>(gd, lane, val, cst, 0, X, k,
+                                                k, a0, a1);
         }
         const int lt = gd.width_lt >> 24, r = lane >> lt;
         const bool owner = (lane & ((1 << lt) - 1)) == 0 && r < gd.nrows;
@@ -703,7 +720,8 @@ __global__ __launch_bounds__(kBlock) void k_diag(
     const int g1 = int(long(lb + 1) * S.ngroups / nb);
     const int lane = threadIdx.x & (kWave - 1);
     for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kWavesPerBlock) {
-        const Group gd = load_group(S.groups, __builtin_amdgcn_readfirstlane(g));
+        const Group gd =
+            load_group(gbl(S.groups), __builtin_amdgcn_readfirstlane(g));
         const int lt = gd.width_lt >> 24, width = gd.width_lt & 0xffffff;
         const int r = lane >> lt;
         const int row = gd.row0 + r;
@@ -737,11 +755,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
         b * kWavesPerBlock + int(threadIdx.x >> 6));
     if (g >= ngroups) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const Group gd = load_group(groups, g);
-    const int gb = N ? load_gbase(gbase, g) : 0;
+    const Group gd = load_group(gbl(groups), g);
+    const int gb = N ? load_gbase(gbl(gbase), g) : 0;
     if constexpr (KM == 1) {
         ST a0[1] = {ST(0)}, a1[1] = {ST(0)};
-        lane_sums<VT, ST, V, 1, N>(gd, lane, val, col, gb, X, 1, ldx, a0, a1);
+        lane_sums<VT, ST, V, 1, N>(gd, lane, gbl(val), gbl(col), gb, gbl(X),
+                                   1, ldx, a0, a1);
         const int lt = gd.width_lt >> 24, r = lane >> lt;
         const ST v = row_reduce(a0[0] + a1[0], lt);
         if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
@@ -750,7 +769,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
         }
     } else {
         coop_group<VT, ST, V, KM, N>(
-            gd, lane, val, col, gb, X, k, ldx, [&](int rg, int q, ST v) {
+            gd, lane, gbl(val), gbl(col), gb, gbl(X), k, ldx,
+            [&](int rg, int q, ST v) {
                 const int row = gd.row0 + rg;
                 Y[(SCATTER ? long(yperm[row]) : long(row)) * ldy + q] = v;
             });

@@ -42,11 +42,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_f64(
         b * kWavesPerBlock + int(threadIdx.x >> 6));
     if (g >= ngroups) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const Group gd = load_group(groups, g);
+    const Group gd = load_group(gbl(groups), g);
     const int lt = gd.width_lt >> 24;
-    const int gb = NARROW ? load_gbase(gbase, g) : 0;
+    const int gb = NARROW ? load_gbase(gbl(gbase), g) : 0;
     double acc = row_reduce(
-        group_lane_sum<V, NARROW>(gd, lane, val, col, gb, x), lt);
+        group_lane_sum<V, NARROW>(gd, lane, gbl(val), gbl(col), gb, gbl(x)),
+        lt);
     const int r = lane >> lt;
     if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
         const int row = gd.row0 + r;

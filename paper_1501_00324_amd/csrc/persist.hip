@@ -102,13 +102,15 @@ __device__ __forceinline__ void residual_rows(const PcgArgs &a, int g0, int g1,
 {
     const int lane = threadIdx.x & (kWave - 1);
     for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kPW) {
-        const Group gd = load_group(a.groups, __builtin_amdgcn_readfirstlane(g));
+        const Group gd = load_group(gbl(a.groups), __builtin_amdgcn_readfirstlane(g));
         const int lt = gd.width_lt >> 24;
         double ax = 0.0;
         if (!XZ)
-            ax = row_reduce(group_lane_sum<V, N>(gd, lane, a.val, a.cstream,
-                                                N ? load_gbase(a.gbase, g) : 0,
-                                                a.x), lt);
+            ax = row_reduce(
+                group_lane_sum<V, N>(gd, lane, gbl(a.val), gbl(a.cstream),
+                                     N ? load_gbase(gbl(a.gbase), g) : 0,
+                                     gbl(a.x)),
+                lt);
         const int r = lane >> lt;
         if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
             const int row = gd.row0 + r;
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
     if (D) {
         for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kPW) {
             const Group gd =
-                load_group(a.groups, __builtin_amdgcn_readfirstlane(g));
+                load_group(gbl(a.groups), __builtin_amdgcn_readfirstlane(g));
             const int lt = gd.width_lt >> 24, width = gd.width_lt & 0xffffff;
             const int r = lane >> lt, row = gd.row0 + r;
             const long base = long(gd.base64) * kWave;
@@ -186,12 +188,14 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
         double v1[1] = {0.0};
         for (int g = g0 + int(threadIdx.x >> 6); g < g1; g += kPW) {
             const Group gd =
-                load_group(a.groups, __builtin_amdgcn_readfirstlane(g));
+                load_group(gbl(a.groups), __builtin_amdgcn_readfirstlane(g));
             const int lt = gd.width_lt >> 24;
             const double qv =
-                row_reduce(group_lane_sum<V, N>(gd, lane, a.val, a.cstream,
-                                                N ? load_gbase(a.gbase, g) : 0,
-                                                a.p), lt);
+                row_reduce(group_lane_sum<V, N>(
+                               gd, lane, gbl(a.val), gbl(a.cstream),
+                               N ? load_gbase(gbl(a.gbase), g) : 0,
+                               gbl(a.p)),
+                           lt);
             const int r = lane >> lt;
             if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
                 const int row = gd.row0 + r;
