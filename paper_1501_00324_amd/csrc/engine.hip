@@ -374,15 +374,17 @@ __global__ __launch_bounds__(kBlock, spmm_dot_min_waves(KM, int(sizeof(ST)))) vo
                 load_group(gbl(S.groups), __builtin_amdgcn_readfirstlane(g));
             const int gb = N ? load_gbase(gbl(S.gbase), g) : 0;
             if constexpr (KM == 1) {
+                const int lt = gd.width_lt >> 24, r = lane >> lt;
+                const bool own = (lane & ((1 << lt) - 1)) == 0 && r < gd.nrows;
+                const long row = gd.row0 + (r < gd.nrows ? r : 0);
+                const ST pr = P[row];          // early, off the tail
                 ST a0[1] = {ST(0)}, a1[1] = {ST(0)};
                 lane_sums<VT, ST, V, 1, N>(gd, lane, val, cst, gb, P, 1, 1,
                                            a0, a1);
-                const int lt = gd.width_lt >> 24, r = lane >> lt;
                 const ST v = row_reduce(a0[0] + a1[0], lt);
-                if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
-                    const long row = gd.row0 + r;
+                if (own) {
                     Q[row] = v;
-                    dot[0] += double(P[row]) * double(v);
+                    dot[0] += double(pr) * double(v);
                 }
             } else {
                 coop_group<VT, ST, V, KM, N>(
