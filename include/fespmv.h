@@ -508,6 +508,14 @@ fs_status asm_matrix(fs_asm_t P, const double *ke, hipStream_t s);
  * is written.  r must not overlap re.  Asynchronous on s. */
 fs_status asm_vector(fs_asm_t P, const double *re, double *r, hipStream_t s);
 
+/* asm_matrix and asm_vector together.  With the row-group plan one launch
+ * does both: the lane that starts each row's element rows also sums the
+ * matching element vector entries (the paper notes that tangent and
+ * residual assembly can be one operation).  Same results, bitwise, as the
+ * two calls.  Asynchronous on s; same argument rules as the two calls. */
+fs_status asm_system(fs_asm_t P, const double *ke, const double *re,
+                     double *r, hipStream_t s);
+
 typedef struct fs_asm_stats {
     int32_t n_elem, nde;
     int64_t contrib_matrix;   /* element entries that land in K             */

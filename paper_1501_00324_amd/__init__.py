@@ -111,7 +111,7 @@ EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "cg_solve_batch", "server_opts_default", "server_create",
            "server_submit", "server_poll", "server_stats", "server_destroy",
            "asm_create", "asm_plan_host", "asm_plan_host_groups",
-           "asm_matrix", "asm_vector",
+           "asm_matrix", "asm_vector", "asm_system",
            "asm_info",
            "asm_destroy", "csr_get_values"]
 
@@ -168,6 +168,7 @@ def load(build_if_missing=True):
                           P(i64), P(i32), P(i64), vp, vp, vp],
         "asm_matrix": [vp, vp, vp],
         "asm_vector": [vp, vp, vp, vp],
+        "asm_system": [vp, vp, vp, vp, vp],
         "asm_info": [vp, P(AsmStats)],
         "asm_destroy": [vp],
         "csr_get_values": [vp, vp, vp],
@@ -782,6 +783,18 @@ def asm_vector(P, re, r=None, stream=None):
                                         "re"),
                              _ptr(r, torch.float64, P.A.n_rows, "r"),
                              _stream(stream)))
+    return r
+
+
+def asm_system(P, ke, re, r=None, stream=None):
+    """asm_matrix(P, ke) and asm_vector(P, re, r) in one pass; returns r."""
+    import torch
+    if r is None:
+        r = torch.empty(P.A.n_rows, dtype=torch.float64, device="cuda")
+    _check(load().asm_system(
+        P._h, _ptr(ke, torch.float64, P.n_elem * P.nde * P.nde, "ke"),
+        _ptr(re, torch.float64, P.n_elem * P.nde, "re"),
+        _ptr(r, torch.float64, P.A.n_rows, "r"), _stream(stream)))
     return r
 
 

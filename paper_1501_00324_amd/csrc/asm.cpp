@@ -678,10 +678,34 @@ fs_status asm_matrix(fs_asm_t P, const double *ke, hipStream_t s)
     const fs_csr *A = P->A;
     if (P->lds)
         FS_HIP_TRY(launch_assemble_lds(P->kl, ke, A->d_val, A->d_val_f32,
-                                       A->d_val_bf16, s));
+                                       A->d_val_bf16, A->d_groups, A->d_perm,
+                                       nullptr, nullptr, s));
     else
         FS_HIP_TRY(launch_assemble(P->km, ke, A->d_val, A->d_val_f32,
                                    A->d_val_bf16, s));
+    return FS_OK;
+}
+
+fs_status asm_system(fs_asm_t P, const double *ke, const double *re,
+                     double *r, hipStream_t s)
+{
+    if (!P) return set_error(FS_E_ARG, "NULL assembly plan");
+    if (!P->lds || !re) {          // gather plan, or no element entries
+        FS_TRY(asm_matrix(P, ke, s));
+        return asm_vector(P, re, r, s);
+    }
+    if (!ke && P->kl.contrib > 0) return set_error(FS_E_ARG, "NULL ke");
+    if (!r && P->A->n_rows > 0) return set_error(FS_E_ARG, "NULL r");
+    const int64_t nre = int64_t(P->n_elem) * P->nde;
+    if (r && r < re + nre && re < r + P->A->n_rows)
+        return set_error(FS_E_ARG, "r overlaps re");
+    DeviceGuard g(P->device);
+    const fs_csr *A = P->A;
+    // every row belongs to one group of the plan, so every entry of r is
+    // written
+    FS_HIP_TRY(launch_assemble_lds(P->kl, ke, A->d_val, A->d_val_f32,
+                                   A->d_val_bf16, A->d_groups, A->d_perm, re,
+                                   r, s));
     return FS_OK;
 }
 

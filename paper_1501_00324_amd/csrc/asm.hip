@@ -68,15 +68,17 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
 // U consecutive steps of one batch: lane q*nde + b adds element value
 // (ea_q * nde + b) into LDS slot off.  Every load is unconditional (indices
 // clamped) and lanes without work add 0.0 into a private dummy slot past
-// the group region, so the loop has no divergent branches.
-template <int U>
+// the group region, so the loop has no divergent branches.  With WR the
+// first lane of row q also adds element vector entry ea_q into racc.
+template <int U, bool WR>
 __device__ __forceinline__ void lds_steps(long rec, int lane, int qc,
                                           bool act, int b, int nde, int rows,
                                           int dummy,
                                           const int *__restrict__ ea,
                                           const uint16_t *__restrict__ off,
                                           const double *__restrict__ ke,
-                                          double *acc)
+                                          const double *__restrict__ re,
+                                          double *acc, double &racc)
 {
     int o[U], e[U];
     double v[U];
@@ -86,15 +88,25 @@ __device__ __forceinline__ void lds_steps(long rec, int lane, int qc,
 #pragma unroll
     for (int u = 0; u < U; ++u)
         e[u] = __builtin_nontemporal_load(ea + (rec + u) * rows + qc);
+    double w[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const bool use = act && e[u] >= 0 && o[u] != 0xffff;
         v[u] = ke[long(use ? e[u] : 0) * nde + b];
         v[u] = use ? v[u] : 0.0;
         o[u] = use ? o[u] : dummy;
+        if constexpr (WR) {
+            const bool ur = act && b == 0 && e[u] >= 0;
+            w[u] = re[ur ? e[u] : 0];
+            w[u] = ur ? w[u] : 0.0;
+        }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[o[u]] += v[u];
+    if constexpr (WR) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) racc += w[u];
+    }
 }
 
 // Row-group assembly: the block's row group accumulates in LDS.  A wave
@@ -104,13 +116,17 @@ __device__ __forceinline__ void lds_steps(long rec, int lane, int qc,
 // The adds into one slot come from steps of one row in ascending order
 // (a slot belongs to one row and an element touches it once), and one
 // wave's LDS accesses complete in program order, so each slot receives its
-// contributions in ascending element order.
-template <int U>
+// contributions in ascending element order.  With WR the element vectors
+// are assembled in the same pass: row q of a batch adds re[ea_q] at every
+// step (again element order) and writes r at its caller row perm[row].
+template <int U, bool WR>
 __global__ __launch_bounds__(kBlock) void k_assemble_lds(
     const int4 *__restrict__ gdesc, const int2 *__restrict__ bdesc,
     const int *__restrict__ ea, const uint16_t *__restrict__ off, int nde,
     int rows, const double *__restrict__ ke, double *__restrict__ val,
-    float *__restrict__ f32, uint16_t *__restrict__ bf16)
+    float *__restrict__ f32, uint16_t *__restrict__ bf16,
+    const Group *__restrict__ groups, const int *__restrict__ perm,
+    const double *__restrict__ re, double *__restrict__ r)
 {
     extern __shared__ double acc[];   // group region + 64 dummy slots
     const int g = xcd_remap(blockIdx.x, gridDim.x);
@@ -128,13 +144,19 @@ __global__ __launch_bounds__(kBlock) void k_assemble_lds(
         const int2 bd = bdesc[gd.z + j];
         const long r0 = __builtin_amdgcn_readfirstlane(bd.x);
         const int K = __builtin_amdgcn_readfirstlane(bd.y);
+        double racc = 0.0;
         int k = 0;
         for (; k + U <= K; k += U)
-            lds_steps<U>(r0 + k, lane, qc, act, b, nde, rows, dummy, ea, off,
-                         ke, acc);
+            lds_steps<U, WR>(r0 + k, lane, qc, act, b, nde, rows, dummy, ea,
+                             off, ke, re, acc, racc);
         for (; k < K; ++k)
-            lds_steps<1>(r0 + k, lane, qc, act, b, nde, rows, dummy, ea, off,
-                         ke, acc);
+            lds_steps<1, WR>(r0 + k, lane, qc, act, b, nde, rows, dummy, ea,
+                             off, ke, re, acc, racc);
+        if constexpr (WR) {
+            const int rr = j * rows + q;
+            const Group lg = load_group(gbl(groups), g);
+            if (act && b == 0 && rr < lg.nrows) r[perm[lg.row0 + rr]] = racc;
+        }
     }
     __syncthreads();
     const long base = long(gd.x) * kWave;
@@ -153,14 +175,23 @@ __global__ __launch_bounds__(kBlock) void k_assemble_lds(
 
 hipError_t launch_assemble_lds(const AsmLdsPlan &P, const double *ke,
                                double *val, float *f32, uint16_t *bf16,
-                               hipStream_t s)
+                               const Group *groups, const int32_t *perm,
+                               const double *re, double *r, hipStream_t s)
 {
     if (P.ngroups == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_assemble_lds<8>, dim3(P.ngroups), dim3(kBlock),
-                       size_t(P.region_max + kWave) * sizeof(double), s,
-                       reinterpret_cast<const int4 *>(P.d_gdesc),
-                       reinterpret_cast<const int2 *>(P.d_bdesc), P.d_ea,
-                       P.d_off, P.nde, P.rows, ke, val, f32, bf16);
+    const size_t lds = size_t(P.region_max + kWave) * sizeof(double);
+    const auto gd = reinterpret_cast<const int4 *>(P.d_gdesc);
+    const auto bd = reinterpret_cast<const int2 *>(P.d_bdesc);
+    if (re)
+        hipLaunchKernelGGL((k_assemble_lds<8, true>), dim3(P.ngroups),
+                           dim3(kBlock), lds, s, gd, bd, P.d_ea, P.d_off,
+                           P.nde, P.rows, ke, val, f32, bf16, groups, perm,
+                           re, r);
+    else
+        hipLaunchKernelGGL((k_assemble_lds<8, false>), dim3(P.ngroups),
+                           dim3(kBlock), lds, s, gd, bd, P.d_ea, P.d_off,
+                           P.nde, P.rows, ke, val, f32, bf16, groups, perm,
+                           re, r);
     return hipGetLastError();
 }
 

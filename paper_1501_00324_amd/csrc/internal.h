@@ -315,9 +315,12 @@ struct AsmLdsPlan {
     int32_t *d_ea = nullptr;     // `rows` per record: e*nde + a, -1 = none
     uint16_t *d_off = nullptr;   // 64 per record: LDS offset, 0xffff = none
 };
+// With re != NULL the element vectors are summed in the same launch into
+// r (caller numbering: r[perm[layout row]]); groups / perm are the matrix's.
 hipError_t launch_assemble_lds(const AsmLdsPlan &P, const double *ke,
                                double *val, float *f32, uint16_t *bf16,
-                               hipStream_t s);
+                               const Group *groups, const int32_t *perm,
+                               const double *re, double *r, hipStream_t s);
 }  // namespace fs
 
 struct fs_asm {

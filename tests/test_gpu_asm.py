@@ -110,6 +110,12 @@ def test_assembly_bitwise(fs, orc, case, plan):
     fs.asm_matrix(P, dev(ke2))
     assert same_bits(host(fs.csr_get_values(M)),
                      orc.assemble_matrix(A, E.edof, ke2))
+    # matrix and vector in one pass: the same bits as the separate calls
+    ke3, re3 = E.ke * 1.25 + 0.5, E.re - 0.75
+    r3 = host(fs.asm_system(P, dev(ke3), dev(re3)))
+    assert same_bits(host(fs.csr_get_values(M)),
+                     orc.assemble_matrix(A, E.edof, ke3))
+    assert same_bits(r3, orc.assemble_vector(A.n_rows, E.edof, re3))
 
 
 def test_untouched_entries_and_dropped_dofs(fs, orc):
@@ -137,6 +143,11 @@ def test_untouched_entries_and_dropped_dofs(fs, orc):
     assert np.all(host(fs.csr_get_values(M)) == 0.0)
     r = fs.asm_vector(P0, torch.zeros(0, dtype=torch.float64, device="cuda"))
     assert np.all(host(r) == 0.0)
+    fs.csr_update_values(M, dev(A.val))
+    r = fs.asm_system(P0, torch.zeros(0, dtype=torch.float64, device="cuda"),
+                      torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert np.all(host(r) == 0.0)
+    assert np.all(host(fs.csr_get_values(M)) == 0.0)
 
 
 def test_non_finite_contributions_stay_local(fs, orc):
@@ -238,5 +249,13 @@ def test_config1_full_size(fs, orc):
         assert same_bits(got, want)
         info = fs.asm_info(P)
         assert info["stored_matrix"] <= 1.2 * info["contrib_matrix"]
-    assert same_bits(host(fs.asm_vector(P, dev(E.re))),
-                     orc.assemble_vector(A.n_rows, E.edof, E.re))
+    rwant = orc.assemble_vector(A.n_rows, E.edof, E.re)
+    assert same_bits(host(fs.asm_vector(P, dev(E.re))), rwant)
+    note("asm config1 system")
+    P = fs.asm_create(M, dev(E.edof))
+    import torch
+    fs.csr_update_values(M, torch.zeros(A.nnz, dtype=torch.float64,
+                                        device="cuda"))
+    r = host(fs.asm_system(P, ke, dev(E.re)))
+    assert same_bits(host(fs.csr_get_values(M)), want)
+    assert same_bits(r, rwant)
