@@ -174,11 +174,24 @@ __device__ __forceinline__ void sum_partials(const double *partials, int nblk,
 {
     __shared__ double sh[NJ][kWavesPerBlock];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    // loads are issued eight at a time (the sum keeps its index order; the
+    // padding adds +0.0, which leaves a sum started at +0.0 unchanged)
+    constexpr int U = 8;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const double *pj = partials + long(j0 + j) * nblk;
+        const auto pj = gbl(partials + long(j0 + j) * nblk);
         double s = 0.0;
-        for (int i = threadIdx.x; i < nblk; i += kBlock) s += pj[i];
+        for (int i0 = threadIdx.x; i0 < nblk; i0 += U * kBlock) {
+            double a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * kBlock;
+                a[u] = pj[i < nblk ? i : 0];
+                a[u] = i < nblk ? a[u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) s += a[u];
+        }
         s = wave_sum(s);
         if (lane == 0) sh[j][w] = s;
     }
@@ -459,6 +472,11 @@ __global__ __launch_bounds__(kBlock) void k_update(
 // derives itself); k_pupdate_fused reads rho_prev and writes rho, beta,
 // rr, iter, status.  The p.q partials stay at partials[0 .. snb), the
 // r.z / r.r partials go to partials[snb .. snb + 2 vnb).
+// The first kPrefetchRows rows of each thread are loaded before the partial
+// sums, so the loads and the reduction's latency overlap (the kernels are
+// short: ~3 rows per thread on a 774k-row system).
+constexpr int kPrefetchRows = 4;
+
 template <typename ST>
 __global__ __launch_bounds__(kBlock) void k_update_fused(
     const SysDesc *__restrict__ sys, const int *__restrict__ vmap)
@@ -467,6 +485,23 @@ __global__ __launch_bounds__(kBlock) void k_update_fused(
     const int lb = blockIdx.x - S.vb0, nb = S.vnb, n = S.n;
     ColState &cs = S.cs[0];
     if (cs.status != CG_RUNNING) return;
+    const auto X = gblw(static_cast<ST *>(S.x));
+    const auto R = gblw(static_cast<ST *>(S.r));
+    const auto P = gbl(static_cast<const ST *>(S.p));
+    const auto Q = gbl(static_cast<const ST *>(S.q));
+    const auto D = gbl(static_cast<const ST *>(S.dinv));
+    constexpr int PF = kPrefetchRows;
+    const long i0 = long(lb) * kBlock + threadIdx.x, st = long(nb) * kBlock;
+    ST xf[PF], pf[PF], rf[PF], qf[PF], df[PF];
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+        const long i = i0 + t * st, ic = i < n ? i : 0;
+        xf[t] = X[ic];
+        pf[t] = P[ic];
+        rf[t] = R[ic];
+        qf[t] = Q[ic];
+        df[t] = D ? D[ic] : ST(1);
+    }
     double g1[1];
     sum_partials<1>(S.partials, S.snb, 0, g1);
     const double gamma = g1[0], rho = cs.rho;
@@ -479,14 +514,21 @@ __global__ __launch_bounds__(kBlock) void k_update_fused(
         if (bad) cs.status = CG_BREAKDOWN;
     }
     if (bad) return;
-    ST *X = static_cast<ST *>(S.x);
-    ST *R = static_cast<ST *>(S.r);
-    const ST *P = static_cast<const ST *>(S.p);
-    const ST *Q = static_cast<const ST *>(S.q);
-    const ST *D = static_cast<const ST *>(S.dinv);
     const ST alpha = ST(alpha_d);
     double v[2] = {0.0, 0.0};
-    for (long i = long(lb) * kBlock + threadIdx.x; i < n; i += long(nb) * kBlock) {
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+        const long i = i0 + t * st;
+        if (i < n) {
+            const ST ri = rf[t] - alpha * qf[t];
+            X[i] = xf[t] + alpha * pf[t];
+            R[i] = ri;
+            const ST zi = D ? df[t] * ri : ri;
+            v[0] += double(ri) * double(zi);
+            v[1] += double(ri) * double(ri);
+        }
+    }
+    for (long i = i0 + PF * st; i < n; i += st) {
         const ST ri = R[i] - alpha * Q[i];
         X[i] += alpha * P[i];
         R[i] = ri;
@@ -505,6 +547,18 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_fused(
     const int lb = blockIdx.x - S.vb0, nb = S.vnb, n = S.n;
     ColState &cs = S.cs[0];
     if (cs.status != CG_RUNNING) return;
+    const auto P = gblw(static_cast<ST *>(S.p));
+    const auto R = gbl(static_cast<const ST *>(S.r));
+    const auto D = gbl(static_cast<const ST *>(S.dinv));
+    constexpr int PF = kPrefetchRows;
+    const long i0 = long(lb) * kBlock + threadIdx.x, st = long(nb) * kBlock;
+    ST pf[PF], zf[PF];
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+        const long i = i0 + t * st, ic = i < n ? i : 0;
+        pf[t] = P[ic];
+        zf[t] = D ? D[ic] * R[ic] : R[ic];
+    }
     double t[2];
     sum_partials<2>(S.partials + S.snb, nb, 0, t);
     const double rz = t[0], rr = t[1];
@@ -533,11 +587,13 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_fused(
         cs.rho = rz;
         if (cs.iter >= cs.maxit) cs.status = CG_MAXIT;
     }
-    ST *P = static_cast<ST *>(S.p);
-    const ST *R = static_cast<const ST *>(S.r);
-    const ST *D = static_cast<const ST *>(S.dinv);
     const ST b = ST(beta);
-    for (long i = long(lb) * kBlock + threadIdx.x; i < n; i += long(nb) * kBlock) {
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+        const long i = i0 + t * st;
+        if (i < n) P[i] = zf[t] + b * pf[t];
+    }
+    for (long i = i0 + PF * st; i < n; i += st) {
         const ST zi = D ? D[i] * R[i] : R[i];
         P[i] = zi + b * P[i];
     }
