@@ -473,6 +473,26 @@ def bench_assembly(fs, oracle, torch, A, d, stream, steps=20):
             "parity_bitwise_all_values": bool(np.array_equal(
                 got.view(np.int64), want.view(np.int64)))}
         if name == "rowgroup":
+            # the element rows stored in the plan's order (the paper's
+            # proposal: element routines write where assembly reads in order)
+            pos, nrows = fs.asm_element_rows(P)
+            ko = np.zeros((nrows, E.nde))
+            keep = pos >= 0
+            ko[pos[keep]] = E.ke.reshape(-1, E.nde)[keep]
+            kod = d(ko)
+            del ko
+            t_ord = back_to_back_us(
+                torch, lambda: fs.asm_matrix_ordered(P, kod, stream), steps,
+                3, stream)
+            got_o = fs.csr_get_values(M).cpu().numpy()
+            out["ordered"] = {
+                "matrix_us": t_ord,
+                "gbs": bytes_m / (t_ord * 1e-6) / 1e9,
+                "frac": bytes_m / (t_ord * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                "buffer_rows": nrows,
+                "parity_bitwise_all_values": bool(np.array_equal(
+                    got_o.view(np.int64), want.view(np.int64)))}
+            del kod
             r = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
             out["vector_us"] = back_to_back_us(
                 torch, lambda: fs.asm_vector(P, red, r, stream), steps, 3,

@@ -508,6 +508,21 @@ fs_status asm_matrix(fs_asm_t P, const double *ke, hipStream_t s);
  * is written.  r must not overlap re.  Asynchronous on s. */
 fs_status asm_vector(fs_asm_t P, const double *re, double *r, hipStream_t s);
 
+/* Element storage in the assembler's order (paper: conclusion -- element
+ * routines can store their contributions where the assembly kernel reads
+ * them in order, which removes the reorder from the hot path).  Row-group
+ * plan only (FS_E_UNSUPPORTED otherwise).  asm_element_rows fills the HOST
+ * array pos (n_elem * nde int32, may be NULL to learn *rows) with, for each
+ * element row (e, a), the row of a plan-ordered buffer of *rows x nde
+ * doubles where that row belongs (-1 if DOF a of element e is not in A).
+ * asm_matrix_ordered then assembles from such a buffer (device memory,
+ * ke_ordered[pos[e*nde+a]*nde + b] = ke[e][a][b]; rows no element row maps
+ * to are never read): the element values stream in order instead of being
+ * gathered.  Same values, bitwise, as asm_matrix.  Asynchronous on s. */
+fs_status asm_element_rows(fs_asm_t P, int32_t *pos, int64_t *rows);
+fs_status asm_matrix_ordered(fs_asm_t P, const double *ke_ordered,
+                             hipStream_t s);
+
 /* asm_matrix and asm_vector together.  With the row-group plan one launch
  * does both: the lane that starts each row's element rows also sums the
  * matching element vector entries (the paper notes that tangent and

@@ -111,7 +111,8 @@ EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "cg_solve_batch", "server_opts_default", "server_create",
            "server_submit", "server_poll", "server_stats", "server_destroy",
            "asm_create", "asm_plan_host", "asm_plan_host_groups",
-           "asm_matrix", "asm_vector", "asm_system",
+           "asm_matrix", "asm_vector", "asm_system", "asm_element_rows",
+           "asm_matrix_ordered",
            "asm_info",
            "asm_destroy", "csr_get_values"]
 
@@ -169,6 +170,8 @@ def load(build_if_missing=True):
         "asm_matrix": [vp, vp, vp],
         "asm_vector": [vp, vp, vp, vp],
         "asm_system": [vp, vp, vp, vp, vp],
+        "asm_element_rows": [vp, vp, P(i64)],
+        "asm_matrix_ordered": [vp, vp, vp],
         "asm_info": [vp, P(AsmStats)],
         "asm_destroy": [vp],
         "csr_get_values": [vp, vp, vp],
@@ -796,6 +799,27 @@ def asm_system(P, ke, re, r=None, stream=None):
         _ptr(re, torch.float64, P.n_elem * P.nde, "re"),
         _ptr(r, torch.float64, P.A.n_rows, "r"), _stream(stream)))
     return r
+
+
+def asm_element_rows(P):
+    """numpy int32 array pos (n_elem * nde): plan-ordered buffer row of each
+    element row (-1: not assembled), and the buffer's row count."""
+    import numpy as np
+    rows = C.c_int64()
+    _check(load().asm_element_rows(P._h, None, C.byref(rows)))
+    pos = np.empty(P.n_elem * P.nde, np.int32)
+    _check(load().asm_element_rows(P._h, pos.ctypes.data if pos.size else
+                                   None, C.byref(rows)))
+    return pos, rows.value
+
+
+def asm_matrix_ordered(P, ke_ordered, stream=None):
+    """Assemble from the plan-ordered element buffer (rows x nde float64,
+    device)."""
+    import torch
+    _check(load().asm_matrix_ordered(
+        P._h, _ptr(ke_ordered, torch.float64, None, "ke_ordered"),
+        _stream(stream)))
 
 
 def asm_info(P):

@@ -679,7 +679,7 @@ fs_status asm_matrix(fs_asm_t P, const double *ke, hipStream_t s)
     if (P->lds)
         FS_HIP_TRY(launch_assemble_lds(P->kl, ke, A->d_val, A->d_val_f32,
                                        A->d_val_bf16, A->d_groups, A->d_perm,
-                                       nullptr, nullptr, s));
+                                       nullptr, nullptr, false, s));
     else
         FS_HIP_TRY(launch_assemble(P->km, ke, A->d_val, A->d_val_f32,
                                    A->d_val_bf16, s));
@@ -705,7 +705,7 @@ fs_status asm_system(fs_asm_t P, const double *ke, const double *re,
     // written
     FS_HIP_TRY(launch_assemble_lds(P->kl, ke, A->d_val, A->d_val_f32,
                                    A->d_val_bf16, A->d_groups, A->d_perm, re,
-                                   r, s));
+                                   r, false, s));
     return FS_OK;
 }
 
@@ -719,6 +719,46 @@ fs_status asm_vector(fs_asm_t P, const double *re, double *r, hipStream_t s)
         return set_error(FS_E_ARG, "r overlaps re");
     DeviceGuard g(P->device);
     FS_HIP_TRY(launch_assemble(P->rv, re, r, nullptr, nullptr, s));
+    return FS_OK;
+}
+
+fs_status asm_element_rows(fs_asm_t P, int32_t *pos, int64_t *rows)
+{
+    if (!P) return set_error(FS_E_ARG, "NULL assembly plan");
+    if (!rows) return set_error(FS_E_ARG, "NULL rows");
+    if (!P->lds)
+        return set_error(FS_E_UNSUPPORTED,
+                         "element-row order needs the row-group plan");
+    const int64_t nr = P->kl.nrec * P->kl.rows;
+    *rows = nr;
+    if (!pos) return FS_OK;
+    const int64_t nee = int64_t(P->n_elem) * P->nde;
+    std::vector<int32_t> ea(static_cast<size_t>(nr));
+    DeviceGuard g(P->device);
+    if (nr > 0) {
+        FS_HIP_TRY(hipMemcpy(ea.data(), P->kl.d_ea, sizeof(int32_t) * size_t(nr),
+                             hipMemcpyDeviceToHost));
+    }
+    for (int64_t i = 0; i < nee; ++i) pos[i] = -1;
+    for (int64_t i = 0; i < nr; ++i)
+        if (ea[size_t(i)] >= 0) pos[ea[size_t(i)]] = int32_t(i);
+    return FS_OK;
+}
+
+fs_status asm_matrix_ordered(fs_asm_t P, const double *ke_ordered,
+                             hipStream_t s)
+{
+    if (!P) return set_error(FS_E_ARG, "NULL assembly plan");
+    if (!P->lds)
+        return set_error(FS_E_UNSUPPORTED,
+                         "the ordered element buffer needs the row-group plan");
+    if (!ke_ordered && P->kl.nrec > 0)
+        return set_error(FS_E_ARG, "NULL ke_ordered");
+    DeviceGuard g(P->device);
+    const fs_csr *A = P->A;
+    FS_HIP_TRY(launch_assemble_lds(P->kl, ke_ordered, A->d_val, A->d_val_f32,
+                                   A->d_val_bf16, A->d_groups, A->d_perm,
+                                   nullptr, nullptr, true, s));
     return FS_OK;
 }
 

@@ -69,8 +69,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
 // (ea_q * nde + b) into LDS slot off.  Every load is unconditional (indices
 // clamped) and lanes without work add 0.0 into a private dummy slot past
 // the group region, so the loop has no divergent branches.  With WR the
-// first lane of row q also adds element vector entry ea_q into racc.
-template <int U, bool WR>
+// first lane of row q also adds element vector entry ea_q into racc.  With
+// ORD the element rows come from a buffer stored in the plan's own order
+// (row rec * rows + q), so they are read contiguously and ea is not needed.
+template <int U, bool WR, bool ORD>
 __device__ __forceinline__ void lds_steps(long rec, int lane, int qc,
                                           bool act, int b, int nde, int rows,
                                           int dummy,
@@ -85,12 +87,23 @@ __device__ __forceinline__ void lds_steps(long rec, int lane, int qc,
 #pragma unroll
     for (int u = 0; u < U; ++u)
         o[u] = int(__builtin_nontemporal_load(off + (rec + u) * kWave + lane));
+    if constexpr (!ORD) {
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-        e[u] = __builtin_nontemporal_load(ea + (rec + u) * rows + qc);
+        for (int u = 0; u < U; ++u)
+            e[u] = __builtin_nontemporal_load(ea + (rec + u) * rows + qc);
+    }
     double w[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+        if constexpr (ORD) {
+            // rows of dropped element rows carry offsets 0xffff only
+            const bool use = act && o[u] != 0xffff;
+            v[u] = __builtin_nontemporal_load(
+                ke + ((rec + u) * rows + qc) * nde + b);
+            v[u] = use ? v[u] : 0.0;
+            o[u] = use ? o[u] : dummy;
+            continue;
+        }
         const bool use = act && e[u] >= 0 && o[u] != 0xffff;
         v[u] = ke[long(use ? e[u] : 0) * nde + b];
         v[u] = use ? v[u] : 0.0;
@@ -119,7 +132,7 @@ __device__ __forceinline__ void lds_steps(long rec, int lane, int qc,
 // contributions in ascending element order.  With WR the element vectors
 // are assembled in the same pass: row q of a batch adds re[ea_q] at every
 // step (again element order) and writes r at its caller row perm[row].
-template <int U, bool WR>
+template <int U, bool WR, bool ORD>
 __global__ __launch_bounds__(kBlock) void k_assemble_lds(
     const int4 *__restrict__ gdesc, const int2 *__restrict__ bdesc,
     const int *__restrict__ ea, const uint16_t *__restrict__ off, int nde,
@@ -147,11 +160,11 @@ __global__ __launch_bounds__(kBlock) void k_assemble_lds(
         double racc = 0.0;
         int k = 0;
         for (; k + U <= K; k += U)
-            lds_steps<U, WR>(r0 + k, lane, qc, act, b, nde, rows, dummy, ea,
-                             off, ke, re, acc, racc);
+            lds_steps<U, WR, ORD>(r0 + k, lane, qc, act, b, nde, rows, dummy,
+                                  ea, off, ke, re, acc, racc);
         for (; k < K; ++k)
-            lds_steps<1, WR>(r0 + k, lane, qc, act, b, nde, rows, dummy, ea,
-                             off, ke, re, acc, racc);
+            lds_steps<1, WR, ORD>(r0 + k, lane, qc, act, b, nde, rows, dummy,
+                                  ea, off, ke, re, acc, racc);
         if constexpr (WR) {
             const int rr = j * rows + q;
             const Group lg = load_group(gbl(groups), g);
@@ -176,22 +189,28 @@ __global__ __launch_bounds__(kBlock) void k_assemble_lds(
 hipError_t launch_assemble_lds(const AsmLdsPlan &P, const double *ke,
                                double *val, float *f32, uint16_t *bf16,
                                const Group *groups, const int32_t *perm,
-                               const double *re, double *r, hipStream_t s)
+                               const double *re, double *r, bool ordered,
+                               hipStream_t s)
 {
     if (P.ngroups == 0) return hipSuccess;
     const size_t lds = size_t(P.region_max + kWave) * sizeof(double);
     const auto gd = reinterpret_cast<const int4 *>(P.d_gdesc);
     const auto bd = reinterpret_cast<const int2 *>(P.d_bdesc);
-    if (re)
-        hipLaunchKernelGGL((k_assemble_lds<8, true>), dim3(P.ngroups),
+    if (ordered)
+        hipLaunchKernelGGL((k_assemble_lds<8, false, true>), dim3(P.ngroups),
+                           dim3(kBlock), lds, s, gd, bd, P.d_ea, P.d_off,
+                           P.nde, P.rows, ke, val, f32, bf16, groups, perm,
+                           nullptr, nullptr);
+    else if (re)
+        hipLaunchKernelGGL((k_assemble_lds<8, true, false>), dim3(P.ngroups),
                            dim3(kBlock), lds, s, gd, bd, P.d_ea, P.d_off,
                            P.nde, P.rows, ke, val, f32, bf16, groups, perm,
                            re, r);
     else
-        hipLaunchKernelGGL((k_assemble_lds<8, false>), dim3(P.ngroups),
-                           dim3(kBlock), lds, s, gd, bd, P.d_ea, P.d_off,
-                           P.nde, P.rows, ke, val, f32, bf16, groups, perm,
-                           re, r);
+        hipLaunchKernelGGL((k_assemble_lds<8, false, false>),
+                           dim3(P.ngroups), dim3(kBlock), lds, s, gd, bd,
+                           P.d_ea, P.d_off, P.nde, P.rows, ke, val, f32, bf16,
+                           groups, perm, re, r);
     return hipGetLastError();
 }
 

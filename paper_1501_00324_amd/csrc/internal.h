@@ -317,10 +317,14 @@ struct AsmLdsPlan {
 };
 // With re != NULL the element vectors are summed in the same launch into
 // r (caller numbering: r[perm[layout row]]); groups / perm are the matrix's.
+// With ordered, ke is the plan-ordered element buffer (row rec * rows + q
+// holds the element row that batch row q adds at record rec) and re is
+// ignored.
 hipError_t launch_assemble_lds(const AsmLdsPlan &P, const double *ke,
                                double *val, float *f32, uint16_t *bf16,
                                const Group *groups, const int32_t *perm,
-                               const double *re, double *r, hipStream_t s);
+                               const double *re, double *r, bool ordered,
+                               hipStream_t s);
 }  // namespace fs
 
 struct fs_asm {

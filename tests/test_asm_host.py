@@ -148,6 +148,21 @@ def test_rowgroup_plan_reproduces_element_loop(fs, orc, case):
     # every element row is read exactly once
     ea = G["ea"][G["ea"] >= 0]
     assert np.array_equal(np.sort(ea), np.nonzero(E.edof.reshape(-1) >= 0)[0])
+    # the same plan fed from a buffer stored in plan order (row rec * rows
+    # + q holds element row ea[rec, q]): rows with offsets 0xffff only are
+    # those without an element row
+    rows = G["rows"]
+    ko = np.full((G["ea"].size, E.nde), np.nan)
+    flat = G["ea"].reshape(-1)
+    ok = flat >= 0
+    ko[np.nonzero(ok)[0]] = E.ke.reshape(-1, E.nde)[flat[ok]]
+    assert np.all(G["off"].reshape(len(G["ea"]), -1)[:, :rows * E.nde]
+                  .reshape(-1, rows, E.nde)[~ok.reshape(-1, rows)] == 0xffff)
+    Go = dict(G)
+    Go["ea"] = np.arange(G["ea"].size, dtype=np.int32).reshape(G["ea"].shape)
+    got_o = run_groups(Go, np.nan_to_num(ko, nan=1e300).reshape(-1),
+                       L["slots"], E.nde)
+    assert np.array_equal(bits(got_o[L["map"]]), bits(want))
 
 
 def test_rowgroup_plan_not_applicable(fs):

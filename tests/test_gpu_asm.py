@@ -110,6 +110,22 @@ def test_assembly_bitwise(fs, orc, case, plan):
     fs.asm_matrix(P, dev(ke2))
     assert same_bits(host(fs.csr_get_values(M)),
                      orc.assemble_matrix(A, E.edof, ke2))
+    # element rows stored in the plan's order stream in (row-group plan)
+    if plan == 0:
+        pos, nrows = fs.asm_element_rows(P)
+        assert np.array_equal(np.sort(pos[pos >= 0]),
+                              np.unique(pos[pos >= 0]))
+        assert np.all((pos >= 0) == (E.edof.reshape(-1) >= 0))
+        ko = np.full((nrows, E.nde), np.nan)      # unused rows: never used
+        keep = pos >= 0
+        ko[pos[keep]] = E.ke.reshape(-1, E.nde)[keep] * 0.25
+        fs.asm_matrix_ordered(P, dev(ko))
+        assert same_bits(host(fs.csr_get_values(M)),
+                         orc.assemble_matrix(A, E.edof, E.ke * 0.25))
+    else:
+        with pytest.raises(fs.FsError) as ei:
+            fs.asm_element_rows(P)
+        assert ei.value.status == fs.FS_E_UNSUPPORTED
     # matrix and vector in one pass: the same bits as the separate calls
     ke3, re3 = E.ke * 1.25 + 0.5, E.re - 0.75
     r3 = host(fs.asm_system(P, dev(ke3), dev(re3)))
@@ -251,6 +267,17 @@ def test_config1_full_size(fs, orc):
         assert info["stored_matrix"] <= 1.2 * info["contrib_matrix"]
     rwant = orc.assemble_vector(A.n_rows, E.edof, E.re)
     assert same_bits(host(fs.asm_vector(P, dev(E.re))), rwant)
+    note("asm config1 ordered")
+    P = fs.asm_create(M, dev(E.edof))
+    pos, nrows = fs.asm_element_rows(P)
+    ko = np.zeros((nrows, E.nde))
+    keep = pos >= 0
+    ko[pos[keep]] = E.ke.reshape(-1, E.nde)[keep]
+    import torch
+    fs.csr_update_values(M, torch.zeros(A.nnz, dtype=torch.float64,
+                                        device="cuda"))
+    fs.asm_matrix_ordered(P, dev(ko))
+    assert same_bits(host(fs.csr_get_values(M)), want)
     note("asm config1 system")
     P = fs.asm_create(M, dev(E.edof))
     import torch
