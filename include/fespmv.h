@@ -72,6 +72,19 @@ enum {  /* fs_csr_opts.reorder */
     FS_REORDER_USER = 3   /* use opts.perm                                 */
 };
 
+enum {  /* fs_csr_opts.build: where the per-non-zero phases of the layout
+           build run (validation of the columns, slot assignment, CSR ->
+           slot map, 16-bit offsets, bandwidth statistics).  The row order
+           and the row groups are computed on the host either way (they
+           need the row lengths, or the graph for reverse Cuthill-McKee).
+           Both builders produce the same layout, bit for bit. */
+    FS_BUILD_HOST = 0,    /* multi-threaded host build (default)           */
+    FS_BUILD_DEVICE = 1   /* device kernels; falls back to the host build
+                             when a row has more than FS_BUILD_DEVICE_MAX_ROW
+                             entries (fs_csr_stats.build tells which ran)  */
+};
+#define FS_BUILD_DEVICE_MAX_ROW 4096
+
 enum {  /* bit mask, fs_csr_opts.dtypes and csr_add_dtype() */
     FS_DT_F64 = 1,
     FS_DT_F32 = 2,        /* FP32 copy of the values, rounded to nearest  */
@@ -104,7 +117,9 @@ typedef struct fs_csr_opts {
                               keep the fastest (results cached per matrix
                               signature for the process); lanes_min/max and
                               vec are then ignored                          */
-    int32_t reserved[5];   /* must be zero                                   */
+    int32_t build;         /* FS_BUILD_HOST or FS_BUILD_DEVICE (ignored by
+                              autotune, which builds on the host)          */
+    int32_t reserved[4];   /* must be zero                                   */
 } fs_csr_opts;
 
 /* Fill *o with the defaults (AUTO reorder, window 256, threshold 48,
@@ -115,7 +130,9 @@ fs_status csr_opts_default(fs_csr_opts *o);
  * colind (nnz) and vals (nnz) are device arrays; columns may be unsorted
  * inside a row but must be unique and in [0, n_cols).  opts may be NULL
  * (defaults).  The call reads the structure on the host, builds the row
- * permutation, groups and slot map, and scatters the values on the device.
+ * permutation, groups and slot map (on the host, or the per-non-zero phases
+ * on the device with opts->build = FS_BUILD_DEVICE), and scatters the
+ * values on the device.
  * It synchronises stream s before returning, after which the caller may
  * free or reuse its arrays.  *out receives the handle.
  * Errors: FS_E_ARG, FS_E_BAD_CSR, FS_E_OOM, FS_E_HIP, FS_E_UNSUPPORTED. */
@@ -154,7 +171,8 @@ typedef struct fs_csr_stats {
     int32_t tune_candidates;  /* layouts timed                              */
     double tune_best_us;      /* product time of the kept layout            */
     int32_t index_bits;       /* 16 or 32: column index width in the slots  */
-    int32_t pad_;
+    int32_t build;            /* FS_BUILD_HOST / FS_BUILD_DEVICE: the builder
+                                 that ran                                    */
 } fs_csr_stats;
 
 fs_status csr_info(fs_csr_t A, fs_csr_stats *st);
@@ -162,6 +180,15 @@ fs_status csr_info(fs_csr_t A, fs_csr_stats *st);
 /* Copy the layout's row permutation to a HOST array of n_rows entries:
  * layout row i is row perm[i] of the caller's matrix. */
 fs_status csr_get_perm(fs_csr_t A, int32_t *perm_host);
+
+/* Copy the handle's layout to HOST arrays (each may be NULL; sizes from
+ * csr_info): groups (4 int32 per group, as csr_layout_host), slot_col
+ * (layout column of every slot, -1 = padding), map (slot of every CSR
+ * position), and, when index_bits is 16, col16 (column minus the group's
+ * base column, 0xffff = padding) and gbase (base column of every group).
+ * Synchronous.  FS_E_ARG when col16 / gbase are asked for a 32-bit layout. */
+fs_status csr_get_layout(fs_csr_t A, int32_t *groups, int32_t *slot_col,
+                         int32_t *map, uint16_t *col16, int32_t *gbase);
 
 /* Host-only dry run of the layout builder on HOST arrays (no device memory
  * is touched, no GPU needed): the same validation, reordering, grouping and

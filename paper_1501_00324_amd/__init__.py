@@ -21,6 +21,8 @@ STATUS_NAMES = {0: "FS_OK", 1: "FS_E_ARG", 2: "FS_E_BAD_CSR",
                 6: "FS_E_HIP", 7: "FS_E_NOT_CONVERGED", 8: "FS_E_BREAKDOWN",
                 9: "FS_E_UNSUPPORTED"}
 REORDER_AUTO, REORDER_NONE, REORDER_RCM, REORDER_USER = range(4)
+BUILD_HOST, BUILD_DEVICE = 0, 1
+BUILD_DEVICE_MAX_ROW = 4096
 DT_F64, DT_F32, DT_BF16 = 1, 2, 4
 ASM_AUTO, ASM_GATHER, ASM_ROWGROUP = 0, 1, 2
 PC_NONE, PC_JACOBI = 0, 1
@@ -40,7 +42,7 @@ class CsrOpts(C.Structure):
                 ("lanes_min", C.c_int32), ("lanes_max", C.c_int32),
                 ("dtypes", C.c_int32), ("vec", C.c_int32),
                 ("index_bits", C.c_int32), ("autotune", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("build", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class CsrStats(C.Structure):
@@ -55,7 +57,7 @@ class CsrStats(C.Structure):
                 ("t_build_ms", C.c_double), ("device_bytes", C.c_int64),
                 ("tuned", C.c_int32), ("tune_candidates", C.c_int32),
                 ("tune_best_us", C.c_double), ("index_bits", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("build", C.c_int32)]
 
     def as_dict(self):
         d = {}
@@ -102,6 +104,7 @@ class AsmStats(C.Structure):
 EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "csr_layout_host",
            "csr_update_values", "csr_add_dtype", "csr_info", "csr_get_perm",
+           "csr_get_layout",
            "csr_destroy", "spmv", "spmv_csr", "spmv_batch", "spmv_perm",
            "probe_read_bandwidth",
            "csr_permute",
@@ -146,6 +149,7 @@ def load(build_if_missing=True):
         "csr_add_dtype": [vp, i32, vp],
         "csr_info": [vp, P(CsrStats)],
         "csr_get_perm": [vp, vp],
+        "csr_get_layout": [vp, vp, vp, vp, vp, vp],
         "csr_destroy": [vp],
         "spmv": [vp, vp, vp, vp],
         "spmv_batch": [i32, vp, vp, vp, vp],
@@ -338,6 +342,25 @@ def csr_get_perm(A):
     out = np.empty(A.n_rows, dtype=np.int32)
     _check(load().csr_get_perm(A._h, out.ctypes.data))
     return out
+
+
+def csr_get_layout(A):
+    """The handle's device layout copied to numpy: groups (n_groups x 4),
+    slot_col, map, and col16 / gbase for a 16-bit layout (else None)."""
+    import numpy as np
+    st = csr_info(A)
+    groups = np.empty((st["n_groups"], 4), dtype=np.int32)
+    slot_col = np.empty(st["slots"], dtype=np.int32)
+    mp = np.empty(st["nnz"], dtype=np.int32)
+    narrow = st["index_bits"] == 16
+    col16 = np.empty(st["slots"], dtype=np.uint16) if narrow else None
+    gbase = np.empty(st["n_groups"], dtype=np.int32) if narrow else None
+    _check(load().csr_get_layout(
+        A._h, groups.ctypes.data, slot_col.ctypes.data, mp.ctypes.data,
+        col16.ctypes.data if narrow else None,
+        gbase.ctypes.data if narrow else None))
+    return dict(groups=groups, slot_col=slot_col, map=mp, col16=col16,
+                gbase=gbase)
 
 
 def csr_destroy(A):

@@ -189,6 +189,194 @@ fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
     return FS_OK;
 }
 
+// Device handle with the per-non-zero phases of the layout build on the
+// device: the host reads only the row offsets (and the columns when the row
+// order needs the graph), computes the row order and the row groups
+// (layout_order, layout_groups, the same code as the host builder), and the
+// kernels validate the columns, assign slots, write the CSR -> slot map and
+// the 16-bit offsets, and sum the bandwidth statistics.  Falls back to the
+// host builder when a row exceeds FS_BUILD_DEVICE_MAX_ROW entries (the
+// per-row ranking costs L * ceil(L / 64) steps for a row of length L).
+// Synchronises s.
+fs_status create_on_device(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                           const int32_t *rowptr, const int32_t *colind,
+                           const double *vals, const fs_csr_opts &o,
+                           hipStream_t s, int dev, fs_csr **out)
+{
+    std::vector<int32_t> h_rp(static_cast<size_t>(n_rows) + 1);
+    FS_HIP_TRY(hipMemcpyAsync(h_rp.data(), rowptr,
+                              sizeof(int32_t) * (size_t(n_rows) + 1),
+                              hipMemcpyDeviceToHost, s));
+    FS_HIP_TRY(hipStreamSynchronize(s));
+    FS_TRY(layout_check_rowptr(n_rows, nnz, h_rp.data()));
+    int32_t maxlen = 0;
+    for (int32_t i = 0; i < n_rows; ++i)
+        maxlen = std::max(maxlen, h_rp[size_t(i) + 1] - h_rp[size_t(i)]);
+    std::vector<int32_t> h_col;
+    auto host_cols = [&]() -> fs_status {
+        h_col.resize(size_t(nnz));
+        if (nnz > 0)
+            FS_HIP_TRY(hipMemcpyAsync(h_col.data(), colind,
+                                      sizeof(int32_t) * size_t(nnz),
+                                      hipMemcpyDeviceToHost, s));
+        FS_HIP_TRY(hipStreamSynchronize(s));
+        return FS_OK;
+    };
+    if (maxlen > FS_BUILD_DEVICE_MAX_ROW) {
+        FS_TRY(host_cols());
+        return create_from_host(n_rows, n_cols, nnz, h_rp.data(),
+                                h_col.data(), vals, o, s, dev, out);
+    }
+
+    // flags: [0] first bad column, [1] first duplicate, [2..3] band sums
+    unsigned long long *d_flags = nullptr;
+    int2 *d_lohi = nullptr;
+    int64_t scratch_bytes = 0;
+    FS_TRY(dalloc(&d_flags, 4, scratch_bytes));
+    struct Scratch {
+        unsigned long long *&f;
+        int2 *&l;
+        ~Scratch() { dfree(f); dfree(l); }
+    } scratch{d_flags, d_lohi};
+    unsigned long long flags[4];
+    const unsigned long long kNone = ~0ull;
+    FS_HIP_TRY(hipMemsetAsync(d_flags, 0xff, 2 * sizeof(flags[0]), s));
+    FS_HIP_TRY(hipMemsetAsync(d_flags + 2, 0, 2 * sizeof(flags[0]), s));
+    FS_HIP_TRY(launch_check_cols(colind, nnz, n_cols, d_flags, s));
+    FS_HIP_TRY(hipMemcpyAsync(flags, d_flags, sizeof(flags[0]),
+                              hipMemcpyDeviceToHost, s));
+    FS_HIP_TRY(hipStreamSynchronize(s));
+    if (flags[0] != kNone) {
+        int32_t c = 0;
+        FS_HIP_TRY(hipMemcpy(&c, colind + flags[0], sizeof c,
+                             hipMemcpyDeviceToHost));
+        return set_error(FS_E_BAD_CSR, "column %d out of range at %lld", c,
+                         (long long)flags[0]);
+    }
+    LayoutParams prm;
+    FS_TRY(layout_params(o, prm));
+    if (layout_order_reads_columns(n_rows, n_cols, o)) FS_TRY(host_cols());
+
+    fs_csr *A = new (std::nothrow) fs_csr();
+    if (!A) return set_error(FS_E_OOM, "host allocation failed");
+    A->n_rows = n_rows;
+    A->n_cols = n_cols;
+    A->nnz = nnz;
+    A->device = dev;
+    A->build = FS_BUILD_DEVICE;
+    HostLayout &L = A->host;
+    auto fail = [&](fs_status code) {
+        (void)hipStreamSynchronize(s);
+        free_handle(A);
+        delete A;
+        return code;
+    };
+    fs_status st = layout_order(n_rows, n_cols, h_rp.data(),
+                                h_col.empty() ? nullptr : h_col.data(), o, L);
+    if (st == FS_OK)
+        st = layout_groups(n_rows, n_cols, h_rp.data(), o, prm, L);
+    if (st != FS_OK) return fail(st);
+    std::vector<int32_t>().swap(h_col);
+    A->n_groups = int32_t(L.groups.size());
+    A->slots = L.slots;
+    const bool square = n_rows == n_cols;
+
+    int64_t &acct = A->device_bytes;
+    if ((st = dalloc(&A->d_groups, A->n_groups, acct)) ||
+        (st = dalloc(&A->d_val, A->slots, acct)) ||
+        (st = dalloc(&A->d_col, A->slots, acct)) ||
+        (st = dalloc(&A->d_map, nnz, acct)) ||
+        (st = dalloc(&A->d_perm, n_rows, acct)) ||
+        (st = dalloc(&A->d_iperm, n_rows, acct)) ||
+        (st = dalloc(&A->d_xtmp, n_cols, acct)) ||
+        (st = dalloc(&d_lohi, A->n_groups, scratch_bytes)))
+        return fail(st);
+    if (o.dtypes & FS_DT_F32)
+        if ((st = dalloc(&A->d_val_f32, A->slots, acct))) return fail(st);
+    if (o.dtypes & FS_DT_BF16)
+        if ((st = dalloc(&A->d_val_bf16, A->slots, acct))) return fail(st);
+
+    hipError_t e = hipSuccess;
+#define FS_DEV_HIP(expr)                                                    \
+    if ((e = (expr)) != hipSuccess)                                         \
+        return fail(set_error(FS_E_HIP, "%s: %s", #expr, hipGetErrorString(e)))
+    if (A->n_groups)
+        FS_DEV_HIP(hipMemcpyAsync(A->d_groups, L.groups.data(),
+                                  sizeof(Group) * L.groups.size(),
+                                  hipMemcpyHostToDevice, s));
+    if (n_rows) {
+        FS_DEV_HIP(hipMemcpyAsync(A->d_perm, L.perm.data(),
+                                  sizeof(int32_t) * size_t(n_rows),
+                                  hipMemcpyHostToDevice, s));
+        FS_DEV_HIP(hipMemcpyAsync(A->d_iperm, L.iperm.data(),
+                                  sizeof(int32_t) * size_t(n_rows),
+                                  hipMemcpyHostToDevice, s));
+    }
+    if (A->slots) {
+        FS_DEV_HIP(hipMemsetAsync(A->d_col, 0xff,
+                                  sizeof(int32_t) * size_t(A->slots), s));
+        FS_DEV_HIP(hipMemsetAsync(A->d_val, 0,
+                                  sizeof(double) * size_t(A->slots), s));
+        if (A->d_val_f32)
+            FS_DEV_HIP(hipMemsetAsync(A->d_val_f32, 0,
+                                      sizeof(float) * size_t(A->slots), s));
+        if (A->d_val_bf16)
+            FS_DEV_HIP(hipMemsetAsync(A->d_val_bf16, 0,
+                                      sizeof(uint16_t) * size_t(A->slots), s));
+    }
+    FS_DEV_HIP(launch_assign_slots(A->d_groups, A->n_groups, L.vec, A->d_perm,
+                                   L.symmetric_relabel ? A->d_iperm : nullptr,
+                                   rowptr, colind, A->d_col, A->d_map, d_lohi,
+                                   d_flags + 1, s));
+    if (square)
+        FS_DEV_HIP(launch_band(n_rows, rowptr, colind, A->d_iperm,
+                               d_flags + 2, s));
+    std::vector<int2> lohi(size_t(A->n_groups));
+    if (A->n_groups)
+        FS_DEV_HIP(hipMemcpyAsync(lohi.data(), d_lohi,
+                                  sizeof(int2) * lohi.size(),
+                                  hipMemcpyDeviceToHost, s));
+    FS_DEV_HIP(hipMemcpyAsync(flags + 1, d_flags + 1, 3 * sizeof(flags[0]),
+                              hipMemcpyDeviceToHost, s));
+    FS_DEV_HIP(hipStreamSynchronize(s));
+    if (flags[1] != kNone) {
+        const int64_t k = int64_t(flags[1]);
+        const int32_t row = int32_t(std::upper_bound(h_rp.begin(), h_rp.end(),
+                                                     int32_t(k)) -
+                                    h_rp.begin()) - 1;
+        int32_t c = 0;
+        FS_DEV_HIP(hipMemcpy(&c, colind + k, sizeof c, hipMemcpyDeviceToHost));
+        return fail(set_error(FS_E_BAD_CSR, "duplicate column %d in row %d",
+                              c, row));
+    }
+    if (square && nnz > 0) {
+        // integer sums: the same values the host builder's chunked sums give
+        L.band_before = double(flags[2]) / double(nnz);
+        L.band_after = double(flags[3]) / double(nnz);
+    }
+    // 16-bit offsets when every group's columns span fewer than 65535
+    L.index_bits = 32;
+    bool fits = o.index_bits == 0 && A->n_groups > 0;
+    for (size_t g = 0; g < lohi.size() && fits; ++g)
+        fits = lohi[g].y - lohi[g].x < 0xffff;
+    if (fits) {
+        if ((st = dalloc(&A->d_col16, A->slots, acct)) ||
+            (st = dalloc(&A->d_gbase, A->n_groups, acct)))
+            return fail(st);
+        FS_DEV_HIP(launch_offsets16(A->d_groups, A->n_groups, A->d_col, d_lohi,
+                                    A->d_col16, A->d_gbase, s));
+        L.index_bits = 16;
+    }
+    FS_DEV_HIP(launch_value_scatter(vals, A->d_map, nnz, A->d_val,
+                                    A->d_val_f32, A->d_val_bf16, s));
+    FS_DEV_HIP(hipStreamSynchronize(s));
+#undef FS_DEV_HIP
+    A->dtypes = FS_DT_F64 | (A->d_val_f32 ? FS_DT_F32 : 0) |
+                (A->d_val_bf16 ? FS_DT_BF16 : 0);
+    *out = A;
+    return FS_OK;
+}
+
 // Mean time of one layout-numbering product, from HIP events around
 // `reps` launches on s.
 fs_status time_product(fs_csr *A, const double *x, double *y, int reps,
@@ -368,8 +556,19 @@ fs_status csr_create(int32_t n_rows, int32_t n_cols, int64_t nnz,
     if (o.dtypes & ~(FS_DT_F64 | FS_DT_F32 | FS_DT_BF16))
         return set_error(FS_E_ARG, "unknown dtype bits 0x%x", o.dtypes);
 
+    if (o.build != FS_BUILD_HOST && o.build != FS_BUILD_DEVICE)
+        return set_error(FS_E_ARG, "unknown build option %d", o.build);
+
     int dev = 0;
     FS_HIP_TRY(hipGetDevice(&dev));
+    if (o.build == FS_BUILD_DEVICE && !o.autotune) {
+        fs_csr *A = nullptr;
+        FS_TRY(create_on_device(n_rows, n_cols, nnz, rowptr, colind, vals, o,
+                                s, dev, &A));
+        A->t_build_ms = now_ms() - t0;
+        *out = A;
+        return FS_OK;
+    }
     std::vector<int32_t> h_rp(static_cast<size_t>(n_rows) + 1);
     std::vector<int32_t> h_col(static_cast<size_t>(nnz));
     FS_HIP_TRY(hipMemcpyAsync(h_rp.data(), rowptr,
@@ -471,6 +670,7 @@ fs_status csr_info(fs_csr_t A, fs_csr_stats *st)
     st->tune_candidates = A->tune_candidates;
     st->tune_best_us = A->tune_best_us;
     st->device_bytes = A->device_bytes;
+    st->build = A->build;
     return FS_OK;
 }
 
@@ -481,6 +681,35 @@ fs_status csr_get_perm(fs_csr_t A, int32_t *perm_host)
     if (A->n_rows)
         std::memcpy(perm_host, A->host.perm.data(),
                     sizeof(int32_t) * size_t(A->n_rows));
+    return FS_OK;
+}
+
+fs_status csr_get_layout(fs_csr_t A, int32_t *groups, int32_t *slot_col,
+                         int32_t *map, uint16_t *col16, int32_t *gbase)
+{
+    FS_TRY(check_handle(A));
+    if ((col16 || gbase) && !A->d_col16)
+        return set_error(FS_E_ARG, "the layout has 32-bit column indices");
+    DeviceGuard g(A->device);
+    if (groups && A->n_groups)
+        FS_HIP_TRY(hipMemcpy(groups, A->d_groups,
+                             sizeof(Group) * size_t(A->n_groups),
+                             hipMemcpyDeviceToHost));
+    if (slot_col && A->slots)
+        FS_HIP_TRY(hipMemcpy(slot_col, A->d_col,
+                             sizeof(int32_t) * size_t(A->slots),
+                             hipMemcpyDeviceToHost));
+    if (map && A->nnz)
+        FS_HIP_TRY(hipMemcpy(map, A->d_map, sizeof(int32_t) * size_t(A->nnz),
+                             hipMemcpyDeviceToHost));
+    if (col16 && A->slots)
+        FS_HIP_TRY(hipMemcpy(col16, A->d_col16,
+                             sizeof(uint16_t) * size_t(A->slots),
+                             hipMemcpyDeviceToHost));
+    if (gbase && A->n_groups)
+        FS_HIP_TRY(hipMemcpy(gbase, A->d_gbase,
+                             sizeof(int32_t) * size_t(A->n_groups),
+                             hipMemcpyDeviceToHost));
     return FS_OK;
 }
 

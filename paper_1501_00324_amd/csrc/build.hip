@@ -1,0 +1,222 @@
+// Device side of the layout build: the phases that touch every non-zero
+// (column range check, bandwidth sums, slot assignment with the
+// CSR-position -> slot map, 16-bit column offsets).  The row order and the
+// row groups come from the host (they need only the row lengths, or the
+// graph for reverse Cuthill-McKee); the results are the same arrays the
+// host builder writes, bit for bit.
+//
+// Paper: section "Cost of Reordering Matrix Values" -- the layout's value
+// map comes from one scan of the pattern, after which every value refresh is
+// a device scatter; here that scan runs on the device as well.
+#include "device.h"
+
+namespace fs {
+namespace {
+
+// Smallest CSR position whose column lies outside [0, n_cols).
+__global__ __launch_bounds__(kBlock) void k_check_cols(
+    const int *__restrict__ col, long nnz, int n_cols,
+    unsigned long long *__restrict__ first)
+{
+    const long stride = long(gridDim.x) * kBlock;
+    for (long k = long(blockIdx.x) * kBlock + threadIdx.x; k < nnz;
+         k += stride) {
+        const int c = col[k];
+        if (c < 0 || c >= n_cols) atomicMin(first, (unsigned long long)k);
+    }
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sums of |i - c| and |iperm[i] - iperm[c]| over the entries (i, c): one
+// wave per row, lanes over the row's entries.  Integer sums, so the order
+// of the additions does not matter.
+__global__ __launch_bounds__(kBlock) void k_band(
+    int n, const int *__restrict__ rowptr, const int *__restrict__ col,
+    const int *__restrict__ iperm, unsigned long long *__restrict__ sums)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w0 = blockIdx.x * kWavesPerBlock + int(threadIdx.x >> 6);
+    const int nw = gridDim.x * kWavesPerBlock;
+    unsigned long long s0 = 0, s1 = 0;
+    for (int i = w0; i < n; i += nw) {
+        const int k0 = rowptr[i], k1 = rowptr[i + 1];
+        const long ri = iperm[i];
+        for (int k = k0 + lane; k < k1; k += kWave) {
+            const int c = col[k];
+            const long d0 = long(i) - c, d1 = ri - iperm[c];
+            s0 += (unsigned long long)(d0 < 0 ? -d0 : d0);
+            s1 += (unsigned long long)(d1 < 0 ? -d1 : d1);
+        }
+    }
+    s0 = wave_sum_u64(s0);
+    s1 = wave_sum_u64(s1);
+    if (lane == 0) {
+        atomicAdd(sums, s0);
+        atomicAdd(sums + 1, s1);
+    }
+}
+
+__device__ __forceinline__ int layout_col(const int *__restrict__ col,
+                                          const int *__restrict__ iperm,
+                                          int k)
+{
+    const int c = col[k];
+    return iperm ? iperm[c] : c;
+}
+
+// Slot assignment, one wave per row group.  A row's entries are ranked by
+// their (relabelled) column: entry e of rank m goes to lane
+// row_in_group * T + m % T, slot m / T of that lane, i.e. element
+// base + (s / V) * 64 * V + lane * V + s % V (the column-interleaved order
+// of sections "ELL-WARP" and "ELL-WARP v2 (K2)", with the columns sorted
+// as in "K1rs").  Lanes hold up to 64 entries of the row; each counts the
+// smaller columns over the whole row through cross-lane reads, so a row of
+// length L costs L * ceil(L / 64) steps.  An entry whose column repeats an
+// earlier entry of its row is a duplicate: the smallest such CSR position
+// is reported through *dup.  The group's smallest and largest column go to
+// lohi (0, -1 for a group without entries).
+__global__ __launch_bounds__(kBlock) void k_assign_slots(
+    const Group *__restrict__ groups, int ngroups, int V,
+    const int *__restrict__ perm, const int *__restrict__ iperm,
+    const int *__restrict__ rowptr, const int *__restrict__ col,
+    int *__restrict__ slot_col, int *__restrict__ map,
+    int2 *__restrict__ lohi, unsigned long long *__restrict__ dup)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w0 = __builtin_amdgcn_readfirstlane(
+        int(blockIdx.x) * kWavesPerBlock + int(threadIdx.x >> 6));
+    const int nw = gridDim.x * kWavesPerBlock;
+    for (int g = w0; g < ngroups; g += nw) {
+        const Group G = load_group(gbl(groups), g);
+        const int lt = G.width_lt >> 24, T = 1 << lt;
+        const long base = long(G.base64) * kWave;
+        int mn = INT_MAX, mx = -1;
+        for (int rr = 0; rr < G.nrows; ++rr) {
+            const int orow = perm[G.row0 + rr];
+            const int k0 = __builtin_amdgcn_readfirstlane(rowptr[orow]);
+            const int len =
+                __builtin_amdgcn_readfirstlane(rowptr[orow + 1]) - k0;
+            for (int e0 = 0; e0 < len; e0 += kWave) {
+                const int e = e0 + lane;
+                const int c = e < len ? layout_col(col, iperm, k0 + e) : INT_MAX;
+                int rank = 0;
+                bool rep = false;
+                for (int f0 = 0; f0 < len; f0 += kWave) {
+                    int cf_lane = c;
+                    if (f0 != e0) {
+                        const int f = f0 + lane;
+                        cf_lane = f < len ? layout_col(col, iperm, k0 + f)
+                                          : INT_MAX;
+                    }
+                    const int nf = min(kWave, len - f0);
+                    for (int t = 0; t < nf; ++t) {
+                        const int cf = __builtin_amdgcn_readlane(cf_lane, t);
+                        rank += cf < c ? 1 : 0;
+                        rep = rep || (cf == c && f0 + t < e);
+                    }
+                }
+                if (e < len) {
+                    const int ln = rr * T + (rank & (T - 1));
+                    const int s = rank >> lt;
+                    const long idx = base + long(s / V) * kWave * V +
+                                     long(ln) * V + s % V;
+                    slot_col[idx] = c;
+                    map[k0 + e] = int(idx);
+                    mn = min(mn, c);
+                    mx = max(mx, c);
+                    if (rep) atomicMin(dup, (unsigned long long)(k0 + e));
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = min(mn, __shfl_xor(mn, o, kWave));
+            mx = max(mx, __shfl_xor(mx, o, kWave));
+        }
+        if (lane == 0) lohi[g] = make_int2(mx < 0 ? 0 : mn, mx);
+    }
+}
+
+// 16-bit column offsets from each group's smallest column (0xffff marks
+// padding), one wave per group over its whole slot region.
+__global__ __launch_bounds__(kBlock) void k_offsets16(
+    const Group *__restrict__ groups, int ngroups,
+    const int *__restrict__ slot_col, const int2 *__restrict__ lohi,
+    uint16_t *__restrict__ col16, int *__restrict__ gbase)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w0 = __builtin_amdgcn_readfirstlane(
+        int(blockIdx.x) * kWavesPerBlock + int(threadIdx.x >> 6));
+    const int nw = gridDim.x * kWavesPerBlock;
+    for (int g = w0; g < ngroups; g += nw) {
+        const Group G = load_group(gbl(groups), g);
+        const long base = long(G.base64) * kWave;
+        const long region = long(G.width_lt & 0xffffff) * kWave;
+        const int lo = lohi[g].x;
+        for (long t = lane; t < region; t += kWave) {
+            const int c = slot_col[base + t];
+            col16[base + t] = c < 0 ? uint16_t(0xffff) : uint16_t(c - lo);
+        }
+        if (lane == 0) gbase[g] = lo;
+    }
+}
+
+int wave_grid(long waves)
+{
+    const long b = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    return int(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
+}  // namespace
+
+hipError_t launch_check_cols(const int32_t *col, int64_t nnz, int32_t n_cols,
+                             unsigned long long *first, hipStream_t s)
+{
+    if (nnz == 0) return hipSuccess;
+    const long b = (nnz + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_check_cols, dim3(unsigned(b > 8192 ? 8192 : b)),
+                       dim3(kBlock), 0, s, col, long(nnz), n_cols, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_band(int32_t n, const int32_t *rowptr, const int32_t *col,
+                       const int32_t *iperm, unsigned long long *sums,
+                       hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_band, dim3(wave_grid(n)), dim3(kBlock), 0, s, n,
+                       rowptr, col, iperm, sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_assign_slots(const Group *groups, int32_t ngroups,
+                               int32_t vec, const int32_t *perm,
+                               const int32_t *iperm, const int32_t *rowptr,
+                               const int32_t *col, int32_t *slot_col,
+                               int32_t *map, int2 *lohi,
+                               unsigned long long *dup, hipStream_t s)
+{
+    if (ngroups == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_assign_slots, dim3(wave_grid(ngroups)), dim3(kBlock),
+                       0, s, groups, ngroups, vec, perm, iperm, rowptr, col,
+                       slot_col, map, lohi, dup);
+    return hipGetLastError();
+}
+
+hipError_t launch_offsets16(const Group *groups, int32_t ngroups,
+                            const int32_t *slot_col, const int2 *lohi,
+                            uint16_t *col16, int32_t *gbase, hipStream_t s)
+{
+    if (ngroups == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_offsets16, dim3(wave_grid(ngroups)), dim3(kBlock), 0,
+                       s, groups, ngroups, slot_col, lohi, col16, gbase);
+    return hipGetLastError();
+}
+
+}  // namespace fs

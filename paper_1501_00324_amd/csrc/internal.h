@@ -57,6 +57,27 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
                        const int32_t *rowptr, const int32_t *col,
                        const fs_csr_opts &o, HostLayout &L);
 
+// Phases of build_layout, shared with the device builder (which runs the
+// per-non-zero phases -- column checks, bandwidth, slot assignment, 16-bit
+// offsets -- on the GPU and these on the host).
+struct LayoutParams { int32_t threshold, tmin, tmax; };
+fs_status layout_check_rowptr(int32_t n_rows, int64_t nnz,
+                              const int32_t *rowptr);
+fs_status layout_params(const fs_csr_opts &o, LayoutParams &p);
+// true when layout_order needs the column indices (graph reordering)
+bool layout_order_reads_columns(int32_t n_rows, int32_t n_cols,
+                                const fs_csr_opts &o);
+// initial row order (identity, caller's, or reverse Cuthill-McKee): L.perm,
+// L.reorder.  col may be NULL when layout_order_reads_columns is false.
+fs_status layout_order(int32_t n_rows, int32_t n_cols, const int32_t *rowptr,
+                       const int32_t *col, const fs_csr_opts &o,
+                       HostLayout &L);
+// window sort and row groups from the row lengths: L.perm (final), iperm,
+// identity, symmetric_relabel, vec, groups, groups_by_lanes, slots
+fs_status layout_groups(int32_t n_rows, int32_t n_cols, const int32_t *rowptr,
+                        const fs_csr_opts &o, const LayoutParams &prm,
+                        HostLayout &L);
+
 // ------------------------------------------------- batched CG engine state
 // Status of one right-hand side.
 enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_RECURRENCE_MET = 2,
@@ -217,6 +238,7 @@ struct fs_csr {
     int64_t device_bytes = 0;
     int32_t tuned = 0, tune_candidates = 0;
     double tune_best_us = 0.0;
+    int32_t build = 0;             // FS_BUILD_HOST or FS_BUILD_DEVICE (ran)
     // solver state, created on the first solve and kept for reuse
     hipStream_t stream = nullptr;  // solves run here, ordered after the
     hipEvent_t ev = nullptr;       // caller's stream by an event
@@ -235,6 +257,21 @@ namespace fs {
 hipError_t launch_value_scatter(const double *vals, const int32_t *map,
                                 int64_t nnz, double *slot_val, float *f32,
                                 uint16_t *bf16, hipStream_t s);
+// device layout build (build.hip)
+hipError_t launch_check_cols(const int32_t *col, int64_t nnz, int32_t n_cols,
+                             unsigned long long *first, hipStream_t s);
+hipError_t launch_band(int32_t n, const int32_t *rowptr, const int32_t *col,
+                       const int32_t *iperm, unsigned long long *sums,
+                       hipStream_t s);
+hipError_t launch_assign_slots(const Group *groups, int32_t ngroups,
+                               int32_t vec, const int32_t *perm,
+                               const int32_t *iperm, const int32_t *rowptr,
+                               const int32_t *col, int32_t *slot_col,
+                               int32_t *map, int2 *lohi,
+                               unsigned long long *dup, hipStream_t s);
+hipError_t launch_offsets16(const Group *groups, int32_t ngroups,
+                            const int32_t *slot_col, const int2 *lohi,
+                            uint16_t *col16, int32_t *gbase, hipStream_t s);
 hipError_t launch_gather(int32_t n, const int32_t *perm, const double *in,
                          double *out, hipStream_t s);
 hipError_t launch_scatter(int32_t n, const int32_t *perm, const double *in,

@@ -366,12 +366,11 @@ bool is_pow2(int32_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 }  // namespace
 
-fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
-                       const int32_t *rowptr, const int32_t *col,
-                       const fs_csr_opts &o, HostLayout &L)
+fs_status layout_check_rowptr(int32_t n_rows, int64_t nnz,
+                              const int32_t *rowptr)
 {
-    // ---- validation (paper: CSR arrays of values, column indices and
-    // row offsets, section "Description of Current GPU Methods")
+    // CSR arrays of values, column indices and row offsets (paper: section
+    // "Description of Current GPU Methods")
     if (rowptr[0] != 0)
         return set_error(FS_E_BAD_CSR, "rowptr[0] = %d, expected 0", rowptr[0]);
     for (int32_t i = 0; i < n_rows; ++i)
@@ -380,24 +379,37 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
     if (int64_t(rowptr[n_rows]) != nnz)
         return set_error(FS_E_BAD_CSR, "rowptr[n] = %d but nnz = %lld",
                          rowptr[n_rows], (long long)nnz);
-    for (int64_t k = 0; k < nnz; ++k)
-        if (col[k] < 0 || col[k] >= n_cols)
-            return set_error(FS_E_BAD_CSR, "column %d out of range at %lld",
-                             col[k], (long long)k);
+    return FS_OK;
+}
 
-    const bool square = n_rows == n_cols;
-    int32_t threshold = o.threshold > 0 ? o.threshold : 48;
-    int32_t tmin = o.lanes_min > 0 ? o.lanes_min : 1;
-    int32_t tmax = o.lanes_max > 0 ? o.lanes_max : 64;
-    if (!is_pow2(tmin) || !is_pow2(tmax) || tmin > tmax || tmax > kWave)
+fs_status layout_params(const fs_csr_opts &o, LayoutParams &p)
+{
+    p.threshold = o.threshold > 0 ? o.threshold : 48;
+    p.tmin = o.lanes_min > 0 ? o.lanes_min : 1;
+    p.tmax = o.lanes_max > 0 ? o.lanes_max : 64;
+    if (!is_pow2(p.tmin) || !is_pow2(p.tmax) || p.tmin > p.tmax ||
+        p.tmax > kWave)
         return set_error(FS_E_ARG, "lanes_min/lanes_max must be powers of "
                          "two with 1 <= min <= max <= 64");
     if (o.vec < 0 || o.vec > 2)
         return set_error(FS_E_ARG, "vec must be 0 (auto), 1 or 2");
     if (o.index_bits != 0 && o.index_bits != 32)
         return set_error(FS_E_ARG, "index_bits must be 0 (auto) or 32");
+    return FS_OK;
+}
 
-    // ---- locality permutation
+bool layout_order_reads_columns(int32_t n_rows, int32_t n_cols,
+                                const fs_csr_opts &o)
+{
+    return (o.reorder == FS_REORDER_RCM || o.reorder == FS_REORDER_AUTO) &&
+           n_rows == n_cols && n_rows > 0;
+}
+
+fs_status layout_order(int32_t n_rows, int32_t n_cols, const int32_t *rowptr,
+                       const int32_t *col, const fs_csr_opts &o,
+                       HostLayout &L)
+{
+    const bool square = n_rows == n_cols;
     L.perm.resize(size_t(n_rows));
     std::iota(L.perm.begin(), L.perm.end(), 0);
     L.reorder = FS_REORDER_NONE;
@@ -437,7 +449,14 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
     } else if (o.reorder != FS_REORDER_NONE) {
         return set_error(FS_E_ARG, "unknown reorder option %d", o.reorder);
     }
+    return FS_OK;
+}
 
+fs_status layout_groups(int32_t n_rows, int32_t n_cols, const int32_t *rowptr,
+                        const fs_csr_opts &o, const LayoutParams &prm,
+                        HostLayout &L)
+{
+    const int32_t threshold = prm.threshold, tmin = prm.tmin, tmax = prm.tmax;
     // ---- longest-first inside windows (stable, keeps locality order),
     // then row groups: one wavefront, T lanes per row, 64/T rows
     struct Raw { int32_t row0, rows, w, lt; };
@@ -515,10 +534,7 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
         L.iperm[L.perm[i]] = i;
         if (L.perm[i] != i) L.identity = false;
     }
-    L.symmetric_relabel = square;
-    L.band_before = square ? mean_band(n_rows, rowptr, col, nullptr) : 0.0;
-    L.band_after = square ? mean_band(n_rows, rowptr, col, L.iperm.data())
-                          : 0.0;
+    L.symmetric_relabel = n_rows == n_cols;
     const std::vector<Raw> &raw = plan.raw;
     const int64_t slots1 = plan.slots1, slots2 = plan.slots2;
     // two slots per load halves the load instructions; one slot per load
@@ -543,6 +559,28 @@ fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
                          "more than 2^31 padded slots (%lld)",
                          (long long)slots);
     L.slots = slots;
+    return FS_OK;
+}
+
+fs_status build_layout(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                       const int32_t *rowptr, const int32_t *col,
+                       const fs_csr_opts &o, HostLayout &L)
+{
+    FS_TRY(layout_check_rowptr(n_rows, nnz, rowptr));
+    for (int64_t k = 0; k < nnz; ++k)
+        if (col[k] < 0 || col[k] >= n_cols)
+            return set_error(FS_E_BAD_CSR, "column %d out of range at %lld",
+                             col[k], (long long)k);
+    LayoutParams prm;
+    FS_TRY(layout_params(o, prm));
+    FS_TRY(layout_order(n_rows, n_cols, rowptr, col, o, L));
+    FS_TRY(layout_groups(n_rows, n_cols, rowptr, o, prm, L));
+    const bool square = n_rows == n_cols;
+    L.band_before = square ? mean_band(n_rows, rowptr, col, nullptr) : 0.0;
+    L.band_after = square ? mean_band(n_rows, rowptr, col, L.iperm.data())
+                          : 0.0;
+    const int64_t slots = L.slots;
+    const int32_t V = L.vec;
 
     // ---- slot columns and the CSR-position -> slot map (groups are
     // independent: parallel over chunks of groups; the first duplicate

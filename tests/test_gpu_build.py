@@ -1,0 +1,186 @@
+"""The device layout build (per-non-zero phases on the GPU) against the host
+build: every layout array bit for bit, the statistics, and the product
+(bitwise between the two handles, and against the CPU oracle)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads.meshes import CSR
+from tests.gpu_util import note, dev, host, make, assert_spmv_close
+from tests.test_abi_cpu import ragged
+from tests.test_gpu_spmv import long_rows
+
+pytestmark = pytest.mark.gpu
+
+SAME_STATS = ("n_rows", "n_cols", "nnz", "slots", "n_groups", "reorder",
+              "padding", "bytes_algorithmic", "bytes_layout",
+              "groups_by_lanes", "vec", "mean_band_before", "mean_band_after",
+              "index_bits", "device_bytes", "dtypes")
+
+
+@pytest.fixture(scope="module")
+def fs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_1501_00324_amd as fs
+    fs.load(build_if_missing=False)
+    return fs
+
+
+def compare_builds(fs, orc, A, what, expect_device=True, **opts):
+    note("build %s n=%d nnz=%d opts=%s" % (what, A.n_rows, A.nnz, opts))
+    Mh = make(A, **opts)
+    Md = make(A, build=fs.BUILD_DEVICE, **opts)
+    sh, sd = fs.csr_info(Mh), fs.csr_info(Md)
+    assert sh["build"] == fs.BUILD_HOST
+    assert sd["build"] == (fs.BUILD_DEVICE if expect_device
+                           else fs.BUILD_HOST)
+    for k in SAME_STATS:
+        assert sh[k] == sd[k], "%s: %s %r vs %r" % (what, k, sh[k], sd[k])
+    assert np.array_equal(fs.csr_get_perm(Mh), fs.csr_get_perm(Md))
+    lh, ld = fs.csr_get_layout(Mh), fs.csr_get_layout(Md)
+    for k in ("groups", "slot_col", "map", "col16", "gbase"):
+        if lh[k] is None:
+            assert ld[k] is None, k
+        else:
+            assert np.array_equal(lh[k], ld[k]), "%s: %s differs" % (what, k)
+    assert np.array_equal(host(fs.csr_get_values(Md)), A.val)
+    x = W.random_vector(A.n_cols, 50, W.XVEC, A.n_rows)
+    yh = host(fs.spmv(Mh, dev(x)))
+    yd = host(fs.spmv(Md, dev(x)))
+    assert np.array_equal(yh.view(np.uint64), yd.view(np.uint64)), what
+    assert_spmv_close(yd, orc.spmv(A, x), orc.spmv_abs(A, x), what)
+    return sh, sd
+
+
+OPTS = [
+    {},
+    dict(reorder=1),
+    dict(reorder=2, sort_window=1),
+    dict(lanes_min=4, lanes_max=4),
+    dict(lanes_min=64, lanes_max=64, vec=1),
+    dict(sort_window=1024, threshold=4),
+    dict(vec=1),
+    dict(index_bits=32),
+    dict(dtypes=6),
+]
+
+
+@pytest.mark.parametrize("oi", range(len(OPTS)))
+def test_config0(fs, orc, oi):
+    compare_builds(fs, orc, W.config0_poisson2d(), "cfg0", **OPTS[oi])
+
+
+@pytest.mark.parametrize("oi", [0, 1, 3, 6])
+def test_elasticity_permuted(fs, orc, oi):
+    A = W.tet_p1(10, "elastic", seed=(91, 0), bc="x0", permute=True)
+    compare_builds(fs, orc, A, "ela10", **OPTS[oi])
+
+
+def test_user_permutation(fs, orc):
+    A = W.tet_p1(8, "elastic", seed=(91, 1), bc="x0", permute=True)
+    perm = np.random.default_rng(91).permutation(A.n_rows)
+    compare_builds(fs, orc, A, "ela8 user perm", perm=perm)
+
+
+@pytest.mark.parametrize("oi", [0, 2, 5])
+@pytest.mark.parametrize("i,permuted", [(3, False), (12, True)])
+def test_sweep(fs, orc, i, permuted, oi):
+    """A P2 / graded sweep matrix (the graded one has skewed rows)."""
+    A = W.sweep_matrix(i, permuted)
+    compare_builds(fs, orc, A, A.meta["name"], **OPTS[oi])
+
+
+@pytest.mark.parametrize("nr,nc", [(1, 1), (63, 63), (65, 65), (1000, 1000),
+                                   (4099, 4099), (300, 1200), (1500, 40),
+                                   (300, 70000)])
+def test_ragged(fs, orc, nr, nc):
+    """Unsorted columns, empty rows, rows of 100..230 entries (several
+    64-entry chunks per row), non-square shapes, and a column span above
+    65535 (32-bit indices chosen by both builders)."""
+    A = ragged(nr, nc, seed=nr * 5 + nc)
+    compare_builds(fs, orc, A, "ragged%dx%d" % (nr, nc))
+    compare_builds(fs, orc, A, "ragged%dx%d T8" % (nr, nc), lanes_min=8,
+                   lanes_max=8)
+
+
+def test_long_rows(fs, orc):
+    compare_builds(fs, orc, long_rows(70, 5000, seed=92), "long rows")
+
+
+def test_empty_matrices(fs, orc):
+    Z = CSR(70, 70, np.zeros(71, np.int32), np.zeros(0, np.int32),
+            np.zeros(0))
+    compare_builds(fs, orc, Z, "no entries")
+    N = CSR(5, 3, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    compare_builds(fs, orc, N, "no entries 5x3")
+    note("build 0x0")
+    E = CSR(0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    M = make(E, build=fs.BUILD_DEVICE)
+    assert fs.csr_info(M)["build"] == fs.BUILD_DEVICE
+
+
+def test_row_above_device_limit_falls_back(fs, orc):
+    g = np.random.default_rng(93)
+    lens = np.array([3, fs.BUILD_DEVICE_MAX_ROW + 1, 0, 7])
+    cols = [g.choice(6000, L, replace=False) for L in lens]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    A = CSR(4, 6000, rp, np.concatenate(cols).astype(np.int32),
+            g.uniform(-1, 1, int(rp[-1])))
+    compare_builds(fs, orc, A, "fallback", expect_device=False)
+    lens[1] = fs.BUILD_DEVICE_MAX_ROW
+    cols = [g.choice(6000, L, replace=False) for L in lens]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    B = CSR(4, 6000, rp, np.concatenate(cols).astype(np.int32),
+            g.uniform(-1, 1, int(rp[-1])))
+    compare_builds(fs, orc, B, "at limit")
+
+
+def test_bad_input_errors(fs, orc):
+    base = ragged(200, 200, seed=94)
+    note("build errors")
+    # duplicate column inside a row
+    col = base.col.copy()
+    r = int(np.argmax(base.row_lengths() >= 3))
+    k0 = int(base.rowptr[r])
+    col[k0 + 2] = col[k0]
+    dup = CSR(200, 200, base.rowptr, col, base.val)
+    for b in (fs.BUILD_HOST, fs.BUILD_DEVICE):
+        with pytest.raises(fs.FsError) as e:
+            make(dup, build=b)
+        assert e.value.status == fs.FS_E_BAD_CSR
+        assert "duplicate column %d in row %d" % (col[k0], r) in str(e.value)
+    # column out of range
+    col = base.col.copy()
+    col[17] = 200
+    oor = CSR(200, 200, base.rowptr, col, base.val)
+    for b in (fs.BUILD_HOST, fs.BUILD_DEVICE):
+        with pytest.raises(fs.FsError) as e:
+            make(oor, build=b)
+        assert e.value.status == fs.FS_E_BAD_CSR
+        assert "column 200 out of range at 17" in str(e.value)
+    # decreasing row offsets
+    rp = base.rowptr.copy()
+    i = int(np.argmax(rp > 0))
+    rp[i + 1] = rp[i] - 1
+    bad = CSR(200, 200, rp, base.col, base.val)
+    for b in (fs.BUILD_HOST, fs.BUILD_DEVICE):
+        with pytest.raises(fs.FsError) as e:
+            make(bad, build=b)
+        assert e.value.status == fs.FS_E_BAD_CSR
+    with pytest.raises(fs.FsError) as e:
+        make(base, build=7)
+    assert e.value.status == fs.FS_E_ARG
+
+
+def test_config1_full_size(fs, orc):
+    """The 64^3 elasticity matrix (774,144 rows, 33,967,818 non-zeros):
+    identical layouts; the device build reports its time."""
+    A = W.config1_elasticity3d()
+    sh, sd = compare_builds(fs, orc, A, "config1")
+    note("config1 build host %.1f ms, device %.1f ms" % (sh["t_build_ms"],
+                                                         sd["t_build_ms"]))
+    sh, sd = compare_builds(fs, orc, A, "config1 no reorder", reorder=1)
+    note("config1 (no reorder) build host %.1f ms, device %.1f ms" % (
+        sh["t_build_ms"], sd["t_build_ms"]))
