@@ -339,25 +339,24 @@ def build_times(fs, A, rp, ci, va, M, gain, reps=2):
     """The structural layout build on the host vs with its per-non-zero
     phases on the device (best of `reps` builds each, after the first build
     of the process), with the default row order and with the caller's
-    numbering kept; the device layouts are checked bit for bit against the
-    host layout."""
-    ref = fs.csr_get_layout(M)
-    res = {"identical_layout": True}
+    numbering kept; the host layout is checked bit for bit against the
+    default (device) build."""
+    ref = fs.csr_get_layout(M)              # the default (device) build
+    res = {"identical_layout": True,
+           "device_ran": fs.csr_info(M)["build"] == fs.BUILD_DEVICE}
     for tag, extra in (("", {}), ("_no_reorder", {"reorder": fs.REORDER_NONE})):
         for name, b in (("host", fs.BUILD_HOST), ("device", fs.BUILD_DEVICE)):
             ts = []
             for _ in range(reps):
                 N = fs.csr_create(rp, ci, va, A.n_rows, A.n_cols, build=b,
                                   **extra)
-                st = fs.csr_info(N)
-                ts.append(st["t_build_ms"])
-                if b == fs.BUILD_DEVICE and not extra:
+                ts.append(fs.csr_info(N)["t_build_ms"])
+                if b == fs.BUILD_HOST and not extra:
                     lay = fs.csr_get_layout(N)
                     res["identical_layout"] &= all(
                         (ref[k] is None and lay[k] is None) or
                         (ref[k] is not None and lay[k] is not None and
                          np.array_equal(ref[k], lay[k])) for k in ref)
-                    res["device_ran"] = st["build"] == fs.BUILD_DEVICE
                 N.close()
             res["%s%s_ms" % (name, tag)] = min(ts)
     res["break_even_products_device"] = (res["device_ms"] * 1e3 / gain

@@ -78,10 +78,11 @@ enum {  /* fs_csr_opts.build: where the per-non-zero phases of the layout
            and the row groups are computed on the host either way (they
            need the row lengths, or the graph for reverse Cuthill-McKee).
            Both builders produce the same layout, bit for bit. */
-    FS_BUILD_HOST = 0,    /* multi-threaded host build (default)           */
-    FS_BUILD_DEVICE = 1   /* device kernels; falls back to the host build
-                             when a row has more than FS_BUILD_DEVICE_MAX_ROW
-                             entries (fs_csr_stats.build tells which ran)  */
+    FS_BUILD_DEVICE = 0,  /* device kernels (default); the host build runs
+                             instead when a row has more than
+                             FS_BUILD_DEVICE_MAX_ROW entries or autotune is
+                             set (fs_csr_stats.build tells which ran)      */
+    FS_BUILD_HOST = 1     /* multi-threaded host build                     */
 };
 #define FS_BUILD_DEVICE_MAX_ROW 4096
 
@@ -117,8 +118,8 @@ typedef struct fs_csr_opts {
                               keep the fastest (results cached per matrix
                               signature for the process); lanes_min/max and
                               vec are then ignored                          */
-    int32_t build;         /* FS_BUILD_HOST or FS_BUILD_DEVICE (ignored by
-                              autotune, which builds on the host)          */
+    int32_t build;         /* FS_BUILD_DEVICE (0) or FS_BUILD_HOST (autotune
+                              always builds on the host)                   */
     int32_t reserved[4];   /* must be zero                                   */
 } fs_csr_opts;
 
@@ -130,9 +131,9 @@ fs_status csr_opts_default(fs_csr_opts *o);
  * colind (nnz) and vals (nnz) are device arrays; columns may be unsorted
  * inside a row but must be unique and in [0, n_cols).  opts may be NULL
  * (defaults).  The call reads the structure on the host, builds the row
- * permutation, groups and slot map (on the host, or the per-non-zero phases
- * on the device with opts->build = FS_BUILD_DEVICE), and scatters the
- * values on the device.
+ * permutation and row groups, assigns the slots and the slot map (on the
+ * device by default, on the host with opts->build = FS_BUILD_HOST), and
+ * scatters the values on the device.
  * It synchronises stream s before returning, after which the caller may
  * free or reuse its arrays.  *out receives the handle.
  * Errors: FS_E_ARG, FS_E_BAD_CSR, FS_E_OOM, FS_E_HIP, FS_E_UNSUPPORTED. */
@@ -171,8 +172,8 @@ typedef struct fs_csr_stats {
     int32_t tune_candidates;  /* layouts timed                              */
     double tune_best_us;      /* product time of the kept layout            */
     int32_t index_bits;       /* 16 or 32: column index width in the slots  */
-    int32_t build;            /* FS_BUILD_HOST / FS_BUILD_DEVICE: the builder
-                                 that ran                                    */
+    int32_t build;            /* FS_BUILD_DEVICE / FS_BUILD_HOST: the
+                                 builder that ran                            */
 } fs_csr_stats;
 
 fs_status csr_info(fs_csr_t A, fs_csr_stats *st);

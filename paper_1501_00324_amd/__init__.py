@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "FS_OK", 1: "FS_E_ARG", 2: "FS_E_BAD_CSR",
                 6: "FS_E_HIP", 7: "FS_E_NOT_CONVERGED", 8: "FS_E_BREAKDOWN",
                 9: "FS_E_UNSUPPORTED"}
 REORDER_AUTO, REORDER_NONE, REORDER_RCM, REORDER_USER = range(4)
-BUILD_HOST, BUILD_DEVICE = 0, 1
+BUILD_DEVICE, BUILD_HOST = 0, 1
 BUILD_DEVICE_MAX_ROW = 4096
 DT_F64, DT_F32, DT_BF16 = 1, 2, 4
 ASM_AUTO, ASM_GATHER, ASM_ROWGROUP = 0, 1, 2

@@ -99,6 +99,7 @@ fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
     A->n_cols = n_cols;
     A->nnz = nnz;
     A->device = dev;
+    A->build = FS_BUILD_HOST;
     fs_status st = build_layout(n_rows, n_cols, nnz, h_rp, h_col, o, A->host);
     if (st != FS_OK) {
         delete A;

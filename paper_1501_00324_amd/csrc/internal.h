@@ -238,7 +238,7 @@ struct fs_csr {
     int64_t device_bytes = 0;
     int32_t tuned = 0, tune_candidates = 0;
     double tune_best_us = 0.0;
-    int32_t build = 0;             // FS_BUILD_HOST or FS_BUILD_DEVICE (ran)
+    int32_t build = FS_BUILD_HOST; // the builder that ran (FS_BUILD_*)
     // solver state, created on the first solve and kept for reuse
     hipStream_t stream = nullptr;  // solves run here, ordered after the
     hipEvent_t ev = nullptr;       // caller's stream by an event

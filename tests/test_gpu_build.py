@@ -30,8 +30,8 @@ def fs():
 
 def compare_builds(fs, orc, A, what, expect_device=True, **opts):
     note("build %s n=%d nnz=%d opts=%s" % (what, A.n_rows, A.nnz, opts))
-    Mh = make(A, **opts)
-    Md = make(A, build=fs.BUILD_DEVICE, **opts)
+    Mh = make(A, build=fs.BUILD_HOST, **opts)
+    Md = make(A, **opts)            # the default build
     sh, sd = fs.csr_info(Mh), fs.csr_info(Md)
     assert sh["build"] == fs.BUILD_HOST
     assert sd["build"] == (fs.BUILD_DEVICE if expect_device
