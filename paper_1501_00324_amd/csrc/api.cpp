@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 
@@ -190,6 +191,37 @@ fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
     return FS_OK;
 }
 
+// Device array -> host array (allocated here, not zero-filled).  The copy
+// lands in a pinned buffer at full link speed and is then copied out by
+// several threads, which also spreads the first-touch page faults of the
+// destination (a direct copy into fresh pageable memory, or a zero-filled
+// std::vector, costs several times the transfer; reading the pinned buffer
+// itself from the host is slower than reading ordinary memory).
+// Synchronises s.
+template <class T>
+fs_status fetch_to_host(std::unique_ptr<T[]> &dst, const T *src, int64_t n,
+                        hipStream_t s)
+{
+    dst.reset();
+    if (n <= 0) return FS_OK;
+    dst.reset(new (std::nothrow) T[size_t(n)]);
+    if (!dst) return set_error(FS_E_OOM, "host allocation failed");
+    PinnedBuf<T> pin;
+    FS_TRY(pin.alloc(n));
+    FS_HIP_TRY(hipMemcpyAsync(pin.data(), src, sizeof(T) * size_t(n),
+                              hipMemcpyDeviceToHost, s));
+    FS_HIP_TRY(hipStreamSynchronize(s));
+    constexpr int64_t kPiece = int64_t(1) << 20;     // elements per task
+    const int64_t np = (n + kPiece - 1) / kPiece;
+    T *d = dst.get();
+    const T *h = pin.data();
+    parallel_chunks(np, [&](int64_t c) {
+        const int64_t a = c * kPiece, len = std::min(kPiece, n - a);
+        std::memcpy(d + a, h + a, sizeof(T) * size_t(len));
+    });
+    return FS_OK;
+}
+
 // Device handle with the per-non-zero phases of the layout build on the
 // device: the host reads only the row offsets (and the columns when the row
 // order needs the graph), computes the row order and the row groups
@@ -213,20 +245,14 @@ fs_status create_on_device(int32_t n_rows, int32_t n_cols, int64_t nnz,
     int32_t maxlen = 0;
     for (int32_t i = 0; i < n_rows; ++i)
         maxlen = std::max(maxlen, h_rp[size_t(i) + 1] - h_rp[size_t(i)]);
-    std::vector<int32_t> h_col;
+    std::unique_ptr<int32_t[]> h_col;
     auto host_cols = [&]() -> fs_status {
-        h_col.resize(size_t(nnz));
-        if (nnz > 0)
-            FS_HIP_TRY(hipMemcpyAsync(h_col.data(), colind,
-                                      sizeof(int32_t) * size_t(nnz),
-                                      hipMemcpyDeviceToHost, s));
-        FS_HIP_TRY(hipStreamSynchronize(s));
-        return FS_OK;
+        return fetch_to_host(h_col, colind, nnz, s);
     };
     if (maxlen > FS_BUILD_DEVICE_MAX_ROW) {
         FS_TRY(host_cols());
         return create_from_host(n_rows, n_cols, nnz, h_rp.data(),
-                                h_col.data(), vals, o, s, dev, out);
+                                h_col.get(), vals, o, s, dev, out);
     }
 
     // flags: [0] first bad column, [1] first duplicate, [2..3] band sums
@@ -272,12 +298,12 @@ fs_status create_on_device(int32_t n_rows, int32_t n_cols, int64_t nnz,
         delete A;
         return code;
     };
-    fs_status st = layout_order(n_rows, n_cols, h_rp.data(),
-                                h_col.empty() ? nullptr : h_col.data(), o, L);
+    fs_status st = layout_order(n_rows, n_cols, h_rp.data(), h_col.get(), o,
+                                L);
     if (st == FS_OK)
         st = layout_groups(n_rows, n_cols, h_rp.data(), o, prm, L);
     if (st != FS_OK) return fail(st);
-    std::vector<int32_t>().swap(h_col);
+    h_col.reset();
     A->n_groups = int32_t(L.groups.size());
     A->slots = L.slots;
     const bool square = n_rows == n_cols;
@@ -570,23 +596,16 @@ fs_status csr_create(int32_t n_rows, int32_t n_cols, int64_t nnz,
         *out = A;
         return FS_OK;
     }
-    std::vector<int32_t> h_rp(static_cast<size_t>(n_rows) + 1);
-    std::vector<int32_t> h_col(static_cast<size_t>(nnz));
-    FS_HIP_TRY(hipMemcpyAsync(h_rp.data(), rowptr,
-                              sizeof(int32_t) * (size_t(n_rows) + 1),
-                              hipMemcpyDeviceToHost, s));
-    if (nnz > 0)
-        FS_HIP_TRY(hipMemcpyAsync(h_col.data(), colind,
-                                  sizeof(int32_t) * size_t(nnz),
-                                  hipMemcpyDeviceToHost, s));
-    FS_HIP_TRY(hipStreamSynchronize(s));
+    std::unique_ptr<int32_t[]> h_rp, h_col;
+    FS_TRY(fetch_to_host(h_rp, rowptr, int64_t(n_rows) + 1, s));
+    FS_TRY(fetch_to_host(h_col, colind, nnz, s));
     fs_csr *A = nullptr;
     if (o.autotune)
-        FS_TRY(create_tuned(n_rows, n_cols, nnz, h_rp.data(), h_col.data(),
+        FS_TRY(create_tuned(n_rows, n_cols, nnz, h_rp.get(), h_col.get(),
                             vals, o, s, dev, &A));
     else
-        FS_TRY(create_from_host(n_rows, n_cols, nnz, h_rp.data(),
-                                h_col.data(), vals, o, s, dev, &A));
+        FS_TRY(create_from_host(n_rows, n_cols, nnz, h_rp.get(),
+                                h_col.get(), vals, o, s, dev, &A));
     A->t_build_ms = now_ms() - t0;
     *out = A;
     return FS_OK;

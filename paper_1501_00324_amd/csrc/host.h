@@ -61,6 +61,37 @@ template <class T> void dfree(T *&p)
     p = nullptr;
 }
 
+// Pinned host array (hipHostMalloc), freed on destruction or release().
+template <class T> struct PinnedBuf {
+    T *p = nullptr;
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf &) = delete;
+    PinnedBuf &operator=(const PinnedBuf &) = delete;
+    ~PinnedBuf() { release(); }
+    fs_status alloc(int64_t n)
+    {
+        release();
+        if (n <= 0) return FS_OK;
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&p),
+                                     size_t(n) * sizeof(T),
+                                     hipHostMallocDefault);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return set_error(FS_E_OOM, "hipHostMalloc(%lld bytes): %s",
+                             (long long)(n * int64_t(sizeof(T))),
+                             hipGetErrorString(e));
+        }
+        return FS_OK;
+    }
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+    }
+    T *data() const { return p; }
+};
+
 // f(c) for every chunk c in [0, nchunks), spread over up to 16 host
 // threads.  Chunks are independent; results must not depend on which
 // thread ran which chunk.
