@@ -184,3 +184,20 @@ def test_config1_full_size(fs, orc):
     sh, sd = compare_builds(fs, orc, A, "config1 no reorder", reorder=1)
     note("config1 (no reorder) build host %.1f ms, device %.1f ms" % (
         sh["t_build_ms"], sd["t_build_ms"]))
+
+
+def test_get_layout_rejects_offsets_of_32bit_layout(fs, orc):
+    """csr_get_layout: 16-bit offsets exist only for a 16-bit layout."""
+    A = ragged(300, 70000, seed=95)        # a group spans 69,969 columns
+    note("get_layout 32-bit")
+    M = make(A)
+    st = fs.csr_info(M)
+    assert st["index_bits"] == 32
+    buf = np.empty(st["slots"], dtype=np.uint16)
+    rc = fs.load().csr_get_layout(M._h, None, None, None, buf.ctypes.data,
+                                  None)
+    assert rc == fs.FS_E_ARG
+    lay = fs.csr_get_layout(M)
+    assert lay["col16"] is None and lay["gbase"] is None
+    assert np.array_equal(np.sort(lay["map"]),
+                          np.sort(np.nonzero(lay["slot_col"] >= 0)[0]))
