@@ -33,32 +33,47 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// Sums of |i - c| and |iperm[i] - iperm[c]| over the entries (i, c): one
-// wave per row, lanes over the row's entries.  Integer sums, so the order
-// of the additions does not matter.
+// Sums of |i - c| and |iperm[i] - iperm[c]| over the entries (i, c): 16
+// lanes per row (four rows per wave in flight), the lanes striding over the
+// row's entries; the block's sums meet in LDS and go out as one pair of
+// atomics (atomics on one address serialise, so a grid of at most
+// kBandBlocks keeps them few).  Integer sums, so the order of the additions
+// does not matter.
+constexpr int kBandLanes = 16;
+constexpr int kBandBlocks = 2048;
+
 __global__ __launch_bounds__(kBlock) void k_band(
     int n, const int *__restrict__ rowptr, const int *__restrict__ col,
     const int *__restrict__ iperm, unsigned long long *__restrict__ sums)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int w0 = blockIdx.x * kWavesPerBlock + int(threadIdx.x >> 6);
-    const int nw = gridDim.x * kWavesPerBlock;
+    const int sub = lane & (kBandLanes - 1);
+    const long first = (long(blockIdx.x) * kBlock + threadIdx.x) / kBandLanes;
+    const long stride = long(gridDim.x) * kBlock / kBandLanes;
     unsigned long long s0 = 0, s1 = 0;
-    for (int i = w0; i < n; i += nw) {
+    for (long i = first; i < n; i += stride) {
         const int k0 = rowptr[i], k1 = rowptr[i + 1];
         const long ri = iperm[i];
-        for (int k = k0 + lane; k < k1; k += kWave) {
+        for (int k = k0 + sub; k < k1; k += kBandLanes) {
             const int c = col[k];
-            const long d0 = long(i) - c, d1 = ri - iperm[c];
+            const long d0 = i - c, d1 = ri - iperm[c];
             s0 += (unsigned long long)(d0 < 0 ? -d0 : d0);
             s1 += (unsigned long long)(d1 < 0 ? -d1 : d1);
         }
     }
+    __shared__ unsigned long long part[2][kWavesPerBlock];
     s0 = wave_sum_u64(s0);
     s1 = wave_sum_u64(s1);
+    const int w = threadIdx.x >> 6;
     if (lane == 0) {
-        atomicAdd(sums, s0);
-        atomicAdd(sums + 1, s1);
+        part[0][w] = s0;
+        part[1][w] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) t += part[threadIdx.x][i];
+        atomicAdd(sums + threadIdx.x, t);
     }
 }
 
@@ -190,8 +205,9 @@ hipError_t launch_band(int32_t n, const int32_t *rowptr, const int32_t *col,
                        hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_band, dim3(wave_grid(n)), dim3(kBlock), 0, s, n,
-                       rowptr, col, iperm, sums);
+    const long b = (long(n) * kBandLanes + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_band, dim3(unsigned(b > kBandBlocks ? kBandBlocks : b)),
+                       dim3(kBlock), 0, s, n, rowptr, col, iperm, sums);
     return hipGetLastError();
 }
 
