@@ -465,24 +465,39 @@ fs_status layout_groups(int32_t n_rows, int32_t n_cols, const int32_t *rowptr,
         std::vector<Raw> raw;
         int64_t slots1 = 0, slots2 = 0;
     };
+    // row lengths in the initial order, read once: the window sorts and the
+    // group cut below touch only this contiguous array
+    std::vector<int32_t> len0(static_cast<size_t>(n_rows));
+    parallel_chunks((n_rows + kRowChunk - 1) / kRowChunk, [&](int64_t c) {
+        const int64_t i1 = std::min<int64_t>(n_rows, (c + 1) * kRowChunk);
+        for (int64_t i = c * kRowChunk; i < i1; ++i) {
+            const int32_t r = L.perm[size_t(i)];
+            len0[size_t(i)] = rowptr[r + 1] - rowptr[r];
+        }
+    });
     auto make_plan = [&](int32_t window, Plan &P) {
         P.perm = L.perm;
+        std::vector<int32_t> len = len0;      // lengths in the plan's order
         if (window > 1) {
             const int64_t nw = (n_rows + window - 1) / window;
             parallel_chunks(nw, [&](int64_t w) {
                 const int64_t w0 = w * window;
-                const int64_t w1 = std::min<int64_t>(n_rows, w0 + window);
-                std::stable_sort(P.perm.begin() + w0, P.perm.begin() + w1,
-                                 [&](int32_t a, int32_t b) {
-                                     return rowptr[a + 1] - rowptr[a] >
-                                            rowptr[b + 1] - rowptr[b];
-                                 });
+                const int32_t m = int32_t(std::min<int64_t>(n_rows, w0 + window) - w0);
+                std::vector<int32_t> ix(static_cast<size_t>(m)),
+                    pv(static_cast<size_t>(m)), lv(static_cast<size_t>(m));
+                std::iota(ix.begin(), ix.end(), 0);
+                const int32_t *lw = len.data() + w0;
+                std::stable_sort(ix.begin(), ix.end(), [&](int32_t a, int32_t b) {
+                    return lw[a] > lw[b];
+                });
+                for (int32_t j = 0; j < m; ++j) {
+                    pv[size_t(j)] = P.perm[size_t(w0 + ix[size_t(j)])];
+                    lv[size_t(j)] = lw[ix[size_t(j)]];
+                }
+                std::copy(pv.begin(), pv.end(), P.perm.begin() + w0);
+                std::copy(lv.begin(), lv.end(), len.begin() + w0);
             });
         }
-        auto len = [&](int32_t layout_row) {
-            int32_t r = P.perm[layout_row];
-            return rowptr[r + 1] - rowptr[r];
-        };
         P.raw.clear();
         P.slots1 = P.slots2 = 0;
         for (int32_t i = 0; i < n_rows;) {
@@ -491,7 +506,7 @@ fs_status layout_groups(int32_t n_rows, int32_t n_cols, const int32_t *rowptr,
                 rows = std::min<int32_t>(kWave / T, n_rows - i);
                 int32_t maxlen = 0;
                 for (int32_t j = 0; j < rows; ++j)
-                    maxlen = std::max(maxlen, len(i + j));
+                    maxlen = std::max(maxlen, len[size_t(i + j)]);
                 w = (maxlen + T - 1) / T;
                 if (w <= threshold || T >= tmax) break;
                 T *= 2;
