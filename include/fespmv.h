@@ -77,7 +77,9 @@ enum {  /* fs_csr_opts.build: where the per-non-zero phases of the layout
            slot map, 16-bit offsets, bandwidth statistics).  The row order
            and the row groups are computed on the host either way (they
            need the row lengths, or the graph for reverse Cuthill-McKee).
-           Both builders produce the same layout, bit for bit. */
+           Both builders produce the same layout, bit for bit.  (Paper:
+           section "Cost of Reordering Matrix Values" -- the value map comes
+           from one scan of the pattern, done here by either builder.) */
     FS_BUILD_DEVICE = 0,  /* device kernels (default); the host build runs
                              instead when a row has more than
                              FS_BUILD_DEVICE_MAX_ROW entries or autotune is
@@ -182,8 +184,9 @@ fs_status csr_info(fs_csr_t A, fs_csr_stats *st);
  * layout row i is row perm[i] of the caller's matrix. */
 fs_status csr_get_perm(fs_csr_t A, int32_t *perm_host);
 
-/* Copy the handle's layout to HOST arrays (each may be NULL; sizes from
- * csr_info): groups (4 int32 per group, as csr_layout_host), slot_col
+/* Copy the handle's layout (the row-grouped, column-interleaved storage of
+ * sections "ELL-WARP", "ELL-WARP v2 (K2)" and "K1rs") to HOST arrays (each
+ * may be NULL; sizes from csr_info): groups (4 int32 per group, as csr_layout_host), slot_col
  * (layout column of every slot, -1 = padding), map (slot of every CSR
  * position), and, when index_bits is 16, col16 (column minus the group's
  * base column, 0xffff = padding) and gbase (base column of every group).
