@@ -21,7 +21,7 @@ void free_handle(fs_csr *A)
 {
     free_solver_state(A);
     dfree(A->d_groups); dfree(A->d_val); dfree(A->d_val_f32);
-    dfree(A->d_val_bf16); dfree(A->d_col); dfree(A->d_map);
+    dfree(A->d_val_bf16); dfree(A->d_col); dfree(A->d_map); dfree(A->d_imap);
     dfree(A->d_col16); dfree(A->d_gbase);
     dfree(A->d_perm); dfree(A->d_iperm); dfree(A->d_xtmp); dfree(A->d_Xtmp);
 }
@@ -121,6 +121,7 @@ fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
         (st = dalloc(&A->d_val, A->slots, acct)) ||
         (st = dalloc(&A->d_col, A->slots, acct)) ||
         (st = dalloc(&A->d_map, nnz, acct)) ||
+        (st = dalloc(&A->d_imap, A->slots, acct)) ||
         (st = dalloc(&A->d_perm, n_rows, acct)) ||
         (st = dalloc(&A->d_iperm, n_rows, acct)) ||
         (st = dalloc(&A->d_xtmp, n_cols, acct)))
@@ -168,6 +169,10 @@ fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
         FS_CREATE_HIP(hipMemcpyAsync(A->d_map, L.map.data(),
                                      sizeof(int32_t) * size_t(nnz),
                                      hipMemcpyHostToDevice, s));
+    if (A->slots)
+        FS_CREATE_HIP(hipMemsetAsync(A->d_imap, 0xff,
+                                     sizeof(int32_t) * size_t(A->slots), s));
+    FS_CREATE_HIP(launch_inverse_map(A->d_map, nnz, A->d_imap, s));
     if (n_rows) {
         FS_CREATE_HIP(hipMemcpyAsync(A->d_perm, L.perm.data(),
                                      sizeof(int32_t) * size_t(n_rows),
@@ -313,6 +318,7 @@ fs_status create_on_device(int32_t n_rows, int32_t n_cols, int64_t nnz,
         (st = dalloc(&A->d_val, A->slots, acct)) ||
         (st = dalloc(&A->d_col, A->slots, acct)) ||
         (st = dalloc(&A->d_map, nnz, acct)) ||
+        (st = dalloc(&A->d_imap, A->slots, acct)) ||
         (st = dalloc(&A->d_perm, n_rows, acct)) ||
         (st = dalloc(&A->d_iperm, n_rows, acct)) ||
         (st = dalloc(&A->d_xtmp, n_cols, acct)) ||
@@ -394,6 +400,10 @@ fs_status create_on_device(int32_t n_rows, int32_t n_cols, int64_t nnz,
                                     A->d_col16, A->d_gbase, s));
         L.index_bits = 16;
     }
+    if (A->slots)
+        FS_DEV_HIP(hipMemsetAsync(A->d_imap, 0xff,
+                                  sizeof(int32_t) * size_t(A->slots), s));
+    FS_DEV_HIP(launch_inverse_map(A->d_map, nnz, A->d_imap, s));
     FS_DEV_HIP(launch_value_scatter(vals, A->d_map, nnz, A->d_val,
                                     A->d_val_f32, A->d_val_bf16, s));
     FS_DEV_HIP(hipStreamSynchronize(s));
@@ -647,8 +657,9 @@ fs_status csr_update_values(fs_csr_t A, const double *vals, hipStream_t s)
     FS_TRY(check_handle(A));
     if (!vals && A->nnz > 0) return set_error(FS_E_ARG, "NULL values");
     DeviceGuard g(A->device);
-    FS_HIP_TRY(launch_value_scatter(vals, A->d_map, A->nnz, A->d_val,
-                                    A->d_val_f32, A->d_val_bf16, s));
+    FS_HIP_TRY(launch_value_refresh(A->d_groups, A->n_groups, A->d_imap,
+                                    vals, A->d_val, A->d_val_f32,
+                                    A->d_val_bf16, s));
     return FS_OK;
 }
 

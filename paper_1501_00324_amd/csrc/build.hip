@@ -182,6 +182,47 @@ __global__ __launch_bounds__(kBlock) void k_offsets16(
     }
 }
 
+// Inverse of the CSR-position -> slot map: imap[map[k]] = k (padding slots
+// keep the -1 they were filled with).
+__global__ __launch_bounds__(kBlock) void k_inverse_map(
+    const int *__restrict__ map, long nnz, int *__restrict__ imap)
+{
+    const long stride = long(gridDim.x) * kBlock;
+    for (long k = long(blockIdx.x) * kBlock + threadIdx.x; k < nnz;
+         k += stride)
+        imap[map[k]] = int(k);
+}
+
+// Value refresh in slot order (paper: section "Cost of Reordering Matrix
+// Values", the per-Newton-step reorder of the values into the layout): one
+// workgroup per row group walks the group's slot region, slot s taking
+// vals[imap[s]] (0 for padding).  The slot arrays are written in full
+// coalesced lines; the CSR values are gathered, but a group's region only
+// touches the CSR ranges of its own rows, which stay in the CU's cache
+// while the workgroup walks it.  The FP32 / BF16 copies round as the
+// scatter at creation does.
+__global__ __launch_bounds__(kBlock) void k_value_refresh(
+    const Group *__restrict__ groups, const int *__restrict__ imap,
+    const double *__restrict__ vals, double *__restrict__ val,
+    float *__restrict__ f32, uint16_t *__restrict__ bf16)
+{
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    const Group G = load_group(gbl(groups), g);
+    const long base = long(G.base64) * kWave;
+    const long region = long(G.width_lt & 0xffffff) * kWave;
+    for (long t = base + threadIdx.x; t < base + region; t += kBlock) {
+        const int k = __builtin_nontemporal_load(imap + t);
+        const double a = vals[k < 0 ? 0 : k];
+        const double v = k < 0 ? 0.0 : a;
+        val[t] = v;
+        if (f32 || bf16) {
+            const float f = float(v);
+            if (f32) f32[t] = f;
+            if (bf16) bf16[t] = f32_to_bf16_rne(f);
+        }
+    }
+}
+
 int wave_grid(long waves)
 {
     const long b = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -189,6 +230,27 @@ int wave_grid(long waves)
 }
 
 }  // namespace
+
+hipError_t launch_inverse_map(const int32_t *map, int64_t nnz, int32_t *imap,
+                              hipStream_t s)
+{
+    if (nnz == 0) return hipSuccess;
+    const long b = (nnz + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_inverse_map, dim3(unsigned(b > 8192 ? 8192 : b)),
+                       dim3(kBlock), 0, s, map, long(nnz), imap);
+    return hipGetLastError();
+}
+
+hipError_t launch_value_refresh(const Group *groups, int32_t ngroups,
+                                const int32_t *imap, const double *vals,
+                                double *val, float *f32, uint16_t *bf16,
+                                hipStream_t s)
+{
+    if (ngroups == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_value_refresh, dim3(ngroups), dim3(kBlock), 0, s,
+                       groups, imap, vals, val, f32, bf16);
+    return hipGetLastError();
+}
 
 hipError_t launch_check_cols(const int32_t *col, int64_t nnz, int32_t n_cols,
                              unsigned long long *first, hipStream_t s)

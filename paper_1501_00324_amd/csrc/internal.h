@@ -228,6 +228,7 @@ struct fs_csr {
     uint16_t *d_col16 = nullptr;   // 16-bit offsets (index_bits 16), or NULL
     int32_t *d_gbase = nullptr;    // per-group column base for d_col16
     int32_t *d_map = nullptr;
+    int32_t *d_imap = nullptr;     // slot -> CSR position, -1 = padding
     int32_t *d_perm = nullptr;
     int32_t *d_iperm = nullptr;
     double *d_xtmp = nullptr;      // gathered x for caller-numbering spmv
@@ -258,6 +259,12 @@ hipError_t launch_value_scatter(const double *vals, const int32_t *map,
                                 int64_t nnz, double *slot_val, float *f32,
                                 uint16_t *bf16, hipStream_t s);
 // device layout build (build.hip)
+hipError_t launch_inverse_map(const int32_t *map, int64_t nnz, int32_t *imap,
+                              hipStream_t s);
+hipError_t launch_value_refresh(const Group *groups, int32_t ngroups,
+                                const int32_t *imap, const double *vals,
+                                double *val, float *f32, uint16_t *bf16,
+                                hipStream_t s);
 hipError_t launch_check_cols(const int32_t *col, int64_t nnz, int32_t n_cols,
                              unsigned long long *first, hipStream_t s);
 hipError_t launch_band(int32_t n, const int32_t *rowptr, const int32_t *col,

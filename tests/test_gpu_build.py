@@ -201,3 +201,31 @@ def test_get_layout_rejects_offsets_of_32bit_layout(fs, orc):
     assert lay["col16"] is None and lay["gbase"] is None
     assert np.array_equal(np.sort(lay["map"]),
                           np.sort(np.nonzero(lay["slot_col"] >= 0)[0]))
+
+
+@pytest.mark.parametrize("name", ["cfg0", "ragged", "ragged_rect"])
+def test_value_refresh_in_slot_order(fs, orc, name):
+    """csr_update_values (slot-ordered gather through the inverse map) leaves
+    every value array -- FP64 slots, FP32 and BF16 copies, padding -- equal
+    to those of a handle created with the new values."""
+    A = {"cfg0": W.config0_poisson2d,
+         "ragged": lambda: ragged(1000, 1000, seed=96),
+         "ragged_rect": lambda: ragged(300, 1200, seed=97)}[name]()
+    note("value refresh %s" % name)
+    g = np.random.default_rng(98)
+    v2 = g.uniform(-1, 1, A.nnz)
+    B = CSR(A.n_rows, A.n_cols, A.rowptr, A.col, v2)
+    for build in (fs.BUILD_DEVICE, fs.BUILD_HOST):
+        M = make(A, dtypes=6, build=build)
+        fs.csr_update_values(M, dev(v2))
+        N = make(B, dtypes=6, build=build)
+        assert np.array_equal(host(fs.csr_get_values(M)), v2)
+        x = W.random_vector(A.n_cols, 51, W.XVEC)
+        assert np.array_equal(host(fs.spmv(M, dev(x))).view(np.uint64),
+                              host(fs.spmv(N, dev(x))).view(np.uint64))
+        if A.n_rows == A.n_cols:
+            xp = dev(x.astype(np.float32))
+            for dt in (fs.DT_F32, fs.DT_BF16):
+                assert np.array_equal(
+                    host(fs.spmv_lowp(M, dt, xp)).view(np.uint32),
+                    host(fs.spmv_lowp(N, dt, xp)).view(np.uint32))
