@@ -214,11 +214,12 @@ __global__ __launch_bounds__(kBlock) void k_value_refresh(
         const int k = __builtin_nontemporal_load(imap + t);
         const double a = vals[k < 0 ? 0 : k];
         const double v = k < 0 ? 0.0 : a;
-        val[t] = v;
+        // streamed out, so the slot arrays do not evict the rows' values
+        __builtin_nontemporal_store(v, val + t);
         if (f32 || bf16) {
             const float f = float(v);
-            if (f32) f32[t] = f;
-            if (bf16) bf16[t] = f32_to_bf16_rne(f);
+            if (f32) __builtin_nontemporal_store(f, f32 + t);
+            if (bf16) __builtin_nontemporal_store(f32_to_bf16_rne(f), bf16 + t);
         }
     }
 }
