@@ -908,6 +908,19 @@ def main():
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+    # explicit teardown while the runtime is fully up: every handle closed,
+    # the device drained, torch's cached pinned host blocks returned
+    M.close()
+    torch.cuda.synchronize()
+    release_host_cache(torch)
+
+
+def release_host_cache(torch):
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    if hasattr(torch._C, "_host_emptyCache"):
+        torch._C._host_emptyCache()
 
 
 if __name__ == "__main__":

@@ -149,7 +149,11 @@ fs_status csr_create(int32_t n_rows, int32_t n_cols, int64_t nnz,
 fs_status csr_update_values(fs_csr_t A, const double *vals, hipStream_t s);
 
 /* Materialise a low-precision copy (FS_DT_F32 or FS_DT_BF16) of the values
- * for mixed-precision solves.  Synchronises s. */
+ * for mixed-precision solves.  Not in the paper, which stores and computes
+ * in FP64 throughout (section "Description of the Physical Problem"): this
+ * is the storage half of the mixed-precision addition (values rounded to
+ * nearest into FP32; BF16 rounded nearest-even from that FP32 value).
+ * Synchronises s. */
 fs_status csr_add_dtype(fs_csr_t A, int32_t dtype, hipStream_t s);
 
 typedef struct fs_csr_stats {
@@ -249,7 +253,8 @@ fs_status probe_read_bandwidth(const double *buf, int64_t n, double *sink,
 
 /* m independent products y_i = A_i x_i in the caller's numbering, the
  * batch form of spmv (same statement of the problem; each result is bitwise
- * the spmv result).  A, x and y are HOST arrays of m entries holding handles
+ * the spmv result).  Not in the paper: the batching addition, for many
+ * small systems whose products alone are launch-latency bound.  A, x and y are HOST arrays of m entries holding handles
  * and DEVICE vector pointers; all handles live on one device.  The y_i are
  * distinct and no x_i is any y_j; a handle may appear more than once.  The products of
  * up to 56 matrices share each launch (per-matrix descriptors are passed as
@@ -268,15 +273,19 @@ fs_status csr_permute(fs_csr_t A, int32_t dir, const double *in, double *out,
 
 /* Y = A X for k right-hand sides, 1 <= k <= 16.  X is n_cols x k and Y is
  * n_rows x k, row-major with row strides ldx >= k and ldy >= k (elements).
+ * Not in the paper: the multi-right-hand-side part of the batching
+ * addition; each column is the product of section "Description of Current
+ * GPU Methods", and the matrix stream is read once for all k columns.
  * Asynchronous on s. */
 fs_status spmm(fs_csr_t A, int32_t k, const double *X, int64_t ldx,
                double *Y, int64_t ldy, hipStream_t s);
 
 /* Low-precision product in the layout numbering: y' = A'_lo x' with the FP32
  * or BF16 copy of the values (csr_add_dtype first), float x' and y', float
- * accumulation.  The inner operation of mixed-precision refinement; BF16
- * values are widened to float exactly.  Square matrices only.
- * Asynchronous on s. */
+ * accumulation.  Not in the paper (FP64 only, section "Description of the
+ * Physical Problem"): the inner operation of the mixed-precision refinement
+ * addition; BF16 values are widened to float exactly.  Square matrices
+ * only.  Asynchronous on s. */
 fs_status spmv_lowp(fs_csr_t A, int32_t dtype, const float *xp, float *yp,
                     hipStream_t s);
 
@@ -331,7 +340,10 @@ fs_status cg_solve(fs_csr_t A, const double *b, double *x,
                    const fs_cg_opts *opts, fs_cg_info *info, hipStream_t s);
 
 /* Stream-ordered form of cg_solve (FP64, one right-hand side): the call
- * only enqueues work on s and returns.  The whole solve -- Jacobi scaling,
+ * only enqueues work on s and returns.  The solver is the Jacobi-PCG of
+ * sections "Computational Cost of the Finite Element Method" and
+ * "Description of Current GPU Methods"; the stream form is an addition (the
+ * paper drives its solver from the host).  The whole solve -- Jacobi scaling,
  * start residual, every iteration, true-residual confirmation with residual
  * replacement -- is one cooperative launch that holds its scalars on the
  * device (no host round trip per chunk), between the permutation of b in
@@ -353,7 +365,10 @@ fs_status cg_solve_async(fs_csr_t A, const double *b, double *x,
                          hipStream_t s);
 
 /* k independent solves A X[:, c] = B[:, c], 1 <= k <= 16, advanced
- * together: one multi-column product per iteration (the k columns of a row
+ * together (not in the paper: the multi-right-hand-side part of the
+ * batching addition; each column runs the Jacobi-PCG of section
+ * "Computational Cost of the Finite Element Method"): one multi-column
+ * product per iteration (the k columns of a row
  * of X are contiguous, so one gathered row serves all k).  B and X are
  * n x k row-major device blocks with row strides ldb, ldx >= k.  Columns
  * stop independently.  The order of every sum is fixed by the column-count
@@ -366,7 +381,10 @@ fs_status cg_solve_multi(fs_csr_t A, int32_t k, const double *B, int64_t ldb,
                          fs_cg_info *info, hipStream_t s);
 
 /* m independent systems A[i] X[i] = B[i] with k[i] right-hand sides each
- * (1 <= k[i] <= 16), advanced by the same launches: every iteration is one
+ * (1 <= k[i] <= 16), advanced by the same launches (not in the paper: the
+ * batching addition, for many small systems -- such as the small heart
+ * meshes of section "Finite Element Comparison Between GPU and Multi-core"
+ * -- whose solves are launch-latency bound): every iteration is one
  * batched product kernel and a fixed number of vector / reduction kernels
  * for all systems together, so many small systems cost what one does.
  * B[i] and X[i] are n_i x k[i] row-major device blocks (row stride k[i]).
@@ -381,7 +399,9 @@ fs_status cg_solve_batch(int32_t m, const fs_csr_t *A, const int32_t *k,
                          hipStream_t s);
 
 /* ------------------------------------------------------------- serving */
-/* A solve server: requests (a matrix handle and k right-hand sides) are
+/* Not in the paper: the serving addition (continuous batching of solves
+ * with admission by device memory), built on cg_solve_batch.
+ * A solve server: requests (a matrix handle and k right-hand sides) are
  * admitted in arrival order while a device-memory budget and a slot count
  * allow, and every admitted request is advanced by the same batched
  * launches as the others (continuous batching: requests join and leave at

@@ -223,6 +223,20 @@ def _ptr(t, dtype=None, n=None, name="tensor"):
     return t.data_ptr() if t.numel() else None
 
 
+def _finalize(close):
+    """Release a handle from a finalizer.  While the interpreter shuts down
+    the HIP runtime (and any tool attached to it) may already be gone, so
+    nothing is released then: the process exit returns the memory.  Owners
+    that want a clean teardown call close() themselves."""
+    import sys
+    if sys.is_finalizing():
+        return
+    try:
+        close()
+    except Exception:
+        pass
+
+
 class Matrix:
     """Owning wrapper of an fs_csr_t handle."""
 
@@ -231,10 +245,7 @@ class Matrix:
         self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, nnz
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self.close)
 
     def close(self):
         if self.handle:
@@ -692,10 +703,7 @@ class Server:
             _check(st)
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self.close)
 
 
 class Assembly:
@@ -706,10 +714,7 @@ class Assembly:
         self.n_elem, self.nde = n_elem, nde
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self.close)
 
     def close(self):
         if self.handle:

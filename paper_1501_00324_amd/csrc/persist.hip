@@ -8,7 +8,15 @@
 // barrier every block sums the per-block partials itself, in one fixed
 // order, so all blocks hold bitwise the same scalars (alpha, beta, the
 // residual norms) and take the same branch at every decision: the number
-// of barriers is the same in every block.  Per iteration:
+// of barriers is the same in every block.
+//
+// Partials live in two regions used in turn by successive reductions.
+// Every write of partials is followed by a grid barrier, and a block
+// reaches that barrier only after it has read the previous reduction's
+// sums; so when reduction k+2 writes region (k mod 2), every block has
+// left get_sums of reduction k (it has passed the barrier of reduction
+// k+1).  With one region a fast block could overwrite partials that a slow
+// block is still summing.  Per iteration:
 //   q = A p, partials of p.q        | barrier | gamma, alpha
 //   x += alpha p, r -= alpha q,     |
 //   z = D^-1 r, partials r.z, r.r   | barrier | rz, rr, beta
@@ -41,7 +49,7 @@ struct PcgArgs {
     int32_t n, ngroups;
     const double *b;               // layout numbering
     double *x, *r, *p, *q, *dinv;  // dinv NULL: no preconditioner
-    double *part;                  // 3 * gridDim.x partials
+    double *part;                  // 2 regions of 3 * kPersistMaxBlocks
     fs_cg_info *info;              // device copy of the result
     double rtol, nnz, clock_khz;
     int32_t maxit, x_zero;
@@ -121,6 +129,14 @@ __device__ __forceinline__ void residual_rows(const PcgArgs &a, int g0, int g1,
 
 enum { P_RUNNING = 0, P_CONVERGED = 1, P_BREAKDOWN = 2, P_MAXIT = 3 };
 
+// Region of the partials for the next reduction (alternates; see the top).
+__device__ __forceinline__ double *next_region(double *part, int &k)
+{
+    double *p = part + (k & 1) * (3 * kPersistMaxBlocks);
+    ++k;
+    return p;
+}
+
 template <int V, bool N>
 __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
 {
@@ -166,10 +182,12 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
     };
     if (a.x_zero) residual_rows<V, N, true>(a, g0, g1, start);
     else residual_rows<V, N, false>(a, g0, g1, start);
-    put_partials<3>(v3, a.part, nb, lb);
+    int red = 0;  // reductions so far (selects the partials region)
+    double *pr = next_region(a.part, red);
+    put_partials<3>(v3, pr, nb, lb);
     grid.sync();
     double s3[3];
-    get_sums<3>(a.part, nb, s3);
+    get_sums<3>(pr, nb, s3);
     const double bb = s3[2], tol2 = a.rtol * a.rtol * bb;
     double rho = s3[1], rr = s3[0], rr_true = s3[0];
     int status = P_RUNNING, it = 0, repl = 0;
@@ -203,10 +221,11 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
                 v1[0] += a.p[row] * qv;
             }
         }
-        put_partials<1>(v1, a.part, nb, lb);
+        pr = next_region(a.part, red);
+        put_partials<1>(v1, pr, nb, lb);
         grid.sync();
         double s1[1];
-        get_sums<1>(a.part, nb, s1);
+        get_sums<1>(pr, nb, s1);
         const double gamma = s1[0];
         if (!(gamma > 0.0) || !isfinite(gamma)) {
             status = P_BREAKDOWN;
@@ -223,10 +242,11 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
             v2[0] += ri * zi;
             v2[1] += ri * ri;
         }
-        put_partials<2>(v2, a.part, nb, lb);
+        pr = next_region(a.part, red);
+        put_partials<2>(v2, pr, nb, lb);
         grid.sync();
         double s2[2];
-        get_sums<2>(a.part, nb, s2);
+        get_sums<2>(pr, nb, s2);
         ++it;
         double rz = s2[0];
         rr = s2[1];
@@ -239,9 +259,10 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
                 w2[0] += ri * zi;
                 w2[1] += ri * ri;
             });
-            put_partials<2>(w2, a.part, nb, lb);
+            pr = next_region(a.part, red);
+            put_partials<2>(w2, pr, nb, lb);
             grid.sync();
-            get_sums<2>(a.part, nb, s2);
+            get_sums<2>(pr, nb, s2);
             rr_true = s2[1];
             if (rr_true <= tol2) {
                 status = P_CONVERGED;
@@ -278,10 +299,11 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
         double w1[1] = {0.0};
         residual_rows<V, N, false>(a, g0, g1,
                                 [&](int, double ri) { w1[0] += ri * ri; });
-        put_partials<1>(w1, a.part, nb, lb);
+        pr = next_region(a.part, red);
+        put_partials<1>(w1, pr, nb, lb);
         grid.sync();
         double s1[1];
-        get_sums<1>(a.part, nb, s1);
+        get_sums<1>(pr, nb, s1);
         rr_true = s1[0];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {

@@ -753,7 +753,7 @@ extern "C" fs_status cg_solve_async(fs_csr_t A, const double *b, double *x,
         FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_async),
                        sizeof(double) * size_t(6 * n), acct));
         FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_apart),
-                       sizeof(double) * 3 * kPersistMaxBlocks, acct));
+                       sizeof(double) * 2 * 3 * kPersistMaxBlocks, acct));
         FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_ainfo),
                        sizeof(fs_cg_info), acct));
         A->device_bytes += acct;

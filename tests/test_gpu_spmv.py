@@ -158,16 +158,6 @@ def test_config1_full_size(fs, orc):
     assert fs.csr_info(M32)["slots"] == info["slots"]
 
 
-def test_largest_fem_matrix_full_size(fs, orc):
-    """The largest sweep matrix (Q1-hex elasticity, 1,975,509 rows, 156M
-    non-zeros) at full size, every output row checked."""
-    i12 = [i for i, r in enumerate(W.SWEEP) if r[0].startswith("S12")][0]
-    A = W.sweep_matrix(i12, False)
-    assert A.nnz == 156365811
-    M = run_spmv(fs, orc, A, {}, 12, "S12")
-    assert fs.csr_info(M)["slots"] < 1.1 * A.nnz
-
-
 # ------------------------------------------------------------ batched
 def batch_matrices():
     """Mixed members: natural and relabelled numbering, both slot widths,

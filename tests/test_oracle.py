@@ -430,7 +430,11 @@ def test_cg_warm_start_resume(orc):
 @pytest.mark.parametrize("keep", [False, True])
 def test_ir_cg_reaches_fp64_residual(orc, kind, keep):
     if keep and kind == "bf16":
-        pytest.skip("kept direction with BF16 values: see the stall test")
+        pytest.skip("parity unpinned here: kappa 2^-9 of this matrix is "
+                    "not small, so neither convergence nor a stall of the "
+                    "kept-direction form is fixed by the mathematics; the "
+                    "BF16 kept-direction form is pinned on a "
+                    "well-conditioned matrix below")
     A = W.tet_p1(6, "elastic", seed=(84, 0), bc="x0", permute=True)
     b = W.random_vector(A.n_rows, 84, W.BVEC)
     if kind == "f32":
@@ -463,19 +467,64 @@ def test_ir_keep_direction_needs_about_the_fp64_iterations(orc):
     assert inr >= 1.2 * it64
 
 
-def test_ir_keep_direction_stalls_on_bf16(orc):
-    """With BF16 values the inner operator is too far from A for a search
-    direction kept across steps: the plain kept-direction method stagnates
-    (the library restarts the inner CG when a step fails), while restarted
-    refinement converges."""
-    A = W.tet_p1(6, "elastic", seed=(84, 0), bc="x0", permute=True)
-    b = W.random_vector(A.n_rows, 84, W.BVEC)
+def shifted(A, c):
+    """A + c diag(A) (same pattern): with A symmetric positive semi-definite
+    the Jacobi-scaled spectrum moves to [c, lambda_max + c]."""
+    from workloads.meshes import CSR
+    rows = np.repeat(np.arange(A.n_rows), A.row_lengths())
+    v = A.val.copy()
+    on = A.col == rows
+    v[on] *= 1.0 + c
+    return CSR(A.n_rows, A.n_cols, A.rowptr, A.col, v)
+
+
+@pytest.mark.parametrize("keep", [False, True])
+def test_ir_bf16_converges_when_rounding_times_kappa_is_small(orc, keep):
+    """Refinement with an inner operator A + E contracts the FP64 error by
+    about max(inner tolerance, kappa |E| / |A|) per step (classic analysis of
+    iterative refinement: Higham, Accuracy and Stability of Numerical
+    Algorithms, ch. 12; Carson and Higham, SISC 2018).  Two-step BF16
+    rounding gives |E_ij| <= (2^-24 + 2^-9)(1 + 2^-24) |A_ij| < 2^-8 |A_ij|.
+    On a Jacobi-scaled condition number below 8 that product is below
+    1/32, so both the restarted and the kept-direction forms must reach the
+    FP64 true residual 1e-8 with BF16 values, in a handful of steps, and the
+    solution must match the dense solve within 2e-8 kappa.  (Where kappa
+    2^-9 exceeds 1, as on the large elasticity matrix, refinement has no
+    such guarantee.)"""
+    A = shifted(W.tet_p1(6, "elastic", seed=(86, 0), bc="x0",
+                         permute=True), 1.0)
+    b = W.random_vector(A.n_rows, 86, W.BVEC)
+    D = A.to_dense()
+    s = 1.0 / np.sqrt(np.diag(D))
+    ev = np.linalg.eigvalsh(D * s[:, None] * s[None, :])
+    kj = ev[-1] / ev[0]
+    assert kj < 8.0                      # the premise of the test
     a = orc.bf16_bits_to_f32(orc.round_bf16(A.val))
-    _, stk, _, ink, rrk = orc.ir_cg(A, a, b, inner_rtol=1e-2, keep=True,
-                                    max_inner=3000)
-    _, str_, _, _, rrr = orc.ir_cg(A, a, b, inner_rtol=1e-2)
-    assert stk == orc.NOT_CONVERGED and rrk > 1e-8 and ink == 3000
-    assert str_ == orc.OK and rrr <= 1e-8
+    assert np.all(np.abs(a - A.val) <= 2.0 ** -8 * np.abs(A.val))
+    x, st, outer, inner, rr = orc.ir_cg(A, a, b, precond=1, rtol=1e-8,
+                                        inner_rtol=1e-2, keep=keep)
+    assert st == orc.OK and rr <= 1e-8
+    assert 2 <= outer <= 8
+    xs = np.linalg.solve(D, b)
+    assert np.linalg.norm(x - xs) <= 2e-8 * np.linalg.cond(D) * \
+        np.linalg.norm(xs)
+
+
+def test_ir_bf16_exact_values_match_fp32(orc):
+    """Where every value is exactly representable in BF16 (the unjittered
+    5-point stencil: 4 and -1), the BF16 copy is A itself: both refinement
+    forms then return bitwise the FP32-copy results and reach 1e-8."""
+    A = W.poisson_2d_p1(24, jitter=0.0, bc="all")
+    b = W.random_vector(A.n_rows, 87, W.BVEC)
+    a16 = orc.bf16_bits_to_f32(orc.round_bf16(A.val))
+    a32 = orc.round_f32(A.val)
+    nz = A.val != 0.0
+    assert np.array_equal(a16[nz], A.val[nz].astype(np.float32))
+    for keep in (False, True):
+        x16, st16, o16, i16, r16 = orc.ir_cg(A, a16, b, keep=keep)
+        x32, st32, o32, i32, r32 = orc.ir_cg(A, a32, b, keep=keep)
+        assert st16 == st32 == orc.OK and r16 <= 1e-8
+        assert (o16, i16) == (o32, i32) and np.array_equal(x16, x32)
 
 
 def test_spmv_par_is_bitwise_spmv(orc):
