@@ -1,14 +1,21 @@
-"""Benchmark: FP64 SpMV effective bandwidth and Jacobi-PCG solves on the
-3-D elasticity matrix (P1 Kuhn tetrahedra, 64^3 nodes, random node
-numbering, x = 0 face clamped: 774,144 rows, 33,967,818 non-zeros).
+"""Benchmark: FP64 SpMV effective bandwidth on the largest FEM matrix, and
+the Jacobi-PCG solves (FP64, mixed precision, multi-RHS, batched, served)
+on the 3-D elasticity system.
 
 One timed step is one FP64 SpMV y' = A' x' in the layout numbering (the
-product the CG iteration performs).  ``value`` is the effective bandwidth on
-the algorithmic-bytes model 12 nnz + 8 n_cols + 8 n_rows (matrix values and
-int32 column indices once, x once, y once), with the inputs resident in HBM.
-The same JSON line reports the caller-numbering product, a full Jacobi-PCG
-solve to a true relative residual of 1e-8, and the single-threaded CPU oracle
-on the same matrix.
+product the CG iteration performs) on the largest FEM matrix of the sparsity
+sweep: Q1 hexahedral elasticity, 87^3 nodes, natural numbering, full
+Neumann (1,975,509 rows, 156,365,811 non-zeros).  ``value`` is the
+effective bandwidth on the algorithmic-bytes model 12 nnz + 8 n_cols +
+8 n_rows (matrix values and int32 column indices once, x once, y once),
+with the inputs resident in HBM, timed with HIP events over K back-to-back
+launches on the launch stream.  The same JSON line reports the cold-cache
+product, the CPU oracle on the same matrix, and the 3-D elasticity system
+(P1 Kuhn tetrahedra, 64^3 nodes, random node numbering, x = 0 face clamped:
+774,144 rows, 33,967,818 non-zeros): its product, Jacobi-PCG to a true
+relative residual of 1e-8 in FP64 and with FP32 / BF16 refinement, the
+stream-ordered, multi-right-hand-side and batched solves, element assembly,
+and the serving experiment.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -31,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # that determine that kernel's code and data layout: the profile is used only
 # while they are unchanged.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles",
-                               "spmv_f64_elasticity64_traffic.md")
+                               "spmv_f64_q1hex_elasticity87_traffic.md")
 KERNEL_SOURCES = ["paper_1501_00324_amd/csrc/kernels.hip",
                   "paper_1501_00324_amd/csrc/device.h",
                   "paper_1501_00324_amd/csrc/layout.h",
@@ -271,7 +278,7 @@ def back_to_back_us(torch, fn, steps, warmup, stream):
 
 
 def measure_matrix(fs, oracle, torch, A, d, steps, warmup, stream,
-                   cold=True):
+                   cold=True, extras=True):
     """Layout build, parity of the timed launch against the oracle on every
     row, warm (back to back, and per call) and cold product times, and the
     plain CSR product without a layout."""
@@ -308,6 +315,8 @@ def measure_matrix(fs, oracle, torch, A, d, steps, warmup, stream,
         out["cold_us"] = dist(c)
         out["cold_gbs"] = bytes_alg / (out["cold_us"]["median"] * 1e-6) / 1e9
         del junk
+    if not extras:
+        return M, out
     # plain CSR product (no layout) in caller numbering
     xd = d(x)
     y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
@@ -598,6 +607,49 @@ def run_sweep(fs, W, oracle, torch, d, steps, warmup, stream):
     return rows
 
 
+def headline_matrix(W):
+    """The largest FEM matrix of the sweep: Q1 hexahedral elasticity, 87^3
+    nodes, natural numbering, full Neumann (1,975,509 rows, 156,365,811
+    non-zeros)."""
+    i12 = [i for i, r in enumerate(W.SWEEP) if r[0].startswith("S12")][0]
+    return W.SWEEP[i12][0], W.sweep_matrix(i12, False)
+
+
+def bench_bf16_variants(fs, oracle, torch, A, M, bd, b, x64, cg):
+    """Refinement with BF16 values on the elasticity matrix: the kept
+    search direction and the restarted inner CG at three inner tolerances,
+    and BF16 values stored after Jacobi scaling (D^-1/2 A D^-1/2 rounded).
+    Each row: status, steps, inner iterations, oracle-recomputed residual,
+    forward error against the FP64 solution, time."""
+    rows = []
+    for restart in (0, 1):
+        for eta in (1e-1, 1e-2, 1e-3):
+            for scaled in (0, 1):
+                if scaled and eta != 1e-2:
+                    continue
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                xs, ci = fs.cg_solve(M, bd, precond=fs.PC_JACOBI, rtol=1e-8,
+                                     precision=fs.PREC_IR_BF16,
+                                     inner_rtol=eta, ir_restart=restart,
+                                     ir_scaled=scaled, check=False)
+                t = time.perf_counter() - t0
+                xh = xs.cpu().numpy()
+                rows.append({
+                    "ir_restart": restart, "inner_rtol": eta,
+                    "jacobi_scaled_storage": scaled,
+                    "status": ci["status"], "outer": ci["outer"],
+                    "inner": ci["iters"], "ms": t * 1e3,
+                    "relres_oracle": float(np.linalg.norm(
+                        b - oracle.spmv(A, xh)) / np.linalg.norm(b)),
+                    "relres_gpu": ci["relres"],
+                    "forward_err_vs_fp64": float(np.linalg.norm(xh - x64) /
+                                                 np.linalg.norm(x64)),
+                    "speedup_vs_fp64": cg["ms"] / (t * 1e3)})
+                log("cg ir-bf16 %s" % json.dumps(rows[-1]))
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -605,9 +657,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cg", action="store_true")
-    ap.add_argument("--no-largest", action="store_true",
-                    help="skip the largest sweep matrix (S12, 156M nnz)")
-    ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--only-headline", action="store_true",
+                    help="only the timed product on the largest FEM matrix "
+                         "(for counter profiles)")
+    ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--no-asm", action="store_true",
                     help="skip the finite-element assembly measurement")
     ap.add_argument("--serving-full", action="store_true",
@@ -645,6 +698,7 @@ def main():
                                     "solves/s vs one-at-a-time FP64 CG",
                           "n_gpus": 1, "dtype": "f64", "data": "synthetic",
                           "serving": srv}), flush=True)
+        release_host_cache(torch)
         return
 
     if args.sweep:
@@ -653,12 +707,8 @@ def main():
                           "unit": "GB/s", "n_gpus": 1, "dtype": "f64",
                           "data": "synthetic", "peak_gbs": HBM_PEAK_GBS,
                           "sweep": rows}), flush=True)
+        release_host_cache(torch)
         return
-
-    t = time.time()
-    A = W.config1_elasticity3d()
-    log("generated config-1 matrix: %d rows, %d nnz in %.1f s"
-        % (A.n_rows, A.nnz, time.time() - t))
 
     if args.calibrate_copy:
         ca = torch.ones(CALIB_DOUBLES, dtype=torch.float64, device=dev)
@@ -671,17 +721,114 @@ def main():
                                         8 * CALIB_DOUBLES))
         del ca, cb
 
-    # the timed product: spmv_perm (layout numbering, as inside CG), K
-    # launches back to back between two events on the launch stream
-    M, prod = measure_matrix(fs, oracle, torch, A, d, args.steps,
-                             args.warmup, stream)
+    # ---- headline: the FP64 product on the largest FEM matrix
+    t = time.time()
+    hname, H = headline_matrix(W)
+    tg = time.time() - t
+    log("generated %s: %d rows, %d nnz in %.1f s" % (hname, H.n_rows, H.nnz,
+                                                     tg))
+    MH, prod = measure_matrix(fs, oracle, torch, H, d, args.steps,
+                              args.warmup, stream,
+                              extras=not args.only_headline)
+    prod.update(matrix=hname, numbering="natural", t_generate_s=tg)
     us = prod["us"]
     gbs = prod["gbs"]
-    bytes_alg = 12 * A.nnz + 8 * A.n_cols + 8 * A.n_rows
-    log("spmv_perm: %.2f us/launch, %.1f GB/s; cold median %.2f us; plain "
-        "CSR %.2f us; parity %s" % (us, gbs, prod["cold_us"]["median"],
-                                    prod["csr_plain"]["us"],
-                                    prod["parity_all_rows"]))
+    bytes_alg = 12 * H.nnz + 8 * H.n_cols + 8 * H.n_rows
+    log("headline spmv_perm on %s: %.2f us/launch, %.1f GB/s (%.1f%% of "
+        "peak); cold median %.2f us (%.1f%%); parity %s"
+        % (hname, us, gbs, 100 * gbs / HBM_PEAK_GBS,
+           prod["cold_us"]["median"], 100 * prod["cold_gbs"] / HBM_PEAK_GBS,
+           prod["parity_all_rows"]))
+    traffic = measured_traffic()
+
+    def line(extra):
+        out = {
+            "metric": "SpMV effective GB/s (% HBM peak); CG solves/s + p99 "
+                      "latency, FP64 vs mixed",
+            "value": round(gbs, 2),
+            "unit": "GB/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": us * 1e-3,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "largest FEM matrix: Q1-hex elasticity, "
+                                   "87^3 nodes, natural numbering, full "
+                                   "Neumann (sweep S12)",
+                       "n_rows": H.n_rows, "nnz": H.nnz,
+                       "op": "spmv_perm (layout numbering, as inside CG)",
+                       "bytes_per_spmv": bytes_alg},
+            "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
+            "cold_pct_hbm_peak": round(100.0 * prod["cold_gbs"] /
+                                       HBM_PEAK_GBS, 2),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 2),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": traffic,
+                         "dram_gbs": (round(traffic / (us * 1e-6) / 1e9, 1)
+                                      if traffic else None),
+                         "bytes_algorithmic": bytes_alg,
+                         "kernel": "k_spmv_f64",
+                         "cold_frac": round(prod["cold_gbs"] /
+                                            HBM_PEAK_GBS, 4)},
+            "paper_model_gbs": round(20 * H.nnz / (us * 1e-6) / 1e9, 2),
+            "parity_all_rows": prod["parity_all_rows"],
+            "spmv": prod,
+        }
+        out.update(extra)
+        return out
+
+    if args.only_headline:
+        print(json.dumps(line({})), flush=True)
+        MH.close()
+        release_host_cache(torch)
+        return
+
+    # CPU oracle on a bounded sample of the headline workload: repeated
+    # full products of the same matrix (single thread, then all cores)
+    xh = W.random_vector(H.n_cols, 1, W.XVEC)
+    reps, tc = 0, 0.0
+    t0 = time.perf_counter()
+    while tc < args.cpu_seconds:
+        oracle.spmv(H, xh)
+        reps += 1
+        tc = time.perf_counter() - t0
+    cpu_gbs = bytes_alg * reps / tc / 1e9
+    cpu = {"value": round(cpu_gbs, 3), "unit": "GB/s", "cores": 1,
+           "kind": "oracle", "cpu": host_cpu_model(),
+           "sample": "%d full FP64 CSR products of the headline matrix "
+                     "(%d nnz), single thread, %.1f s" % (reps, H.nnz, tc)}
+    log("cpu oracle: %s" % json.dumps(cpu))
+    reps_p, tc_p, used = 0, 0.0, 1
+    t0 = time.perf_counter()
+    while tc_p < max(2.0, args.cpu_seconds / 2):
+        _, used = oracle.spmv_par(H, xh)
+        reps_p += 1
+        tc_p = time.perf_counter() - t0
+    cpu_all = {"value": round(bytes_alg * reps_p / tc_p / 1e9, 3),
+               "unit": "GB/s", "cores": used, "kind": "oracle",
+               "cpu": host_cpu_model(),
+               "sample": "%d full FP64 CSR products of the headline matrix, "
+                         "rows split over %d OpenMP threads" % (reps_p, used)}
+    log("cpu oracle, all cores: %s" % json.dumps(cpu_all))
+    MH.close()
+    del MH, H
+    torch.cuda.synchronize()
+
+    # ---- config 1: the 3-D elasticity system the CG legs solve
+    t = time.time()
+    A = W.config1_elasticity3d()
+    log("generated config-1 matrix: %d rows, %d nnz in %.1f s"
+        % (A.n_rows, A.nnz, time.time() - t))
+    M, c1 = measure_matrix(fs, oracle, torch, A, d, args.steps, args.warmup,
+                           stream)
+    c1_bytes = 12 * A.nnz + 8 * A.n_cols + 8 * A.n_rows
+    log("config-1 spmv_perm: %.2f us/launch, %.1f GB/s; cold median %.2f us"
+        % (c1["us"], c1["gbs"], c1["cold_us"]["median"]))
 
     # achievable streaming read rate (project kernel, 2 GiB, best of three
     # grid sizes): the practical ceiling the product is compared with
@@ -693,20 +840,21 @@ def main():
             buf, sink, blocks), 20, 3, stream)
         stream_gbs = max(stream_gbs, buf.numel() * 8 / (t_rd * 1e-6) / 1e9)
     del buf, sink
-    log("streaming read probe: %.1f GB/s; product at %.1f%% of it"
+    log("streaming read probe: %.1f GB/s; headline product at %.1f%% of it"
         % (stream_gbs, 100 * gbs / stream_gbs))
 
-    # caller numbering (gather of x + fused scatter of y)
+    # caller numbering (gather of x + fused scatter of y) on config 1
     x = W.random_vector(A.n_cols, 1, W.XVEC)
     xd = d(x)
     y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
     us_caller = back_to_back_us(torch, lambda: fs.spmv(M, xd, y), args.steps,
                                 args.warmup, stream)
-    gbs_caller = bytes_alg / (us_caller * 1e-6) / 1e9
-    log("spmv (caller numbering): %.2f us, %.1f GB/s" % (us_caller,
-                                                         gbs_caller))
+    gbs_caller = c1_bytes / (us_caller * 1e-6) / 1e9
+    log("config-1 spmv (caller numbering): %.2f us, %.1f GB/s"
+        % (us_caller, gbs_caller))
 
-    cg = ir = multi = batch = asy = asy_small = sbatch = newton = None
+    cg = ir = bf16 = multi = batch = asy = asy_small = sbatch = None
+    newton = cpu_cg = None
     if not args.no_cg:
         b = W.random_vector(A.n_rows, 1, W.BVEC)
         bd = d(b)
@@ -724,27 +872,36 @@ def main():
             rel = float(np.linalg.norm(b - oracle.spmv(A, xs_h)) /
                         np.linalg.norm(b))
             tmed = float(np.median(times))
-            return xs_h, {"status": ci["status"], "iters": ci["iters"],
-                          "outer": ci["outer"], "ms": tmed * 1e3,
-                          "solves_per_s": 1.0 / tmed,
-                          "relres_oracle": rel, "relres_gpu": ci["relres"],
-                          "replacements": ci["replacements"],
-                          "gbs_per_solve": ci["bytes"] / tmed / 1e9}
+            return xs_h, ci, {"status": ci["status"], "iters": ci["iters"],
+                              "outer": ci["outer"], "ms": tmed * 1e3,
+                              "solves_per_s": 1.0 / tmed,
+                              "relres_oracle": rel, "relres_gpu": ci["relres"],
+                              "replacements": ci["replacements"],
+                              "gbs_per_solve": ci["bytes"] / tmed / 1e9}
 
-        x64, cg = timed_solve()
-        cg.update(precond="jacobi", rtol=1e-8)
+        x64, ci64, cg = timed_solve(estimate_cond=1)
+        cg.update(precond="jacobi", rtol=1e-8,
+                  cond_est_jacobi=ci64.get("cond_est"))
         log("cg fp64: %s" % json.dumps(cg))
         ir = {}
         for name, prec, rs in (("f32", fs.PREC_IR_F32, 0),
-                               ("f32_restart", fs.PREC_IR_F32, 1),
-                               ("bf16", fs.PREC_IR_BF16, 0)):
-            xl, r = timed_solve(reps=2, precision=prec, inner_rtol=1e-2,
-                                ir_restart=rs)
+                               ("f32_restart", fs.PREC_IR_F32, 1)):
+            xl, _, r = timed_solve(reps=2, precision=prec, inner_rtol=1e-2,
+                                   ir_restart=rs)
             r["forward_err_vs_fp64"] = float(np.linalg.norm(xl - x64) /
                                              np.linalg.norm(x64))
             r["speedup_vs_fp64"] = cg["ms"] / r["ms"]
             ir[name] = r
             log("cg ir-%s: %s" % (name, json.dumps(r)))
+        bf16 = bench_bf16_variants(fs, oracle, torch, A, M, bd, b, x64, cg)
+        ir["bf16"] = bf16
+        ke = cg.get("cond_est_jacobi")
+        ir["bf16_note"] = {
+            "cond_est_jacobi": ke,
+            "cond_est_times_2^-9": ke * 2.0 ** -9 if ke else None,
+            "converged_variants": sum(r["status"] == fs.FS_OK
+                                      for r in bf16),
+            "best_relres": min(r["relres_oracle"] for r in bf16)}
         asy = bench_async(fs, oracle, torch, A, M, d, b, reps=3)
         log("cg stream-ordered (config 1): %s" % json.dumps(asy))
         A0 = W.config0_poisson2d()
@@ -753,6 +910,7 @@ def main():
         asy_small = bench_async(fs, oracle, torch, A0, M0, d,
                                 W.random_vector(A0.n_rows, 0, W.BVEC),
                                 reps=20)
+        M0.close()
         log("cg stream-ordered (config 0): %s" % json.dumps(asy_small))
         # k right-hand sides through one multi-column product per iteration
         multi = {}
@@ -782,62 +940,6 @@ def main():
         log("batched small systems: %s" % json.dumps(batch))
         sbatch = bench_spmv_batch(fs, W, oracle, d, torch, stream)
         log("batched small products: %s" % json.dumps(sbatch))
-    assembly = None
-    if not args.no_asm:
-        assembly = bench_assembly(fs, oracle, torch, A, d, stream)
-        log("assembly: %s" % json.dumps(assembly))
-    serving = None
-    if args.serving_requests > 0:
-        serving = bench_serving(fs, W, oracle, d, torch,
-                                n_req=args.serving_requests)
-        log("serving: %s" % json.dumps(serving))
-
-    largest = None
-    if not args.no_largest:
-        i12 = [i for i, r in enumerate(W.SWEEP) if r[0].startswith("S12")][0]
-        t = time.time()
-        A12 = W.sweep_matrix(i12, False)
-        tg = time.time() - t
-        M12, largest = measure_matrix(fs, oracle, torch, A12, d, 50, 5,
-                                      stream)
-        largest.update(matrix=W.SWEEP[i12][0], numbering="natural",
-                       t_generate_s=tg)
-        del M12
-        log("largest FEM matrix: %s" % json.dumps(largest))
-
-    # CPU oracle on a bounded sample: repeated full products
-    reps, tc = 0, 0.0
-    t0 = time.perf_counter()
-    while tc < args.cpu_seconds:
-        oracle.spmv(A, x)
-        reps += 1
-        tc = time.perf_counter() - t0
-    cpu = None
-    if reps:
-        cpu_gbs = bytes_alg * reps / tc / 1e9
-        log("cpu oracle: %d products in %.1f s, %.2f GB/s"
-            % (reps, tc, cpu_gbs))
-        cpu = {"value": round(cpu_gbs, 3), "unit": "GB/s", "cores": 1,
-               "kind": "oracle", "cpu": host_cpu_model(),
-               "sample": "%d full FP64 CSR products of the same matrix, "
-                         "single thread" % reps}
-    cpu_all = None
-    if reps:
-        reps_p, tc_p, used = 0, 0.0, 1
-        t0 = time.perf_counter()
-        while tc_p < max(2.0, args.cpu_seconds / 2):
-            _, used = oracle.spmv_par(A, x)
-            reps_p += 1
-            tc_p = time.perf_counter() - t0
-        cpu_all = {"value": round(bytes_alg * reps_p / tc_p / 1e9, 3),
-                   "unit": "GB/s", "cores": used, "kind": "oracle",
-                   "cpu": host_cpu_model(),
-                   "sample": "%d full FP64 CSR products of the same matrix, "
-                             "rows split over %d OpenMP threads"
-                             % (reps_p, used)}
-        log("cpu oracle, all cores: %s" % json.dumps(cpu_all))
-    cpu_cg = None
-    if reps and not args.no_cg:
         # the oracle's Jacobi-PCG on the host: config 0 to 1e-8, and a
         # bounded run of config-1 iterations scaled to the GPU's count
         A0 = W.config0_poisson2d()
@@ -845,58 +947,35 @@ def main():
         t0 = time.perf_counter()
         _, st0, it0, _ = oracle.pcg(A0, b0, precond=1)
         t_c0 = time.perf_counter() - t0
-        b1 = W.random_vector(A.n_rows, 1, W.BVEC)
         t0 = time.perf_counter()
-        _, _, it1, _ = oracle.pcg(A, b1, precond=1, maxit=40)
+        _, _, it1, _ = oracle.pcg(A, b, precond=1, maxit=40)
         per_it = (time.perf_counter() - t0) / max(1, it1)
         cpu_cg = {"config0_ms": t_c0 * 1e3, "config0_iters": it0,
                   "config1_ms_per_iter": per_it * 1e3,
-                  "config1_est_ms": per_it * 1e3 * (cg["iters"] if cg
-                                                     else 0),
+                  "config1_est_ms": per_it * 1e3 * cg["iters"],
                   "cores": 1, "kind": "oracle",
                   "sample": "config 0 solved to 1e-8; 40 config-1 "
                             "iterations, scaled to the GPU iteration count"}
         log("cpu oracle CG: %s" % json.dumps(cpu_cg))
-    traffic = measured_traffic()
+    assembly = None
+    if not args.no_asm:
+        assembly = bench_assembly(fs, oracle, torch, A, d, stream)
+        log("assembly: %s" % json.dumps(assembly))
+    serving = None
+    if args.serving_requests > 0:
+        serving = bench_serving(fs, W, oracle, d, torch,
+                                n_req=args.serving_requests,
+                                lam_factors=(0.5, 1.0, 2.0))
+        log("serving: %s" % json.dumps(serving))
 
-    out = {
-        "metric": "SpMV effective GB/s (% HBM peak); CG solves/s + p99 "
-                  "latency, FP64 vs mixed",
-        "value": round(gbs, 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": us * 1e-3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "3-D P1-tet elasticity 64^3 nodes, random "
-                               "node numbering, x=0 clamped",
-                   "n_rows": A.n_rows, "nnz": A.nnz,
-                   "op": "spmv_perm (layout numbering, as inside CG)",
-                   "bytes_per_spmv": bytes_alg},
-        "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
-        "stream_read_gbs": round(stream_gbs, 1),
-        "pct_of_stream_read": round(100.0 * gbs / stream_gbs, 2),
-        "roofline": {"bound": "hbm", "achieved": round(gbs, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "dram_gbs": (round(traffic / (us * 1e-6) / 1e9, 1)
-                                  if traffic else None),
-                     "bytes_algorithmic": bytes_alg,
-                     "kernel": "k_spmv_f64"},
+    print(json.dumps(line({
         "cpu_baseline": cpu,
         "cpu_oracle_all_cores": cpu_all,
         "cpu_oracle_cg": cpu_cg,
-        "spmv": prod,
-        "spmv_caller_numbering_gbs": round(gbs_caller, 2),
-        "paper_model_gbs": round(20 * A.nnz / (us * 1e-6) / 1e9, 2),
-        "parity_all_rows": prod["parity_all_rows"],
-        "largest_fem_matrix": largest,
+        "stream_read_gbs": round(stream_gbs, 1),
+        "pct_of_stream_read": round(100.0 * gbs / stream_gbs, 2),
+        "config1_spmv": c1,
+        "config1_spmv_caller_numbering_gbs": round(gbs_caller, 2),
         "cg": cg,
         "cg_mixed_precision": ir,
         "cg_stream_ordered": {"config1": asy, "config0": asy_small},
@@ -906,8 +985,7 @@ def main():
         "cg_batched_small": batch,
         "spmv_batched_small": sbatch,
         "serving": serving,
-    }
-    print(json.dumps(out), flush=True)
+    })), flush=True)
     # explicit teardown while the runtime is fully up: every handle closed,
     # the device drained, torch's cached pinned host blocks returned
     M.close()

@@ -310,7 +310,19 @@ typedef struct fs_cg_opts {
                              direction from step to step (the FP64
                              residual replaces the inner one); 1 restarts
                              the inner CG from zero at every step           */
-    int32_t reserved[5];  /* must be zero                                    */
+    int32_t ir_scaled;    /* IR: 1 stores the low-precision copy after
+                             Jacobi scaling, round(D^-1/2 A D^-1/2) with
+                             D = diag(A) (all diagonal entries must be
+                             positive); the inner CG then solves the
+                             scaled system with M = I, on the right-hand
+                             side D^-1/2 r, and the FP64 update is
+                             x += D^-1/2 d.  0 (default): round(A)         */
+    int32_t estimate_cond;/* FP64, one right-hand side: 1 records the CG
+                             coefficients alpha_j, beta_j and returns in
+                             info->cond_est the ratio of the extreme
+                             eigenvalues of their Lanczos tridiagonal, an
+                             estimate of the condition number of M^-1 A   */
+    int32_t reserved[3];  /* must be zero                                    */
 } fs_cg_opts;
 
 fs_status cg_opts_default(fs_cg_opts *o);
@@ -323,6 +335,13 @@ typedef struct fs_cg_info {
     double relres;        /* true relative residual |b - A x| / |b| (FP64) */
     double ms;            /* wall time of the call                          */
     double bytes;         /* algorithmic HBM bytes moved by the solve       */
+    double cond_est;      /* with opts->estimate_cond (FP64, one column):
+                             lambda_max / lambda_min of the Lanczos
+                             tridiagonal T of the CG coefficients,
+                             T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+                             T_j,j+1 = sqrt(beta_j)/alpha_j (Saad, Iterative
+                             Methods for Sparse Linear Systems, sec. 6.7.3);
+                             0 when not asked for                           */
 } fs_cg_info;
 
 /* Solve A x = b (A square, symmetric positive definite).  b and x are

@@ -87,10 +87,12 @@ def _declare(L):
                          i32, P(i32), P(f64)]
     L.or_pcg.restype = C.c_int
     L.or_ir_cg.argtypes = [i32, _i32p, _i32p, _f64p, _f32p, _f64p, _f64p,
-                           i32, f64, f64, i32, i32, P(i32), P(i32), P(f64)]
+                           i32, f64, f64, i32, i32, P(i32), P(i32), P(f64),
+                           C.c_void_p]
     L.or_ir_cg.restype = C.c_int
     L.or_ir_cg_keep.argtypes = [i32, _i32p, _i32p, _f64p, _f32p, _f64p, _f64p,
-                           i32, f64, f64, i32, i32, P(i32), P(i32), P(f64)]
+                           i32, f64, f64, i32, i32, P(i32), P(i32), P(f64),
+                           C.c_void_p]
     L.or_ir_cg_keep.restype = C.c_int
 
 
@@ -246,10 +248,12 @@ def pcg(A, b, x0=None, precond=1, rtol=1e-8, maxit=20000):
 
 
 def ir_cg(A, a_lo, b, x0=None, precond=1, rtol=1e-8, inner_rtol=1e-3,
-          max_outer=100, max_inner=20000, keep=False):
+          max_outer=100, max_inner=20000, keep=False, scale=None):
     """FP64-outer / FP32-inner refinement; returns
     (x, status, outer, inner, relres).  keep=True: one inner CG kept across
-    the steps (its residual replaced by the FP64 one at each step)."""
+    the steps (its residual replaced by the FP64 one at each step).
+    scale = s (diag(A)^-1/2): a_lo holds round(S A S) and the inner solve
+    runs on the Jacobi-scaled system (pass precond=0)."""
     L = load()
     rp, c, v = _csr(A)
     b = _f64(b)
@@ -259,10 +263,25 @@ def ir_cg(A, a_lo, b, x0=None, precond=1, rtol=1e-8, inner_rtol=1e-3,
     i = C.c_int32(0)
     rr = C.c_double(0.0)
     fn = L.or_ir_cg_keep if keep else L.or_ir_cg
+    sc = None if scale is None else np.ascontiguousarray(scale,
+                                                        dtype=np.float64)
     st = fn(A.n_rows, rp, c, v, a, b, x, int(precond), float(rtol),
             float(inner_rtol), int(max_outer), int(max_inner),
-            C.byref(o), C.byref(i), C.byref(rr))
+            C.byref(o), C.byref(i), C.byref(rr),
+            None if sc is None else sc.ctypes.data)
     return x, st, o.value, i.value, rr.value
+
+
+def jacobi_scaled_values(A):
+    """(s, v): s_i = diag(A)_i^-1/2 and the values of S A S in CSR order,
+    each formed as (a_ij s_i) s_j in FP64 (diagonal entries summed per row,
+    as stored duplicates would be)."""
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.rowptr))
+    d = np.zeros(A.n_rows)
+    on = A.col == rows
+    np.add.at(d, rows[on], A.val[on])
+    s = 1.0 / np.sqrt(d)
+    return s, (A.val * s[rows]) * s[A.col]
 
 
 def assemble_matrix(A, edof, ke):

@@ -347,6 +347,11 @@ done:
  * a_lo holds the stored low-precision values (FP32, or BF16 widened to
  * float).  *outer counts refinement steps, *inner the inner iterations over
  * all steps.  The Jacobi scaling of the inner solve uses diag(A_lo).
+ * With scale = s != NULL the inner system is the Jacobi-scaled one,
+ * S A S d' = S r with S = diag(s), s_i = diag(A)_i^-1/2 (a_lo then holds
+ * round(S A S), and the caller passes precond = 0 since that diagonal is
+ * 1): the inner right-hand side is float(s_i r_i) and the FP64 update
+ * x_i += s_i d'_i -- exactly A d = r for d = S d'.
  * ---------------------------------------------------------------------- */
 static float dotf(int32_t n, const float *a, const float *b)
 {
@@ -400,7 +405,7 @@ int or_ir_cg(int32_t n, const int32_t *rowptr, const int32_t *col,
              const double *val, const float *a_lo, const double *b,
              double *x, int32_t precond, double rtol, double inner_rtol,
              int32_t max_outer, int32_t max_inner, int32_t *outer,
-             int32_t *inner, double *relres)
+             int32_t *inner, double *relres, const double *scale)
 {
     *outer = 0;
     *inner = 0;
@@ -438,7 +443,7 @@ int or_ir_cg(int32_t n, const int32_t *rowptr, const int32_t *col,
         if (*outer >= max_outer)
             break;
         for (int32_t i = 0; i < n; ++i)
-            rf[i] = (float)r[i];
+            rf[i] = (float)(scale ? scale[i] * r[i] : r[i]);
         float rfn = sqrtf(dotf(n, rf, rf));
         int bad = 0;
         *inner += inner_cg_f32(n, rowptr, col, a_lo, dinv, rf, df,
@@ -450,7 +455,7 @@ int or_ir_cg(int32_t n, const int32_t *rowptr, const int32_t *col,
             break;
         }
         for (int32_t i = 0; i < n; ++i)
-            x[i] += (double)df[i];
+            x[i] += scale ? scale[i] * (double)df[i] : (double)df[i];
     }
 done:
     true_residual(n, rowptr, col, val, b, x, r);
@@ -470,7 +475,7 @@ int or_ir_cg_keep(int32_t n, const int32_t *rowptr, const int32_t *col,
                   const double *val, const float *a_lo, const double *b,
                   double *x, int32_t precond, double rtol, double inner_rtol,
                   int32_t max_outer, int32_t max_inner, int32_t *outer,
-                  int32_t *inner, double *relres)
+                  int32_t *inner, double *relres, const double *scale)
 {
     *outer = 0;
     *inner = 0;
@@ -504,7 +509,7 @@ int or_ir_cg_keep(int32_t n, const int32_t *rowptr, const int32_t *col,
     }
     for (int32_t i = 0; i < n; ++i) {
         d[i] = 0.0f;
-        r[i] = (float)r64[i];
+        r[i] = (float)(scale ? scale[i] * r64[i] : r64[i]);
         z[i] = dinv[i] * r[i];
         p[i] = z[i];
     }
@@ -526,7 +531,7 @@ int or_ir_cg_keep(int32_t n, const int32_t *rowptr, const int32_t *col,
         if (sqrtf(dotf(n, r, r)) <= tol) {
             /* FP64 steps: update and residual; then rebase the inner CG */
             for (int32_t i = 0; i < n; ++i)
-                x[i] += (double)d[i];
+                x[i] += scale ? scale[i] * (double)d[i] : (double)d[i];
             *outer += 1;
             true_residual(n, rowptr, col, val, b, x, r64);
             if (sqrt(dot(n, r64, r64)) <= rtol * bnorm) {
@@ -537,7 +542,7 @@ int or_ir_cg_keep(int32_t n, const int32_t *rowptr, const int32_t *col,
                 break;
             for (int32_t i = 0; i < n; ++i) {
                 d[i] = 0.0f;
-                r[i] = (float)r64[i];
+                r[i] = (float)(scale ? scale[i] * r64[i] : r64[i]);
             }
             tol = (float)inner_rtol * sqrtf(dotf(n, r, r));
         }

@@ -73,14 +73,15 @@ class CgOpts(C.Structure):
                 ("inner_rtol", C.c_double), ("check_every", C.c_int32),
                 ("x0_zero", C.c_int32), ("use_graph", C.c_int32),
                 ("max_outer", C.c_int32), ("ir_restart", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("ir_scaled", C.c_int32), ("estimate_cond", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class CgInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32),
                 ("outer", C.c_int32), ("replacements", C.c_int32),
                 ("relres", C.c_double), ("ms", C.c_double),
-                ("bytes", C.c_double)]
+                ("bytes", C.c_double), ("cond_est", C.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -123,7 +124,9 @@ _lib = None
 
 
 def lib_path():
-    return _build.LIB
+    """The library this process loads: libfespmv.so, or the file named by
+    the FESPMV_LIB environment variable (e.g. the sanitizer build)."""
+    return os.environ.get("FESPMV_LIB") or _build.LIB
 
 
 def load(build_if_missing=True):
@@ -131,11 +134,12 @@ def load(build_if_missing=True):
     global _lib
     if _lib is not None:
         return _lib
-    if build_if_missing and _build.needs_build():
+    path = lib_path()
+    if path == _build.LIB and build_if_missing and _build.needs_build():
         _build.build()
-    if not os.path.exists(_build.LIB):
-        raise FsError(FS_E_HIP, "libfespmv.so is not built")
-    L = C.CDLL(_build.LIB)
+    if not os.path.exists(path):
+        raise FsError(FS_E_HIP, "%s is not built" % os.path.basename(path))
+    L = C.CDLL(path)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     P = C.POINTER
     L.fs_last_error.restype = C.c_char_p

@@ -660,6 +660,7 @@ fs_status csr_update_values(fs_csr_t A, const double *vals, hipStream_t s)
     FS_HIP_TRY(launch_value_refresh(A->d_groups, A->n_groups, A->d_imap,
                                     vals, A->d_val, A->d_val_f32,
                                     A->d_val_bf16, s));
+    A->lo_scaled_dt = 0;   // the scaled copy is rebuilt by the next solve
     return FS_OK;
 }
 

@@ -31,6 +31,7 @@
 // The vector type ST is double for FP64 solves and float for the inner
 // solve of mixed-precision refinement; values VT are double, float or bf16;
 // every dot product is accumulated in double.
+#include <algorithm>
 #include <type_traits>
 
 #include "device.h"
@@ -477,6 +478,18 @@ __global__ __launch_bounds__(kBlock) void k_update(
 // short: ~3 rows per thread on a 774k-row system).
 constexpr int kPrefetchRows = 4;
 
+// alpha_j and beta_j of iteration j = cs.iter into the system's coefficient
+// record (condition estimate), when it asks for one; beta = 0 where the
+// recurrence stopped (the record then splits there).
+__device__ __forceinline__ void record_coeffs(const SysDesc &S,
+                                              const ColState &cs, double beta)
+{
+    if (S.hist && cs.iter < S.hist_cap) {
+        S.hist[2 * long(cs.iter)] = cs.alpha;
+        S.hist[2 * long(cs.iter) + 1] = beta;
+    }
+}
+
 template <typename ST>
 __global__ __launch_bounds__(kBlock) void k_update_fused(
     const SysDesc *__restrict__ sys, const int *__restrict__ vmap)
@@ -565,6 +578,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_fused(
     const bool lead = lb == 0 && threadIdx.x == 0;
     if (rr <= cs.tol2) {
         if (lead) {
+            record_coeffs(S, cs, 0.0);
             cs.iter += 1;
             cs.rr = rr;
             cs.status = CG_RECURRENCE_MET;
@@ -581,6 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_fused(
         return;
     }
     if (lead) {
+        record_coeffs(S, cs, beta);
         cs.iter += 1;
         cs.rr = rr;
         cs.beta = beta;
@@ -1030,22 +1045,84 @@ __global__ __launch_bounds__(kBlock) void k_permute_rows(
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_to_f32(long n,
+// b = float(a), or float(sc[row] * a) with sc != NULL (k entries per row)
+__global__ __launch_bounds__(kBlock) void k_to_f32(long n, int k,
                                                    const double *__restrict__ a,
+                                                   const double *__restrict__ sc,
                                                    float *__restrict__ b)
 {
     for (long e = long(blockIdx.x) * kBlock + threadIdx.x; e < n;
          e += long(gridDim.x) * kBlock)
-        b[e] = float(a[e]);
+        b[e] = float(sc ? sc[e / k] * a[e] : a[e]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_add_f32(long n, double alpha,
+// x += alpha d, or x += alpha (sc[row] d) with sc != NULL
+__global__ __launch_bounds__(kBlock) void k_add_f32(long n, int k, double alpha,
                                                     const float *__restrict__ d,
+                                                    const double *__restrict__ sc,
                                                     double *__restrict__ x)
 {
     for (long e = long(blockIdx.x) * kBlock + threadIdx.x; e < n;
-         e += long(gridDim.x) * kBlock)
-        x[e] += alpha * double(d[e]);
+         e += long(gridDim.x) * kBlock) {
+        const double de = sc ? sc[e / k] * double(d[e]) : double(d[e]);
+        x[e] += alpha * de;
+    }
+}
+
+// Jacobi scaling of the layout: sc[row] = 1 / sqrt(a_row,row); rows whose
+// diagonal is not positive and finite get 0 and are counted in *bad.  One
+// wavefront per row group (grid-stride).
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_diag_rsqrt(
+    const Group *__restrict__ groups, int ngroups, const double *__restrict__ val,
+    const int32_t *__restrict__ col, double *__restrict__ sc,
+    int32_t *__restrict__ bad)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int g = blockIdx.x * kWavesPerBlock + int(threadIdx.x >> 6);
+         g < ngroups; g += gridDim.x * kWavesPerBlock) {
+        const Group gd = load_group(gbl(groups), __builtin_amdgcn_readfirstlane(g));
+        const int lt = gd.width_lt >> 24, width = gd.width_lt & 0xffffff;
+        const int r = lane >> lt, row = gd.row0 + r;
+        const long base = long(gd.base64) * kWave;
+        double d = 0.0;
+        for (int s = 0; s < width; ++s) {
+            const long idx = base + long(s / V) * kWave * V + lane * V + s % V;
+            if (col[idx] == row) d += val[idx];
+        }
+        d = row_reduce(d, lt);
+        if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
+            const bool ok = d > 0.0 && isfinite(d);
+            if (!ok) atomicAdd(bad, 1);
+            sc[row] = ok ? 1.0 / sqrt(d) : 0.0;
+        }
+    }
+}
+
+// Low-precision copy of the Jacobi-scaled values: slot (row, col) holds
+// round((a * sc[row]) * sc[col]) (FP64 products, then float nearest, then
+// bf16 nearest-even); padding stays 0.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_cast_scaled(
+    const Group *__restrict__ groups, int ngroups, const double *__restrict__ val,
+    const int32_t *__restrict__ col, const double *__restrict__ sc,
+    float *__restrict__ f32, uint16_t *__restrict__ bf16)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int g = blockIdx.x * kWavesPerBlock + int(threadIdx.x >> 6);
+         g < ngroups; g += gridDim.x * kWavesPerBlock) {
+        const Group gd = load_group(gbl(groups), __builtin_amdgcn_readfirstlane(g));
+        const int lt = gd.width_lt >> 24, width = gd.width_lt & 0xffffff;
+        const int row = gd.row0 + (lane >> lt);
+        const long base = long(gd.base64) * kWave;
+        for (int s = 0; s < width; ++s) {
+            const long idx = base + long(s / V) * kWave * V + lane * V + s % V;
+            const int c = col[idx];
+            const float f = c >= 0 ? float((val[idx] * sc[row]) * sc[c]) : 0.0f;
+            if (f32) f32[idx] = f;
+            if (bf16) bf16[idx] = f32_to_bf16_rne(f);
+        }
+    }
 }
 
 // Low-precision copies of the slot values (padding stays 0).
@@ -1059,6 +1136,14 @@ __global__ __launch_bounds__(kBlock) void k_cast_slots(
         if (f32) f32[e] = f;
         if (bf16) bf16[e] = f32_to_bf16_rne(f);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_f64(long n, double v,
+                                                     double *__restrict__ p)
+{
+    for (long e = long(blockIdx.x) * kBlock + threadIdx.x; e < n;
+         e += long(gridDim.x) * kBlock)
+        p[e] = v;
 }
 
 int flat_blocks(long n)
@@ -1096,20 +1181,55 @@ hipError_t permute_rows(int32_t n, int32_t k, const int32_t *perm,
     return hipGetLastError();
 }
 
-hipError_t to_f32(int64_t n, const double *a, float *b, hipStream_t s)
+hipError_t to_f32(int64_t n, int32_t k, const double *a, const double *sc,
+                  float *b, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_to_f32, dim3(flat_blocks(n)), dim3(kBlock), 0, s,
-                       long(n), a, b);
+                       long(n), int(k), a, sc, b);
     return hipGetLastError();
 }
 
-hipError_t add_f32(int64_t n, double alpha, const float *d, double *x,
-                   hipStream_t s)
+hipError_t add_f32(int64_t n, int32_t k, double alpha, const float *d,
+                   const double *sc, double *x, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_add_f32, dim3(flat_blocks(n)), dim3(kBlock), 0, s,
-                       long(n), alpha, d, x);
+                       long(n), int(k), alpha, d, sc, x);
+    return hipGetLastError();
+}
+
+hipError_t scaled_lowp_copy(const fs_csr *A, int32_t dtype, double *sc,
+                            void *out, int32_t *bad, hipStream_t s)
+{
+    if (A->n_groups == 0) return hipSuccess;
+    const int nb = std::min((A->n_groups + kWavesPerBlock - 1) / kWavesPerBlock,
+                            8192);
+    float *f32 = dtype == FS_DT_F32 ? static_cast<float *>(out) : nullptr;
+    uint16_t *bf = dtype == FS_DT_BF16 ? static_cast<uint16_t *>(out) : nullptr;
+    if (A->host.vec == 1) {
+        hipLaunchKernelGGL(k_diag_rsqrt<1>, dim3(nb), dim3(kBlock), 0, s,
+                           A->d_groups, A->n_groups, A->d_val, A->d_col, sc,
+                           bad);
+        hipLaunchKernelGGL(k_cast_scaled<1>, dim3(nb), dim3(kBlock), 0, s,
+                           A->d_groups, A->n_groups, A->d_val, A->d_col, sc,
+                           f32, bf);
+    } else {
+        hipLaunchKernelGGL(k_diag_rsqrt<2>, dim3(nb), dim3(kBlock), 0, s,
+                           A->d_groups, A->n_groups, A->d_val, A->d_col, sc,
+                           bad);
+        hipLaunchKernelGGL(k_cast_scaled<2>, dim3(nb), dim3(kBlock), 0, s,
+                           A->d_groups, A->n_groups, A->d_val, A->d_col, sc,
+                           f32, bf);
+    }
+    return hipGetLastError();
+}
+
+hipError_t fill_f64(int64_t n, double v, double *p, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3(flat_blocks(n)), dim3(kBlock), 0, s,
+                       long(n), v, p);
     return hipGetLastError();
 }
 

@@ -110,6 +110,8 @@ struct SysDesc {
     int32_t *bad_diag;           // rows with a zero / non-finite diagonal
     double *partials;            // 3 * k * max(snb, vnb) entries
     double rtol;
+    double *hist;                // alpha_j, beta_j per iteration (one
+    int32_t hist_cap, pad2;      //   column), or NULL: not recorded
 };
 
 // Column-count class of a system with k right-hand sides: the launch's
@@ -161,12 +163,21 @@ hipError_t engine_gather_states(const EngineLaunch &L, ColState *staging,
 hipError_t permute_rows(int32_t n, int32_t k, const int32_t *perm,
                         const double *src, int64_t lds, double *dst,
                         int64_t ldd, bool to_layout, hipStream_t s);
-hipError_t to_f32(int64_t n, const double *a, float *b, hipStream_t s);
-// x += alpha * d (d widened exactly)
-hipError_t add_f32(int64_t n, double alpha, const float *d, double *x,
-                   hipStream_t s);
+// b = float(a) (sc NULL) or float(sc[row] a), n entries, k per row
+hipError_t to_f32(int64_t n, int32_t k, const double *a, const double *sc,
+                  float *b, hipStream_t s);
+// x += alpha * d (d widened exactly), or x += alpha * (sc[row] d)
+hipError_t add_f32(int64_t n, int32_t k, double alpha, const float *d,
+                   const double *sc, double *x, hipStream_t s);
+// sc = diag(A)^-1/2 (FP64, layout rows; non-positive diagonals counted in
+// *bad) and out = the FP32 / BF16 copy of D^-1/2 A D^-1/2 in slot order
+hipError_t scaled_lowp_copy(const struct ::fs_csr *A, int32_t dtype,
+                            double *sc, void *out, int32_t *bad,
+                            hipStream_t s);
 hipError_t cast_slots(int64_t n, const double *v, float *f32, uint16_t *bf16,
                       hipStream_t s);
+// p[0 .. n) = v (a kernel, not a memset: safe inside captured work)
+hipError_t fill_f64(int64_t n, double v, double *p, hipStream_t s);
 
 // ------------------------------------------------------------ host engine
 // Device state of one system (matrix + k right-hand sides) in one vector
@@ -183,6 +194,10 @@ struct CgSys {
     double rtol = 1e-8;
     int32_t maxit = 20000;
     int64_t bytes = 0;
+    const void *val = nullptr;   // values used instead of A's (scaled copy)
+    double *hist = nullptr;      // coefficient record (2 per iteration)
+    int32_t hist_cap = 0;
+    bool record = false;         // record the coefficients in this solve
 };
 
 // A set of systems launched together (same value/vector types and slot
@@ -210,6 +225,16 @@ fs_status batch_iterations(Batch &B, int32_t iters, bool use_graph,
                            hipStream_t s);
 fs_status batch_read_states(Batch &B, hipStream_t s);  // -> h_stage
 void free_solver_state(struct ::fs_csr *A);
+// Stream-ordered solve (cg_solve_async and its no-allocation variant):
+// argument checks (o receives the normalised options), then the enqueue
+// with workspace ws (6 n doubles), part (kPersistPartials doubles) and the
+// device result dinfo, copied to the host record info on s.
+fs_status async_check(struct ::fs_csr *A, const double *b, double *x,
+                      const fs_cg_opts *opts, fs_cg_info *info,
+                      fs_cg_opts &o);
+fs_status async_enqueue(struct ::fs_csr *A, const double *b, double *x,
+                        const fs_cg_opts &o, double *ws, double *part,
+                        fs_cg_info *dinfo, fs_cg_info *info, hipStream_t s);
 
 }  // namespace fs
 
@@ -250,6 +275,12 @@ struct fs_csr {
     // numbering, block partials, the device result
     double *d_async = nullptr, *d_apart = nullptr;
     fs_cg_info *d_ainfo = nullptr;
+    // scaled refinement: D^-1/2 per layout row and the low-precision copy
+    // of D^-1/2 A D^-1/2 (dtype lo_scaled_dt; 0 = none or stale after a
+    // value update)
+    double *d_iscale = nullptr;
+    void *d_val_lo_scaled = nullptr;
+    int32_t lo_scaled_dt = 0;
 };
 
 namespace fs {
@@ -300,6 +331,8 @@ hipError_t launch_spmv_batch(int32_t m, const fs_csr *const *A,
 // FP64, layout numbering): grid size for the handle, and the launch.  info
 // is a device struct written at the end.
 constexpr int kPersistMaxBlocks = 1024;
+// block partials of the persistent kernel: two regions of 3 per block
+constexpr int kPersistPartials = 2 * 3 * kPersistMaxBlocks;
 int32_t persistent_blocks(const fs_csr *A);
 hipError_t launch_cg_persistent(const fs_csr *A, int32_t nblocks,
                                 const double *b, double *x, double *r,

@@ -314,6 +314,7 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
         o.iters = it;
         o.outer = 0;
         o.replacements = repl;
+        o.cond_est = 0.0;
         o.relres = bb > 0.0 ? sqrt(rr_true / bb) : 0.0;
         o.ms = double(wall_clock64() - t_start) / a.clock_khz;
         o.bytes = double(it) * (12.0 * a.nnz + (D ? 104.0 : 88.0) * a.n) +

@@ -45,6 +45,8 @@ void sys_free(CgSys &S)
 {
     dfree(S.x); dfree(S.r); dfree(S.p); dfree(S.q); dfree(S.b);
     dfree(S.dinv); dfree(S.cs); dfree(S.bad); dfree(S.partials);
+    dfree(S.hist);
+    S.hist_cap = 0;
     S.bytes = 0;
     S.k = 0;
 }
@@ -122,7 +124,7 @@ fs_status batch_build(Batch &B, hipStream_t s)
         SysDesc &d = descs[size_t(i)];
         std::memset(&d, 0, sizeof d);
         d.groups = A->d_groups;
-        d.val = values_of(A, S.vt);
+        d.val = S.val ? S.val : values_of(A, S.vt);
         d.col = A->d_col;
         d.cstream = A->d_col16 ? static_cast<const void *>(A->d_col16)
                                : static_cast<const void *>(A->d_col);
@@ -142,6 +144,8 @@ fs_status batch_build(Batch &B, hipStream_t s)
         d.bad_diag = S.bad;
         d.partials = S.partials;
         d.rtol = S.rtol;
+        d.hist = S.record && S.k == 1 ? S.hist : nullptr;
+        d.hist_cap = S.hist_cap;
         smap.insert(smap.end(), size_t(S.snb), i);
         vmap.insert(vmap.end(), size_t(S.vnb), i);
         for (int32_t c = 0; c < S.k; ++c) B.cols.push_back(int2{i, c});
@@ -387,6 +391,64 @@ fs_status store_block(const fs_csr *A, int32_t k, const void *src,
                            hipGetErrorString(hipGetLastError()));
 }
 
+// Number of eigenvalues below x of the symmetric tridiagonal (diag a,
+// off-diagonal e; m entries), by the signs of the LDL^T pivots (Sturm).
+int32_t sturm_count(const std::vector<double> &a, const std::vector<double> &e,
+                    double x)
+{
+    const int32_t m = int32_t(a.size());
+    int32_t cnt = 0;
+    double d = 1.0;
+    for (int32_t i = 0; i < m; ++i) {
+        const double off = i ? e[size_t(i - 1)] * e[size_t(i - 1)] / d : 0.0;
+        d = a[size_t(i)] - x - off;
+        if (d == 0.0) d = -1e-300;
+        if (d < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Condition estimate from m CG steps (ab = alpha_0, beta_0, alpha_1, ...):
+// the extreme eigenvalues of the Lanczos tridiagonal T of the PCG
+// coefficients, T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+// T_j,j+1 = sqrt(beta_j)/alpha_j, found by bisection on the Sturm count
+// inside the Gershgorin interval.  0 when nothing was recorded.
+double lanczos_cond(const std::vector<double> &ab, int32_t m)
+{
+    if (m < 1) return 0.0;
+    std::vector<double> a(static_cast<size_t>(m)), e(static_cast<size_t>(m));
+    for (int32_t j = 0; j < m; ++j) {
+        const double al = ab[size_t(2 * j)], be = ab[size_t(2 * j + 1)];
+        a[size_t(j)] = 1.0 / al;
+        if (j) {
+            const double alp = ab[size_t(2 * j - 2)], bep = ab[size_t(2 * j - 1)];
+            a[size_t(j)] += bep / alp;
+        }
+        e[size_t(j)] = be > 0.0 ? std::sqrt(be) / al : 0.0;
+    }
+    double lo = a[0], hi = a[0];
+    for (int32_t j = 0; j < m; ++j) {
+        const double r = (j ? std::fabs(e[size_t(j - 1)]) : 0.0) +
+                         (j + 1 < m ? std::fabs(e[size_t(j)]) : 0.0);
+        lo = std::min(lo, a[size_t(j)] - r);
+        hi = std::max(hi, a[size_t(j)] + r);
+    }
+    if (!std::isfinite(lo) || !std::isfinite(hi)) return 0.0;
+    auto kth = [&](int32_t k) {          // the k-th smallest (1-based)
+        double l = lo, h = hi;
+        for (int it = 0; it < 200 && h - l > 1e-15 * std::max(std::fabs(l),
+                                                                std::fabs(h));
+             ++it) {
+            const double mid = 0.5 * (l + h);
+            if (sturm_count(a, e, mid) >= k) h = mid;
+            else l = mid;
+        }
+        return 0.5 * (l + h);
+    };
+    const double lmin = kth(1), lmax = kth(m);
+    return lmin > 0.0 ? lmax / lmin : 0.0;
+}
+
 // FP64 CG on one handle with k right-hand sides (caller blocks B, X).
 fs_status solve_f64(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
                     double *Xc, int64_t ldx, const fs_cg_opts &o,
@@ -400,6 +462,16 @@ fs_status solve_f64(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
     CgSys &S = *A->sys_f64;
     S.rtol = o.rtol;
     S.maxit = o.maxit;
+    S.val = nullptr;
+    S.record = o.estimate_cond != 0 && k == 1;
+    if (S.record && S.hist_cap < o.maxit) {
+        dfree(S.hist);
+        S.hist_cap = 0;
+        int64_t acct = 0;
+        FS_TRY(dmalloc(reinterpret_cast<void **>(&S.hist),
+                       sizeof(double) * 2 * size_t(o.maxit), acct));
+        S.hist_cap = o.maxit;
+    }
     FS_TRY(load_block(A, k, Bc, ldb, S.b, s));
     if (o.x0_zero)
         FS_HIP_TRY(hipMemsetAsync(S.x, 0, sizeof(double) * size_t(S.n) * k, s));
@@ -419,6 +491,18 @@ fs_status solve_f64(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
                                         sizeof(double) * size_t(k), 0,
                                         sizeof(double), size_t(S.n), s));
     FS_TRY(store_block(A, k, S.x, Xc, ldx, s));
+    double cond = 0.0;
+    if (S.record) {
+        const int32_t m = std::min(B.h_stage[0].iter, S.hist_cap);
+        std::vector<double> ab(2 * static_cast<size_t>(std::max(m, 1)));
+        if (m > 0)
+            FS_HIP_TRY(hipMemcpyAsync(ab.data(), S.hist,
+                                      sizeof(double) * 2 * size_t(m),
+                                      hipMemcpyDeviceToHost, s));
+        FS_HIP_TRY(hipStreamSynchronize(s));
+        cond = lanczos_cond(ab, m);
+        S.record = false;
+    }
     FS_HIP_TRY(hipStreamSynchronize(s));
     fs_status ret = FS_OK;
     const double it_bytes = 12.0 * double(A->nnz) +
@@ -428,6 +512,7 @@ fs_status solve_f64(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
         infos[c].outer = 0;
         infos[c].bytes = double(B.h_stage[c].iter) * it_bytes / k +
                          2.0 * (12.0 * double(A->nnz) + 16.0 * A->n_rows);
+        infos[c].cond_est = cond;
         ret = worst(ret, infos[c].status);
     }
     return ret;
@@ -465,17 +550,56 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
 {
     const int32_t dt = o.precision == FS_PREC_IR_F32 ? FS_DT_F32 : FS_DT_BF16;
     const int32_t vt = dt == FS_DT_F32 ? VT_F32 : VT_BF16;
-    if (!(A->dtypes & dt)) FS_TRY(csr_add_dtype(A, dt, caller));
+    const bool scaled = o.ir_scaled != 0;
+    if (!scaled && !(A->dtypes & dt)) FS_TRY(csr_add_dtype(A, dt, caller));
     FS_TRY(ensure_stream(A));
     hipStream_t s = A->stream;
     FS_HIP_TRY(hipEventRecord(A->ev, caller));
     FS_HIP_TRY(hipStreamWaitEvent(s, A->ev, 0));
+    if (scaled && A->lo_scaled_dt != dt) {
+        // the low-precision copy of D^-1/2 A D^-1/2 (after a value update
+        // or for the other precision: rebuilt)
+        A->lo_scaled_dt = 0;
+        dfree(A->d_val_lo_scaled);
+        int64_t acct = 0;
+        if (!A->d_iscale)
+            FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_iscale),
+                           sizeof(double) * size_t(A->n_rows), acct));
+        FS_TRY(dmalloc(&A->d_val_lo_scaled,
+                       size_t(A->slots) * (dt == FS_DT_F32 ? 4 : 2), acct));
+        int32_t *d_bad = nullptr;
+        FS_TRY(dmalloc(reinterpret_cast<void **>(&d_bad), sizeof(int32_t),
+                       acct));
+        int32_t bad = 0;
+        hipError_t e = hipMemsetAsync(d_bad, 0, sizeof(int32_t), s);
+        if (e == hipSuccess)
+            e = scaled_lowp_copy(A, dt, A->d_iscale, A->d_val_lo_scaled,
+                                 d_bad, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&bad, d_bad, sizeof bad, hipMemcpyDeviceToHost,
+                               s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        dfree(d_bad);
+        FS_HIP_TRY(e);
+        if (bad)
+            return set_error(FS_E_ARG,
+                             "scaled refinement: %d rows without a positive "
+                             "diagonal", bad);
+        A->lo_scaled_dt = dt;
+    }
     FS_TRY(ensure_sys(A->sys_f64, A, k, VT_F64, ST_F64, o.precond));
-    FS_TRY(ensure_sys(A->sys_lo, A, k, vt, ST_F32, o.precond));
+    FS_TRY(ensure_sys(A->sys_lo, A, k, vt, ST_F32, scaled ? 0 : o.precond));
     CgSys &Out = *A->sys_f64, &In = *A->sys_lo;
     Out.rtol = o.rtol;
     Out.maxit = o.maxit;
+    Out.val = nullptr;
+    Out.record = false;
     In.rtol = o.inner_rtol;
+    In.val = scaled ? A->d_val_lo_scaled : nullptr;
+    In.record = false;
+    // Jacobi scaling of the vectors around the inner solve (NULL: none)
+    const double *sc = scaled ? A->d_iscale : nullptr;
+    const bool in_pc = !scaled && o.precond != 0;
     FS_TRY(load_block(A, k, Bc, ldb, Out.b, s));
     if (o.x0_zero)
         FS_HIP_TRY(hipMemsetAsync(Out.x, 0, sizeof(double) * size_t(Out.n) * k,
@@ -529,8 +653,8 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
             // converge (rounding error times condition number >= 1): stop.
             // After a step that kept the search direction, retry once with
             // a fresh inner solve.
-            FS_HIP_TRY(add_f32(nk, -1.0, static_cast<const float *>(In.x),
-                               static_cast<double *>(Out.x), s));
+            FS_HIP_TRY(add_f32(nk, k, -1.0, static_cast<const float *>(In.x),
+                               sc, static_cast<double *>(Out.x), s));
             FS_HIP_TRY(engine_residual(BO.L, 0, false, s));
             FS_TRY(batch_read_states(BO, s));
             for (int32_t c = 0; c < k; ++c) last[size_t(c)] = BO.h_stage[c];
@@ -553,14 +677,14 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
                     static_cast<double *>(Out.r) + c,
                     sizeof(double) * size_t(k), 0, sizeof(double),
                     size_t(Out.n), s));
-        FS_HIP_TRY(to_f32(nk, static_cast<const double *>(Out.r),
+        FS_HIP_TRY(to_f32(nk, k, static_cast<const double *>(Out.r), sc,
                           static_cast<float *>(In.b), s));
         FS_HIP_TRY(hipMemsetAsync(In.x, 0, sizeof(float) * size_t(nk), s));
         inner_bad = false;
         if (fresh || o.ir_restart) {
             inner_base = inner_total;
             In.maxit = std::max(1, o.maxit - inner_base);
-            FS_TRY(start_inner(BI, o.precond != 0, s));
+            FS_TRY(start_inner(BI, in_pc, s));
             fresh = false;
             last_fresh = true;
         } else {
@@ -612,7 +736,7 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
                 BI.h_stage[c].status == CG_BREAKDOWN)
                 fresh = true;
         ++outer;
-        FS_HIP_TRY(add_f32(nk, 1.0, static_cast<const float *>(In.x),
+        FS_HIP_TRY(add_f32(nk, k, 1.0, static_cast<const float *>(In.x), sc,
                            static_cast<double *>(Out.x), s));
     }
     FS_TRY(store_block(A, k, Out.x, Xc, ldx, s));
@@ -620,7 +744,7 @@ fs_status solve_ir(fs_csr *A, int32_t k, const double *Bc, int64_t ldb,
     fs_status ret = FS_OK;
     const double sv = dt == FS_DT_F32 ? 4.0 : 2.0;
     const double in_bytes = (sv + 4.0) * double(A->nnz) +
-                            (o.precond ? 52.0 : 44.0) * A->n_rows * k;
+                            (in_pc ? 52.0 : 44.0) * A->n_rows * k;
     const double out_bytes = 12.0 * double(A->nnz) + 40.0 * A->n_rows * k;
     for (int32_t c = 0; c < k; ++c) {
         const ColState &cs = last[size_t(c)];
@@ -700,6 +824,9 @@ void free_solver_state(fs_csr *A)
     dfree(A->d_async);
     dfree(A->d_apart);
     dfree(A->d_ainfo);
+    dfree(A->d_iscale);
+    dfree(A->d_val_lo_scaled);
+    A->lo_scaled_dt = 0;
     if (A->ev) (void)hipEventDestroy(A->ev);
     A->ev = nullptr;
     if (A->stream) (void)hipStreamDestroy(A->stream);
@@ -724,28 +851,62 @@ extern "C" fs_status cg_solve(fs_csr_t A, const double *b, double *x,
     return st;
 }
 
-extern "C" fs_status cg_solve_async(fs_csr_t A, const double *b, double *x,
-                                    const fs_cg_opts *opts, fs_cg_info *info,
-                                    hipStream_t s)
+namespace fs {
+
+fs_status async_check(fs_csr *A, const double *b, double *x,
+                      const fs_cg_opts *opts, fs_cg_info *info,
+                      fs_cg_opts &o)
 {
-    fs_cg_opts o;
     FS_TRY(normalise_opts(opts, o));
     FS_TRY(check_solve_args(A, 1, b, x, 1, 1));
     if (!info) return set_error(FS_E_ARG, "info is required");
     if (o.precision != FS_PREC_F64)
         return set_error(FS_E_UNSUPPORTED,
                          "the stream-ordered solve runs in FP64");
-    if (A->n_rows == 0) {
-        std::memset(info, 0, sizeof(fs_cg_info));
-        return FS_OK;
-    }
-    DeviceGuard g(A->device);
+    if (A->n_rows == 0) return FS_OK;
     int coop = 0;
     FS_HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch,
                                      A->device));
     if (!coop)
         return set_error(FS_E_UNSUPPORTED,
                          "device without cooperative launches");
+    return FS_OK;
+}
+
+fs_status async_enqueue(fs_csr *A, const double *b, double *x,
+                        const fs_cg_opts &o, double *ws, double *part,
+                        fs_cg_info *dinfo, fs_cg_info *info, hipStream_t s)
+{
+    const int64_t n = A->n_rows;
+    double *B = ws, *X = B + n, *R = X + n, *P = R + n, *Q = P + n,
+           *Dv = Q + n;
+    FS_TRY(load_block(A, 1, b, 1, B, s));
+    if (o.x0_zero)
+        FS_HIP_TRY(fill_f64(n, 0.0, X, s));
+    else
+        FS_TRY(load_block(A, 1, x, 1, X, s));
+    FS_HIP_TRY(launch_cg_persistent(A, persistent_blocks(A), B, X, R, P, Q,
+                                    o.precond ? Dv : nullptr, part, dinfo,
+                                    o.rtol, o.maxit, o.x0_zero != 0, s));
+    FS_TRY(store_block(A, 1, X, x, 1, s));
+    FS_HIP_TRY(hipMemcpyAsync(info, dinfo, sizeof(fs_cg_info),
+                              hipMemcpyDeviceToHost, s));
+    return FS_OK;
+}
+
+}  // namespace fs
+
+extern "C" fs_status cg_solve_async(fs_csr_t A, const double *b, double *x,
+                                    const fs_cg_opts *opts, fs_cg_info *info,
+                                    hipStream_t s)
+{
+    fs_cg_opts o;
+    FS_TRY(async_check(A, b, x, opts, info, o));
+    if (A->n_rows == 0) {
+        std::memset(info, 0, sizeof(fs_cg_info));
+        return FS_OK;
+    }
+    DeviceGuard g(A->device);
     const int64_t n = A->n_rows;
     if (!A->d_async) {
         // first use: workspace of the handle (allocation synchronises)
@@ -753,26 +914,13 @@ extern "C" fs_status cg_solve_async(fs_csr_t A, const double *b, double *x,
         FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_async),
                        sizeof(double) * size_t(6 * n), acct));
         FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_apart),
-                       sizeof(double) * 2 * 3 * kPersistMaxBlocks, acct));
+                       sizeof(double) * kPersistPartials, acct));
         FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_ainfo),
                        sizeof(fs_cg_info), acct));
         A->device_bytes += acct;
     }
-    double *B = A->d_async, *X = B + n, *R = X + n, *P = R + n, *Q = P + n,
-           *Dv = Q + n;
-    FS_TRY(load_block(A, 1, b, 1, B, s));
-    if (o.x0_zero)
-        FS_HIP_TRY(hipMemsetAsync(X, 0, sizeof(double) * size_t(n), s));
-    else
-        FS_TRY(load_block(A, 1, x, 1, X, s));
-    FS_HIP_TRY(launch_cg_persistent(A, persistent_blocks(A), B, X, R, P, Q,
-                                    o.precond ? Dv : nullptr, A->d_apart,
-                                    A->d_ainfo, o.rtol, o.maxit,
-                                    o.x0_zero != 0, s));
-    FS_TRY(store_block(A, 1, X, x, 1, s));
-    FS_HIP_TRY(hipMemcpyAsync(info, A->d_ainfo, sizeof(fs_cg_info),
-                              hipMemcpyDeviceToHost, s));
-    return FS_OK;
+    return async_enqueue(A, b, x, o, A->d_async, A->d_apart, A->d_ainfo, info,
+                         s);
 }
 
 extern "C" fs_status cg_solve_multi(fs_csr_t A, int32_t k, const double *B,

@@ -63,3 +63,121 @@ def test_bf16_refinement_stops_when_it_stalls(fs, orc, restart):
     # the same system in FP64 converges
     x64, i64 = fs.cg_solve(M, dev(b), precond=1)
     assert i64["status"] == fs.FS_OK
+
+
+# ------------------------------------------- Jacobi-scaled low precision
+def exact_stencil(n):
+    """The 2-D 5-point stencil with its exact values 4, -1 (the unjittered
+    P1 assembly rounded to them), n x n nodes, boundary rows removed."""
+    U = W.poisson_2d_p1(n, jitter=0.0, bc="all")
+    return CSR(U.n_rows, U.n_cols, U.rowptr, U.col, np.round(U.val))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("restart", [0, 1])
+def test_scaled_refinement_is_bitwise_jacobi_on_power_of_two_diagonal(
+        fs, orc, prec, restart):
+    """diag(A) = 4 I: the scaled copy is A / 4 exactly and every quantity of
+    the scaled refinement is the unscaled (Jacobi) one times an exact power
+    of two, so x, steps and inner iterations agree bitwise."""
+    A = exact_stencil(24)
+    b = W.random_vector(A.n_rows, 37, W.BVEC)
+    p = fs.PREC_IR_F32 if prec == "f32" else fs.PREC_IR_BF16
+    note("ir scaled vs jacobi %s restart=%d" % (prec, restart))
+    M = make(A)
+    xu, iu = fs.cg_solve(M, dev(b), precond=1, precision=p, inner_rtol=1e-2,
+                         ir_restart=restart)
+    xs, is_ = fs.cg_solve(M, dev(b), precond=1, precision=p,
+                          inner_rtol=1e-2, ir_restart=restart, ir_scaled=1)
+    assert iu["status"] == is_["status"] == fs.FS_OK
+    assert (iu["outer"], iu["iters"]) == (is_["outer"], is_["iters"])
+    assert np.array_equal(host(xu), host(xs))
+    rel = np.linalg.norm(b - orc.spmv(A, host(xs))) / np.linalg.norm(b)
+    assert rel <= 1.001e-8
+
+
+@pytest.mark.parametrize("restart", [0, 1])
+def test_scaled_bf16_refinement_converges_when_well_conditioned(fs, orc,
+                                                                restart):
+    """Jacobi-scaled BF16 copy of the shifted elasticity operator (scaled
+    condition number below 8): reaches the FP64 true residual, recomputed
+    by the oracle, and the oracle's FP64 solution within 4e-8 kappa."""
+    from tests.test_oracle import shifted
+    A = shifted(W.tet_p1(6, "elastic", seed=(86, 0), bc="x0",
+                         permute=True), 1.0)
+    b = W.random_vector(A.n_rows, 86, W.BVEC)
+    note("ir scaled bf16 well-conditioned restart=%d" % restart)
+    M = make(A)
+    x, info = fs.cg_solve(M, dev(b), precond=1, precision=fs.PREC_IR_BF16,
+                          inner_rtol=1e-2, ir_restart=restart, ir_scaled=1)
+    assert info["status"] == fs.FS_OK and 2 <= info["outer"] <= 8
+    xg = host(x)
+    rel = np.linalg.norm(b - orc.spmv(A, xg)) / np.linalg.norm(b)
+    assert rel <= 1.001e-8
+    xo, st, _, _ = orc.pcg(A, b, precond=1)
+    kap = np.linalg.cond(A.to_dense())
+    assert np.linalg.norm(xg - xo) <= 4e-8 * kap * np.linalg.norm(xo)
+    # the oracle's scaled refinement converges on the same data too
+    sc, vs = orc.jacobi_scaled_values(A)
+    _, sto, _, _, rro = orc.ir_cg(A, orc.bf16_bits_to_f32(orc.round_bf16(vs)),
+                                  b, precond=0, inner_rtol=1e-2,
+                                  keep=not restart, scale=sc)
+    assert sto == orc.OK and rro <= 1e-8
+
+
+def test_scaled_copy_follows_value_updates(fs, orc):
+    """After csr_update_values the scaled copy is rebuilt: the solve
+    converges on the new matrix (oracle residual of the new values)."""
+    from tests.test_oracle import shifted
+    A = shifted(W.tet_p1(5, "elastic", seed=(38, 0), bc="x0",
+                         permute=True), 1.0)
+    # far from A: refinement with a stale copy of A's scaled values would
+    # over-correct by ~25x and stop without converging
+    B = shifted(W.tet_p1(5, "elastic", seed=(38, 0), bc="x0",
+                         permute=True), 50.0)
+    b = W.random_vector(A.n_rows, 38, W.BVEC)
+    note("ir scaled after value update")
+    M = make(A)
+    fs.cg_solve(M, dev(b), precond=1, precision=fs.PREC_IR_BF16, ir_scaled=1)
+    fs.csr_update_values(M, dev(B.val))
+    x, info = fs.cg_solve(M, dev(b), precond=1, precision=fs.PREC_IR_BF16,
+                          ir_scaled=1)
+    assert info["status"] == fs.FS_OK
+    rel = np.linalg.norm(b - orc.spmv(B, host(x))) / np.linalg.norm(b)
+    assert rel <= 1.001e-8
+
+
+def test_scaled_refinement_needs_a_positive_diagonal(fs, orc):
+    A = exact_stencil(8)
+    N = CSR(A.n_rows, A.n_cols, A.rowptr, A.col, -A.val)
+    note("ir scaled, negative diagonal")
+    M = make(N)
+    with pytest.raises(fs.FsError) as e:
+        fs.cg_solve(M, dev(np.ones(N.n_rows)), precision=fs.PREC_IR_BF16,
+                    ir_scaled=1)
+    assert e.value.status == fs.FS_E_ARG
+    assert "positive diagonal" in str(e.value)
+
+
+# ------------------------------------------------- condition estimate
+@pytest.mark.parametrize("precond", [0, 1])
+def test_condition_estimate_matches_closed_form(fs, orc, precond):
+    """The 5-point stencil on 62 x 62 interior nodes has the eigenvalues
+    4 - 2 cos(i pi / 63) - 2 cos(j pi / 63); with M = I or M = diag(A) = 4 I
+    the condition number is their extreme ratio, 1607.9.  The Lanczos
+    estimate from the CG coefficients of a solve to 1e-8 must find it."""
+    A = exact_stencil(64)
+    t = np.pi / 63
+    lmin = 4 - 4 * np.cos(t)
+    lmax = 4 - 4 * np.cos(62 * t)
+    kap = lmax / lmin
+    assert abs(kap - 1607.9) < 0.1
+    b = W.random_vector(A.n_rows, 39, W.BVEC)
+    note("cg condition estimate precond=%d" % precond)
+    M = make(A)
+    x, info = fs.cg_solve(M, dev(b), precond=precond, estimate_cond=1)
+    assert info["status"] == fs.FS_OK
+    assert abs(info["cond_est"] / kap - 1.0) < 1e-3, (info["cond_est"], kap)
+    # not asked for: 0
+    _, info2 = fs.cg_solve(M, dev(b), precond=precond)
+    assert info2["cond_est"] == 0.0

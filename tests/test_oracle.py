@@ -510,6 +510,68 @@ def test_ir_bf16_converges_when_rounding_times_kappa_is_small(orc, keep):
         np.linalg.norm(xs)
 
 
+@pytest.mark.parametrize("keep", [False, True])
+def test_ir_scaled_with_unit_scale_is_unscaled(orc, keep):
+    """scale = 1 leaves every refinement step unchanged (s r = r and
+    s d = d exactly): bitwise the unscaled result."""
+    A = W.tet_p1(5, "elastic", seed=(88, 0), bc="x0", permute=True)
+    b = W.random_vector(A.n_rows, 88, W.BVEC)
+    a = orc.round_f32(A.val)
+    x0, st0, o0, i0, r0 = orc.ir_cg(A, a, b, inner_rtol=1e-2, keep=keep)
+    x1, st1, o1, i1, r1 = orc.ir_cg(A, a, b, inner_rtol=1e-2, keep=keep,
+                                    scale=np.ones(A.n_rows))
+    assert st0 == st1 == orc.OK
+    assert (o0, i0) == (o1, i1) and np.array_equal(x0, x1)
+
+
+@pytest.mark.parametrize("keep", [False, True])
+def test_ir_scaled_power_of_two_diagonal_is_bitwise_jacobi(orc, keep):
+    """With diag(A) = 4 I (the unjittered 5-point stencil) the scaling is
+    s = 1/2 exactly: S A S = A / 4, and the scaled inner CG (M = I,
+    right-hand side r / 2) runs the unscaled Jacobi CG (M = 4 I) with every
+    quantity multiplied by an exact power of two -- the same alpha and beta,
+    d' = 2 d.  The update x += d' / 2 then gives bitwise the same x, steps
+    and inner iterations.  A misplaced scale (x += d', or s^2) fails."""
+    from workloads.meshes import CSR
+    U = W.poisson_2d_p1(20, jitter=0.0, bc="all")
+    # the assembled stencil carries rounding (4 - 1e-15): take the exact
+    # textbook values 4, -1 (and the structural zeros)
+    A = CSR(U.n_rows, U.n_cols, U.rowptr, U.col, np.round(U.val))
+    assert np.array_equal(np.unique(A.val), [-1.0, 0.0, 4.0])
+    b = W.random_vector(A.n_rows, 89, W.BVEC)
+    sc, vs = orc.jacobi_scaled_values(A)
+    assert np.all(sc == 0.5)
+    for lo in (lambda v: orc.round_f32(v),
+               lambda v: orc.bf16_bits_to_f32(orc.round_bf16(v))):
+        xu, stu, ou, iu, ru = orc.ir_cg(A, lo(A.val), b, precond=1,
+                                        inner_rtol=1e-2, keep=keep)
+        xs, sts, os_, is_, rs = orc.ir_cg(A, lo(vs), b, precond=0,
+                                          inner_rtol=1e-2, keep=keep,
+                                          scale=sc)
+        assert stu == sts == orc.OK and rs <= 1e-8
+        assert (ou, iu) == (os_, is_) and np.array_equal(xu, xs)
+
+
+@pytest.mark.parametrize("keep", [False, True])
+def test_ir_scaled_bf16_converges_when_well_conditioned(orc, keep):
+    """The Jacobi-scaled BF16 copy on the shifted elasticity operator of
+    the test above (scaled condition number below 8): both forms reach the
+    FP64 true residual and the dense solution."""
+    A = shifted(W.tet_p1(6, "elastic", seed=(86, 0), bc="x0",
+                         permute=True), 1.0)
+    b = W.random_vector(A.n_rows, 86, W.BVEC)
+    sc, vs = orc.jacobi_scaled_values(A)
+    a = orc.bf16_bits_to_f32(orc.round_bf16(vs))
+    x, st, outer, inner, rr = orc.ir_cg(A, a, b, precond=0, rtol=1e-8,
+                                        inner_rtol=1e-2, keep=keep,
+                                        scale=sc)
+    assert st == orc.OK and rr <= 1e-8 and 2 <= outer <= 8
+    D = A.to_dense()
+    xs = np.linalg.solve(D, b)
+    assert np.linalg.norm(x - xs) <= 2e-8 * np.linalg.cond(D) * \
+        np.linalg.norm(xs)
+
+
 def test_ir_bf16_exact_values_match_fp32(orc):
     """Where every value is exactly representable in BF16 (the unjittered
     5-point stencil: 4 and -1), the BF16 copy is A itself: both refinement
