@@ -383,6 +383,24 @@ fs_status cg_solve_async(fs_csr_t A, const double *b, double *x,
                          const fs_cg_opts *opts, fs_cg_info *info,
                          hipStream_t s);
 
+/* cg_solve_async for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same stream-ordered solve, same kernels and results
+ * (bitwise those of cg_solve_async on the same arguments), but its
+ * workspace -- 6 n doubles of Krylov vectors, the block partials and the
+ * device result record -- is a fixed device array of the library, sized
+ * for systems of up to 262,144 rows (12.6 MB, held by every GPU the
+ * library runs on until the process ends).  The call allocates nothing:
+ * no hipMalloc, no host or device allocation by the library.  Systems
+ * above 262,144 rows return FS_E_ARG.  All calls on one GPU share that
+ * array (the last call's contents stay in it): calls whose solves overlap
+ * on one GPU -- on different streams, or from different threads without
+ * ordering -- race and must not be made; calls ordered on one stream are
+ * safe.  Arguments, info and errors as cg_solve_async. */
+fs_status cg_solve_async_noalloc(fs_csr_t A, const double *b, double *x,
+                                 const fs_cg_opts *opts, fs_cg_info *info,
+                                 hipStream_t s);
+
 /* k independent solves A X[:, c] = B[:, c], 1 <= k <= 16, advanced
  * together (not in the paper: the multi-right-hand-side part of the
  * batching addition; each column runs the Jacobi-PCG of section

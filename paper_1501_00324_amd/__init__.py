@@ -111,6 +111,7 @@ EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "csr_permute",
            "spmm",
            "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_async",
+           "cg_solve_async_noalloc",
            "cg_solve_multi",
            "cg_solve_batch", "server_opts_default", "server_create",
            "server_submit", "server_poll", "server_stats", "server_destroy",
@@ -166,6 +167,7 @@ def load(build_if_missing=True):
         "cg_opts_default": [P(CgOpts)],
         "cg_solve": [vp, vp, vp, P(CgOpts), P(CgInfo), vp],
         "cg_solve_async": [vp, vp, vp, P(CgOpts), vp, vp],
+        "cg_solve_async_noalloc": [vp, vp, vp, P(CgOpts), vp, vp],
         "cg_solve_multi": [vp, i32, vp, i64, vp, i64, P(CgOpts), P(CgInfo),
                            vp],
         "cg_solve_batch": [i32, vp, vp, vp, vp, P(CgOpts), P(CgInfo), vp],
@@ -544,6 +546,28 @@ def cg_solve_async(A, b, x=None, stream=None, **opts):
                                  C.byref(o), C.c_void_p(buf.data_ptr()),
                                  _stream(stream)))
     return AsyncSolve(x, buf, stream)
+
+
+def cg_solve_async_noalloc(A, b, x, info_buf, stream=None, **opts):
+    """cg_solve_async without allocation: the caller passes x (device) and
+    info_buf (a pinned uint8 host tensor of sizeof(fs_cg_info) bytes); the
+    library uses its fixed device workspace.  Returns an AsyncSolve."""
+    import torch
+    o = cg_opts(**opts)
+    if info_buf.numel() < C.sizeof(CgInfo) or info_buf.is_cuda:
+        raise FsError(FS_E_ARG, "info_buf must be a host buffer of %d bytes"
+                      % C.sizeof(CgInfo))
+    _check(load().cg_solve_async_noalloc(
+        A._h, _ptr(b, torch.float64, A.n_rows, "b"),
+        _ptr(x, torch.float64, A.n_rows, "x"), C.byref(o),
+        C.c_void_p(info_buf.data_ptr()), _stream(stream)))
+    return AsyncSolve(x, info_buf, stream)
+
+
+def info_buffer():
+    """A pinned host buffer for one fs_cg_info record."""
+    import torch
+    return torch.zeros(C.sizeof(CgInfo), dtype=torch.uint8, pin_memory=True)
 
 
 def cg_solve_multi(A, B, X=None, stream=None, check=True, **opts):
