@@ -209,17 +209,34 @@ __global__ __launch_bounds__(kBlock) void k_value_refresh(
     const int g = xcd_remap(blockIdx.x, gridDim.x);
     const Group G = load_group(gbl(groups), g);
     const long base = long(G.base64) * kWave;
-    const long region = long(G.width_lt & 0xffffff) * kWave;
-    for (long t = base + threadIdx.x; t < base + region; t += kBlock) {
-        const int k = __builtin_nontemporal_load(imap + t);
-        const double a = vals[k < 0 ? 0 : k];
-        const double v = k < 0 ? 0.0 : a;
-        // streamed out, so the slot arrays do not evict the rows' values
-        __builtin_nontemporal_store(v, val + t);
-        if (f32 || bf16) {
-            const float f = float(v);
-            if (f32) __builtin_nontemporal_store(f, f32 + t);
-            if (bf16) __builtin_nontemporal_store(f32_to_bf16_rne(f), bf16 + t);
+    const long end = base + long(G.width_lt & 0xffffff) * kWave;
+    // U slots per thread at a time: all their positions are loaded, then
+    // all their values gathered, then all stored, so each thread keeps U
+    // independent gathers in flight instead of one dependent pair
+    constexpr int U = 8;
+    for (long t0 = base + threadIdx.x; t0 < end; t0 += U * kBlock) {
+        int k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long t = t0 + long(u) * kBlock;
+            k[u] = t < end ? __builtin_nontemporal_load(imap + t) : -1;
+        }
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = k[u] < 0 ? 0.0 : vals[k[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long t = t0 + long(u) * kBlock;
+            if (t >= end) continue;
+            const double v = a[u];
+            // streamed out, so the slot arrays do not evict the rows' values
+            __builtin_nontemporal_store(v, val + t);
+            if (f32 || bf16) {
+                const float f = float(v);
+                if (f32) __builtin_nontemporal_store(f, f32 + t);
+                if (bf16)
+                    __builtin_nontemporal_store(f32_to_bf16_rne(f), bf16 + t);
+            }
         }
     }
 }

@@ -234,12 +234,40 @@ __device__ __forceinline__ void store_col_partials(double (&v)[NVPC], int k,
     }
 }
 
+// A slot's (value, column) pair as the wavefront shares it through LDS.
+template <typename ST> struct SlotRec;
+template <> struct SlotRec<double> { double a; int c, pad; };   // 16 bytes
+template <> struct SlotRec<float> { float a; int c; };          // 8 bytes
+
+// The block's broadcast buffers: two per wavefront of V * 64 records (one
+// array per element type and slot width, shared by every caller in a
+// kernel).
+template <typename ST, int V> __device__ __forceinline__ SlotRec<ST> *coop_buffer()
+{
+    __shared__ SlotRec<ST> recs[kWavesPerBlock * 2 * V * kWave];
+    return recs;
+}
+
+// Order this wavefront's LDS writes before its later LDS reads (and its
+// reads before later writes): LDS operations of one wavefront execute in
+// order, so only the compiler has to be kept from moving them.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Multi-column product of one row group with cooperative gathers (KM > 1).
 // Lane L works on column q = L % KM for the slot pairs held by lanes
 // p = r * (64/KM) + L / KM, rounds r = 0..KM-1: the matrix entry (column,
-// value) of lane p is broadcast with cross-lane shuffles and 64/KM rows of
-// X are read per instruction, each a contiguous run of KM values.  (A lane
-// gathering its own row of X would touch 64 cache lines per instruction.)
+// value) of lane p is broadcast -- each lane writes its entries to a
+// per-wavefront LDS buffer once, and every round is one LDS read that the
+// KM lanes of a row share -- and 64/KM rows of X are read per instruction,
+// each a contiguous run of KM values.  (A lane gathering its own row of X
+// would touch 64 cache lines per instruction; broadcasting by cross-lane
+// shuffles costs three permutes per round.)  Two buffers alternate, so the
+// writes for the next slot load never wait for this one's reads.
 // emit(row_in_group, q, value) is called once per (row, column < k).
 template <typename VT, typename ST, int V, int KM, bool N, class Emit>
 __device__ __forceinline__ void coop_group(const Group &g, int lane,
@@ -265,6 +293,9 @@ __device__ __forceinline__ void coop_group(const Group &g, int lane,
     const int qc = qok ? q : 0;
     constexpr int RB = KM < 8 ? KM : 8;      // rounds per batch of gathers
     const int nch = width / V;
+    SlotRec<ST> *const recs = coop_buffer<ST, V>() +
+                              int(threadIdx.x >> 6) * 2 * V * kWave;
+    int buf = 0;
     // with few columns the next chunk's (column, value) loads are issued
     // before this chunk's gathers (k = 2: 23% faster); with 8 or 16 columns
     // the gathers dominate and the extra registers would spill
@@ -294,6 +325,14 @@ __device__ __forceinline__ void coop_group(const Group &g, int lane,
 #pragma unroll
         for (int t = 0; t < V; ++t) cc[t] = cs.get(cv, t);
         unpack<VT, ST, V>(av, aa);
+        SlotRec<ST> *rb = recs + buf * V * kWave;
+        buf ^= 1;
+#pragma unroll
+        for (int t = 0; t < V; ++t) {
+            rb[t * kWave + lane].a = aa[t];
+            rb[t * kWave + lane].c = cc[t];
+        }
+        wave_lds_sync();
 #pragma unroll
         for (int t = 0; t < V; ++t) {
 #pragma unroll
@@ -302,9 +341,9 @@ __device__ __forceinline__ void coop_group(const Group &g, int lane,
                 ST sa[RB], xv[RB];
 #pragma unroll
                 for (int u = 0; u < RB; ++u) {
-                    const int src = (r0 + u) * R + m;
-                    sc[u] = __shfl(cc[t], src, kWave);
-                    sa[u] = __shfl(aa[t], src, kWave);
+                    const SlotRec<ST> &e = rb[t * kWave + (r0 + u) * R + m];
+                    sc[u] = e.c;
+                    sa[u] = e.a;
                 }
 #pragma unroll
                 for (int u = 0; u < RB; ++u)

@@ -198,6 +198,7 @@ struct CgSys {
     double *hist = nullptr;      // coefficient record (2 per iteration)
     int32_t hist_cap = 0;
     bool record = false;         // record the coefficients in this solve
+    bool carved = false;         // parts of a caller-owned block
 };
 
 // A set of systems launched together (same value/vector types and slot
@@ -214,12 +215,27 @@ struct Batch {
     hipGraphExec_t graph = nullptr;
     int32_t graph_iters = 0;
     std::vector<int2> cols;           // (member, column) per finalize block
+    // pinned staging of stream-ordered descriptor uploads, and the event
+    // of the last upload
+    void *h_up = nullptr;
+    size_t up_cap = 0;
+    hipEvent_t up_ev = nullptr;
 };
 
 fs_status sys_alloc(CgSys &S, struct ::fs_csr *A, int32_t k, int32_t vt,
                     int32_t st, int32_t precond);
+// One device block for all of a system's state (sys_alloc_in carves it;
+// the block stays the caller's: sys_free only forgets the parts).
+int64_t sys_block_bytes(const struct ::fs_csr *A, int32_t k, int32_t st,
+                        int32_t precond);
+void sys_alloc_in(CgSys &S, struct ::fs_csr *A, int32_t k, int32_t vt,
+                  int32_t st, int32_t precond, void *block);
 void sys_free(CgSys &S);
 fs_status batch_build(Batch &B, hipStream_t s);   // upload descs and maps
+// async_upload: stream-ordered upload from pinned staging, no host wait
+fs_status batch_build(Batch &B, hipStream_t s, bool async_upload);
+// gather the column states and copy them to h_stage, without waiting
+fs_status batch_stage_states(Batch &B, hipStream_t s);
 void batch_free(Batch &B);
 fs_status batch_iterations(Batch &B, int32_t iters, bool use_graph,
                            hipStream_t s);

@@ -3,13 +3,25 @@
 // Requests (a matrix handle and k right-hand sides) are queued by
 // server_submit and admitted in arrival order while the device-memory
 // budget and the slot count allow.  One worker thread owns the device work:
-// every admitted request becomes a member of one batch that the CG engine
-// advances with shared launches (one batched product and a fixed number of
-// vector / reduction kernels per iteration for all members).  Membership
-// changes only at chunk boundaries (every check_every iterations): finished
-// requests leave, their memory is released, and queued requests join.  A
-// member's arithmetic does not depend on the other members, so every result
-// is bitwise the result of solving that request alone.
+// every admitted request becomes a member of the batch of its launch class
+// (slot width x column-count class), which the CG engine advances with
+// shared launches (one batched product and a fixed number of vector /
+// reduction kernels per iteration for all members).  Membership changes
+// only at chunk boundaries (every check_every iterations): finished
+// requests leave and queued requests join.  A member's arithmetic does not
+// depend on the other members, so every result is bitwise the result of
+// solving that request alone.
+//
+// One step of the worker: the joiners' start (diagonal, first residual) and
+// one chunk of every class are enqueued first -- the classes on separate
+// streams, so their launches overlap on the device -- together with the
+// copy of every class's column states to pinned host memory; then the
+// worker waits once.  Descriptors are uploaded in stream order (no host
+// wait); a class replays a captured graph only once its membership has
+// stayed the same for a step (a graph is not worth capturing for one
+// chunk).  Request state comes from a pool of device blocks kept by the
+// server, so admitting and finishing requests calls neither hipMalloc nor
+// hipFree (which waits for the whole device) once the pool is warm.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -40,7 +52,24 @@ struct Request {
     double t_submit = 0.0, t_admit = 0.0;
     int64_t footprint = 0;         // Krylov state bytes
     CgSys sys;
+    void *block = nullptr;         // pool block holding sys's state
+    int64_t block_bytes = 0;
 };
+
+// Streams the launch classes are spread over (at most the hardware queues
+// of a process).
+constexpr int kServerStreams = 4;
+
+// Pool block size class of a request of `bytes`: rounded up to 1/8 of its
+// power of two (at most 12.5% unused), so blocks are reused across
+// neighbouring sizes.
+int64_t pool_class(int64_t bytes)
+{
+    int64_t p = 256;
+    while (p < bytes) p <<= 1;
+    const int64_t step = std::max<int64_t>(256, p / 8);
+    return (bytes + step - 1) / step * step;
+}
 
 int64_t krylov_bytes(const fs_csr *A, int32_t k, int32_t precond)
 {
@@ -58,7 +87,8 @@ int64_t krylov_bytes(const fs_csr *A, int32_t k, int32_t precond)
 struct fs_server {
     fs_server_opts o{};
     int device = 0;
-    hipStream_t s = nullptr;
+    hipStream_t s = nullptr;                   // streams[0]
+    hipStream_t streams[fs::kServerStreams] = {};
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv;
@@ -74,14 +104,77 @@ struct fs_server {
     int64_t peak_used = 0;
     int32_t peak_active = 0;
     // running members per slot width and column-count class; joiners
-    fs::Batch batch[2 * fs::kKmClasses], check;
+    fs::Batch batch[2 * fs::kKmClasses], join[2 * fs::kKmClasses];
+    int32_t stable[2 * fs::kKmClasses] = {};   // steps without a change
+    // free device blocks by size class (worker thread only)
+    std::multimap<int64_t, void *> pool;
+    int64_t pool_bytes = 0;                    // all blocks, free or in use
     uint64_t submitted = 0, completed = 0;
 };
 
 namespace fs {
 namespace {
 
-fs_status finish(fs_server *S, Request *R, const ColState *cols)
+hipStream_t class_stream(const fs_server *S, int32_t cls)
+{
+    return S->streams[cls % kServerStreams];
+}
+
+int32_t class_of(const Request *R)
+{
+    return (R->A->host.vec - 1) * kKmClasses + km_index(R->k);
+}
+
+// A block of at least `bytes` from the pool (or a new one).
+fs_status pool_get(fs_server *S, int64_t bytes, void **out, int64_t *got)
+{
+    const int64_t c = pool_class(bytes);
+    auto it = S->pool.find(c);
+    if (it != S->pool.end()) {
+        *out = it->second;
+        *got = c;
+        S->pool.erase(it);
+        return FS_OK;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, size_t(c));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // give the free blocks back and try once more
+        for (auto &f : S->pool) {
+            (void)hipFree(f.second);
+            S->pool_bytes -= f.first;
+        }
+        S->pool.clear();
+        e = hipMalloc(&p, size_t(c));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FS_E_OOM, "server state block (%lld bytes): %s",
+                             static_cast<long long>(c), hipGetErrorString(e));
+        }
+    }
+    S->pool_bytes += c;
+    *out = p;
+    *got = c;
+    return FS_OK;
+}
+
+// Return a block; free blocks beyond the budget are released.
+void pool_put(fs_server *S, void *p, int64_t bytes)
+{
+    if (!p) return;
+    S->pool.emplace(bytes, p);
+    while (S->pool_bytes > S->o.hbm_budget_bytes && !S->pool.empty()) {
+        auto it = std::prev(S->pool.end());
+        (void)hipFree(it->second);
+        S->pool_bytes -= it->first;
+        S->pool.erase(it);
+    }
+}
+
+// Enqueue the solution's way out (caller numbering) on the class stream.
+fs_status finish_enqueue(fs_server *S, Request *R, const ColState *cols,
+                         hipStream_t st)
 {
     // a column with b = 0 returns x = 0
     for (int32_t c = 0; c < R->k; ++c)
@@ -89,12 +182,18 @@ fs_status finish(fs_server *S, Request *R, const ColState *cols)
             FS_HIP_TRY(hipMemset2DAsync(static_cast<double *>(R->sys.x) + c,
                                         sizeof(double) * size_t(R->k), 0,
                                         sizeof(double), size_t(R->sys.n),
-                                        S->s));
+                                        st));
     FS_HIP_TRY(permute_rows(R->A->n_rows, R->k,
                             R->A->host.identity ? nullptr : R->A->d_perm,
                             static_cast<const double *>(R->sys.x), R->k, R->X,
-                            R->k, false, S->s));
-    FS_HIP_TRY(hipStreamSynchronize(S->s));
+                            R->k, false, st));
+    (void)S;
+    return FS_OK;
+}
+
+// After the streams have drained: the done record, memory back.
+void finish_complete(fs_server *S, Request *R, const ColState *cols)
+{
     fs_server_done d;
     std::memset(&d, 0, sizeof d);
     d.req_id = R->id;
@@ -117,6 +216,7 @@ fs_status finish(fs_server *S, Request *R, const ColState *cols)
     }
     d.info.ms = d.t_done_ms - d.t_submit_ms;
     sys_free(R->sys);
+    pool_put(S, R->block, R->block_bytes);
     std::lock_guard<std::mutex> lk(S->mu);
     S->used -= R->footprint;
     auto it = S->mat_refs.find(R->A);
@@ -127,6 +227,11 @@ fs_status finish(fs_server *S, Request *R, const ColState *cols)
     S->done.push_back(d);
     S->completed++;
     delete R;
+}
+
+fs_status sync_streams(fs_server *S)
+{
+    for (hipStream_t st : S->streams) FS_HIP_TRY(hipStreamSynchronize(st));
     return FS_OK;
 }
 
@@ -151,123 +256,152 @@ void admit(fs_server *S, std::vector<Request *> &joining)
 
 fs_status step(fs_server *S)
 {
+    constexpr int32_t NC = 2 * kKmClasses;
     std::vector<Request *> joining;
     admit(S, joining);
-    if (!joining.empty()) {
-        Batch &J = S->check;
+    // joiners: state from the pool, b into layout order, x = 0, then their
+    // start (Jacobi diagonal, first residual) per class
+    for (Request *R : joining) {
+        const int64_t need = sys_block_bytes(R->A, R->k, ST_F64, S->o.precond);
+        FS_TRY(pool_get(S, need, &R->block, &R->block_bytes));
+        sys_alloc_in(R->sys, R->A, R->k, VT_F64, ST_F64, S->o.precond,
+                     R->block);
+        R->sys.rtol = S->o.rtol;
+        R->sys.maxit = S->o.maxit;
+        const hipStream_t st = class_stream(S, class_of(R));
+        FS_HIP_TRY(permute_rows(R->A->n_rows, R->k,
+                                R->A->host.identity ? nullptr : R->A->d_perm,
+                                R->B, R->k, static_cast<double *>(R->sys.b),
+                                R->k, true, st));
+        FS_HIP_TRY(fill_f64(int64_t(R->sys.n) * R->k, 0.0,
+                            static_cast<double *>(R->sys.x), st));
+    }
+    bool joined[NC] = {};
+    for (int32_t cls = 0; cls < NC && !joining.empty(); ++cls) {
+        Batch &J = S->join[cls];
         J.members.clear();
+        for (Request *R : joining)
+            if (class_of(R) == cls) J.members.push_back(&R->sys);
+        if (J.members.empty()) continue;
+        joined[cls] = true;
         J.vt = VT_F64;
         J.st = ST_F64;
-        for (Request *R : joining) {
-            FS_TRY(sys_alloc(R->sys, R->A, R->k, VT_F64, ST_F64, S->o.precond));
-            R->sys.rtol = S->o.rtol;
-            R->sys.maxit = S->o.maxit;
-            FS_HIP_TRY(permute_rows(R->A->n_rows, R->k,
-                                    R->A->host.identity ? nullptr
-                                                        : R->A->d_perm,
-                                    R->B, R->k,
-                                    static_cast<double *>(R->sys.b), R->k,
-                                    true, S->s));
-            FS_HIP_TRY(hipMemsetAsync(R->sys.x, 0,
-                                      sizeof(double) * size_t(R->sys.n) * R->k,
-                                      S->s));
-        }
-        // start the joiners (diagonal, initial residual) per launch class
-        for (int32_t cls = 0; cls < 2 * kKmClasses; ++cls) {
-            const int32_t vec = 1 + cls / kKmClasses, kc = cls % kKmClasses;
-            J.members.clear();
-            J.vec = vec;
-            for (Request *R : joining)
-                if (R->A->host.vec == vec && km_index(R->k) == kc)
-                    J.members.push_back(&R->sys);
-            if (J.members.empty()) continue;
-            FS_TRY(batch_build(J, S->s));
-            if (S->o.precond) FS_HIP_TRY(engine_diag_inv(J.L, S->s));
-            FS_HIP_TRY(engine_residual(J.L, 0, true, S->s));
-        }
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            for (Request *R : joining) S->active.push_back(R);
-            S->peak_active = std::max(S->peak_active,
-                                      int32_t(S->active.size()));
-        }
+        J.vec = 1 + cls / kKmClasses;
+        const hipStream_t st = class_stream(S, cls);
+        FS_TRY(batch_build(J, st, true));
+        if (S->o.precond) FS_HIP_TRY(engine_diag_inv(J.L, st));
+        FS_HIP_TRY(engine_residual(J.L, 0, true, st));
     }
-    if (S->active.empty()) return FS_OK;
-    // one batch per slot width and column-count class; members iterate,
-    // then leave when done
-    for (int32_t cls = 0; cls < 2 * kKmClasses; ++cls) {
-        const int32_t vec = 1 + cls / kKmClasses, kc = cls % kKmClasses;
+    if (!joining.empty()) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (Request *R : joining) S->active.push_back(R);
+        S->peak_active = std::max(S->peak_active, int32_t(S->active.size()));
+    }
+    if (S->active.empty()) return sync_streams(S);
+    // members of every class (in admission order)
+    std::vector<Request *> mem[NC];
+    for (Request *R : S->active) mem[class_of(R)].push_back(R);
+    // one chunk of every class, and the copy of its column states
+    for (int32_t cls = 0; cls < NC; ++cls) {
+        if (mem[cls].empty()) continue;
         Batch &B = S->batch[cls];
-        std::vector<Request *> mem;
+        const hipStream_t st = class_stream(S, cls);
         std::vector<CgSys *> syss;
-        for (Request *R : S->active)
-            if (R->A->host.vec == vec && km_index(R->k) == kc) {
-                mem.push_back(R);
-                syss.push_back(&R->sys);
-            }
-        if (mem.empty()) continue;
-        if (syss != B.members || !joining.empty()) {
-            // membership changed: new descriptors (and a new graph)
+        for (Request *R : mem[cls]) syss.push_back(&R->sys);
+        if (syss != B.members || joined[cls]) {
+            // membership changed: new descriptors (the graph goes too)
             B.members = syss;
             B.vt = VT_F64;
             B.st = ST_F64;
-            B.vec = vec;
-            FS_TRY(batch_build(B, S->s));
+            B.vec = 1 + cls / kKmClasses;
+            FS_TRY(batch_build(B, st, true));
+            S->stable[cls] = 0;
+        } else {
+            S->stable[cls]++;
         }
-        FS_TRY(batch_read_states(B, S->s));
-        auto running = [&]() {
-            for (int32_t i = 0; i < B.L.ncols; ++i)
-                if (B.h_stage[i].status == CG_RUNNING) return true;
-            return false;
-        };
-        if (running()) {
-            FS_TRY(batch_iterations(B, S->o.check_every, S->o.use_graph != 0,
-                                    S->s));
-            FS_TRY(batch_read_states(B, S->s));
-        }
+        FS_TRY(batch_iterations(B, S->o.check_every,
+                                S->o.use_graph != 0 && S->stable[cls] > 0,
+                                st));
+        FS_TRY(batch_stage_states(B, st));
+    }
+    FS_TRY(sync_streams(S));
+    // columns whose recurrence residual met the tolerance: confirm against
+    // the true residual (replacing it where it misses)
+    bool any_met = false;
+    for (int32_t cls = 0; cls < NC; ++cls) {
+        if (mem[cls].empty()) continue;
+        Batch &B = S->batch[cls];
         bool met = false;
         for (int32_t i = 0; i < B.L.ncols; ++i)
             met |= B.h_stage[i].status == CG_RECURRENCE_MET;
-        if (met) {
-            FS_HIP_TRY(engine_residual(B.L, 1, false, S->s));
-            FS_TRY(batch_read_states(B, S->s));
+        if (!met) continue;
+        any_met = true;
+        const hipStream_t st = class_stream(S, cls);
+        FS_HIP_TRY(engine_residual(B.L, 1, false, st));
+        FS_TRY(batch_stage_states(B, st));
+    }
+    if (any_met) {
+        FS_TRY(sync_streams(S));
+        for (int32_t cls = 0; cls < NC; ++cls) {
+            if (mem[cls].empty()) continue;
+            Batch &B = S->batch[cls];
             bool pend = false;
             for (int32_t i = 0; i < B.L.ncols; ++i)
                 pend |= B.h_stage[i].pending != 0;
-            if (pend) FS_HIP_TRY(engine_pupdate_pending(B.L, S->s));
-        }
-        // members whose columns have all stopped
-        bool any_fail = false;
-        std::vector<bool> fin(mem.size(), false);
-        int32_t j = 0;
-        for (size_t m = 0; m < mem.size(); ++m) {
-            bool all = true;
-            for (int32_t c = 0; c < mem[m]->k; ++c, ++j) {
-                const int32_t st = B.h_stage[j].status;
-                all &= st != CG_RUNNING;
-                any_fail |= st == CG_MAXIT || st == CG_BREAKDOWN;
-            }
-            fin[m] = all;
-        }
-        if (any_fail) {                  // final true residual for reports
-            FS_HIP_TRY(engine_residual(B.L, 2, false, S->s));
-            FS_TRY(batch_read_states(B, S->s));
-        }
-        std::vector<ColState> cols(B.h_stage, B.h_stage + B.L.ncols);
-        j = 0;
-        for (size_t m = 0; m < mem.size(); ++m) {
-            Request *R = mem[m];
-            const int32_t j0 = j;
-            j += R->k;
-            if (!fin[m]) continue;
-            {
-                std::lock_guard<std::mutex> lk(S->mu);
-                S->active.erase(std::find(S->active.begin(),
-                                          S->active.end(), R));
-            }
-            FS_TRY(finish(S, R, cols.data() + j0));
+            if (pend)
+                FS_HIP_TRY(engine_pupdate_pending(B.L, class_stream(S, cls)));
         }
     }
+    // members whose columns have all stopped
+    bool any_fail = false;
+    std::vector<std::vector<bool>> fin(NC);
+    for (int32_t cls = 0; cls < NC; ++cls) {
+        if (mem[cls].empty()) continue;
+        Batch &B = S->batch[cls];
+        fin[cls].assign(mem[cls].size(), false);
+        int32_t j = 0;
+        bool fail = false;
+        for (size_t m = 0; m < mem[cls].size(); ++m) {
+            bool all = true;
+            for (int32_t c = 0; c < mem[cls][m]->k; ++c, ++j) {
+                const int32_t st = B.h_stage[j].status;
+                all &= st != CG_RUNNING;
+                fail |= st == CG_MAXIT || st == CG_BREAKDOWN;
+            }
+            fin[cls][m] = all;
+        }
+        if (fail) {                    // final true residual for reports
+            FS_HIP_TRY(engine_residual(B.L, 2, false, class_stream(S, cls)));
+            FS_TRY(batch_stage_states(B, class_stream(S, cls)));
+            any_fail = true;
+        }
+    }
+    if (any_fail) FS_TRY(sync_streams(S));
+    // finished requests leave: their solutions out, then one wait
+    std::vector<std::pair<Request *, std::vector<ColState>>> out;
+    for (int32_t cls = 0; cls < NC; ++cls) {
+        if (mem[cls].empty()) continue;
+        Batch &B = S->batch[cls];
+        int32_t j = 0;
+        for (size_t m = 0; m < mem[cls].size(); ++m) {
+            Request *R = mem[cls][m];
+            const int32_t j0 = j;
+            j += R->k;
+            if (!fin[cls][m]) continue;
+            std::vector<ColState> cols(B.h_stage + j0, B.h_stage + j0 + R->k);
+            FS_TRY(finish_enqueue(S, R, cols.data(), class_stream(S, cls)));
+            out.emplace_back(R, std::move(cols));
+        }
+    }
+    if (out.empty()) return FS_OK;
+    FS_TRY(sync_streams(S));
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto &o : out)
+            S->active.erase(std::find(S->active.begin(), S->active.end(),
+                                      o.first));
+    }
+    for (auto &o : out) finish_complete(S, o.first, o.second.data());
     return FS_OK;
 }
 
@@ -334,12 +468,15 @@ fs_status server_create(const fs_server_opts *opts, fs_server_t *out)
     if (!S) return set_error(FS_E_OOM, "host allocation failed");
     S->o = o;
     hipError_t e = hipGetDevice(&S->device);
-    if (e == hipSuccess)
-        e = hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking);
+    for (int i = 0; i < kServerStreams && e == hipSuccess; ++i)
+        e = hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking);
     if (e != hipSuccess) {
+        for (hipStream_t st : S->streams)
+            if (st) (void)hipStreamDestroy(st);
         delete S;
         return set_error(FS_E_HIP, "server stream: %s", hipGetErrorString(e));
     }
+    S->s = S->streams[0];
     S->worker = std::thread(worker_main, S);
     *out = S;
     return FS_OK;
@@ -424,16 +561,19 @@ fs_status server_destroy(fs_server_t S)
     }
     S->cv.notify_all();
     if (S->worker.joinable()) S->worker.join();
+    for (hipStream_t st : S->streams) (void)hipStreamSynchronize(st);
     // requests left behind after a fatal error
     for (Request *R : S->active) {
         sys_free(R->sys);
+        if (R->block) (void)hipFree(R->block);
         delete R;
     }
     for (Request *R : S->queue) delete R;
-    (void)hipStreamSynchronize(S->s);
     for (Batch &B : S->batch) batch_free(B);
-    batch_free(S->check);
-    (void)hipStreamDestroy(S->s);
+    for (Batch &B : S->join) batch_free(B);
+    for (auto &f : S->pool) (void)hipFree(f.second);
+    S->pool.clear();
+    for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
     const fs_status f = S->fatal;
     delete S;
     return f == FS_OK ? FS_OK : set_error(f, "server had stopped on an error");

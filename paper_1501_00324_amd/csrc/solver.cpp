@@ -43,12 +43,78 @@ const void *values_of(const fs_csr *A, int32_t vt)
 // ------------------------------------------------------------- systems
 void sys_free(CgSys &S)
 {
-    dfree(S.x); dfree(S.r); dfree(S.p); dfree(S.q); dfree(S.b);
-    dfree(S.dinv); dfree(S.cs); dfree(S.bad); dfree(S.partials);
+    if (S.carved) {
+        // parts of a block the caller owns: only forget them
+        S.x = S.r = S.p = S.q = S.b = S.dinv = nullptr;
+        S.cs = nullptr;
+        S.bad = nullptr;
+        S.partials = nullptr;
+        S.carved = false;
+    } else {
+        dfree(S.x); dfree(S.r); dfree(S.p); dfree(S.q); dfree(S.b);
+        dfree(S.dinv); dfree(S.cs); dfree(S.bad); dfree(S.partials);
+    }
     dfree(S.hist);
     S.hist_cap = 0;
     S.bytes = 0;
     S.k = 0;
+}
+
+namespace {
+// sizes of the parts of a system's state, in sys_alloc order
+void sys_parts(const fs_csr *A, int32_t k, int32_t st, int32_t precond,
+               size_t (&sz)[9])
+{
+    const size_t n = size_t(A->n_rows);
+    const size_t nk = n * size_t(k) * st_size(st);
+    const size_t nbk = size_t(std::max(engine_spmv_blocks(A->n_groups),
+                                       engine_vec_blocks(A->n_rows)));
+    sz[0] = sz[1] = sz[2] = sz[3] = sz[4] = nk;
+    sz[5] = precond ? n * st_size(st) : 0;
+    sz[6] = sizeof(ColState) * size_t(k);
+    sz[7] = sizeof(int32_t);
+    sz[8] = sizeof(double) * 3 * size_t(k) * nbk;
+}
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+}  // namespace
+
+int64_t sys_block_bytes(const fs_csr *A, int32_t k, int32_t st,
+                        int32_t precond)
+{
+    size_t sz[9];
+    sys_parts(A, k, st, precond, sz);
+    size_t t = 0;
+    for (size_t v : sz) t += align256(v);
+    return int64_t(t);
+}
+
+void sys_alloc_in(CgSys &S, fs_csr *A, int32_t k, int32_t vt, int32_t st,
+                  int32_t precond, void *block)
+{
+    sys_free(S);
+    S.A = A;
+    S.k = k;
+    S.vt = vt;
+    S.st = st;
+    S.precond = precond;
+    S.n = A->n_rows;
+    S.snb = engine_spmv_blocks(A->n_groups);
+    S.vnb = engine_vec_blocks(S.n);
+    size_t sz[9];
+    sys_parts(A, k, st, precond, sz);
+    char *p = static_cast<char *>(block);
+    void *parts[9];
+    for (int i = 0; i < 9; ++i) {
+        parts[i] = sz[i] ? p : nullptr;
+        p += align256(sz[i]);
+    }
+    S.x = parts[0]; S.r = parts[1]; S.p = parts[2]; S.q = parts[3];
+    S.b = parts[4]; S.dinv = parts[5];
+    S.cs = static_cast<ColState *>(parts[6]);
+    S.bad = static_cast<int32_t *>(parts[7]);
+    S.partials = static_cast<double *>(parts[8]);
+    S.bytes = int64_t(p - static_cast<char *>(block));
+    S.carved = true;
 }
 
 fs_status sys_alloc(CgSys &S, fs_csr *A, int32_t k, int32_t vt, int32_t st,
@@ -93,6 +159,12 @@ void batch_free(Batch &B)
     dfree(B.d_stage);
     if (B.h_stage) (void)hipHostFree(B.h_stage);
     B.h_stage = nullptr;
+    if (B.up_ev) (void)hipEventSynchronize(B.up_ev);
+    if (B.h_up) (void)hipHostFree(B.h_up);
+    B.h_up = nullptr;
+    B.up_cap = 0;
+    if (B.up_ev) (void)hipEventDestroy(B.up_ev);
+    B.up_ev = nullptr;
     B.cap_sys = B.cap_s = B.cap_v = B.cap_c = 0;
 }
 
@@ -111,7 +183,9 @@ fs_status ensure_cap(T *&p, int32_t &cap, int32_t want)
 }
 }  // namespace
 
-fs_status batch_build(Batch &B, hipStream_t s)
+fs_status batch_build(Batch &B, hipStream_t s) { return batch_build(B, s, false); }
+
+fs_status batch_build(Batch &B, hipStream_t s, bool async_upload)
 {
     const int32_t m = int32_t(B.members.size());
     std::vector<SysDesc> descs(static_cast<size_t>(m));
@@ -174,16 +248,53 @@ fs_status batch_build(Batch &B, hipStream_t s)
                                  hipHostMallocDefault));
         B.cap_c = cap;
     }
-    // blocking copies: the host vectors are temporaries
-    FS_HIP_TRY(hipStreamSynchronize(s));
-    if (m) FS_HIP_TRY(hipMemcpy(B.d_sys, descs.data(), sizeof(SysDesc) * m,
-                                hipMemcpyHostToDevice));
-    if (sb) FS_HIP_TRY(hipMemcpy(B.d_smap, smap.data(), sizeof(int32_t) * sb,
-                                 hipMemcpyHostToDevice));
-    if (vb) FS_HIP_TRY(hipMemcpy(B.d_vmap, vmap.data(), sizeof(int32_t) * vb,
-                                 hipMemcpyHostToDevice));
-    if (nc) FS_HIP_TRY(hipMemcpy(B.d_cmap, B.cols.data(), sizeof(int2) * nc,
-                                 hipMemcpyHostToDevice));
+    if (async_upload) {
+        // stream-ordered copies from a pinned staging area of the batch:
+        // the staging area is rewritten only once the previous upload has
+        // completed (its event)
+        const size_t bytes = sizeof(SysDesc) * size_t(m) +
+                             sizeof(int32_t) * size_t(sb + vb) +
+                             sizeof(int2) * size_t(nc);
+        if (B.up_ev) FS_HIP_TRY(hipEventSynchronize(B.up_ev));
+        else FS_HIP_TRY(hipEventCreateWithFlags(&B.up_ev,
+                                                hipEventDisableTiming));
+        if (bytes > B.up_cap) {
+            const size_t cap = std::max(bytes, 2 * B.up_cap);
+            if (B.h_up) (void)hipHostFree(B.h_up);
+            B.h_up = nullptr;
+            B.up_cap = 0;
+            FS_HIP_TRY(hipHostMalloc(&B.h_up, cap, hipHostMallocDefault));
+            B.up_cap = cap;
+        }
+        char *h = static_cast<char *>(B.h_up);
+        auto put = [&](void *dst, const void *src, size_t n) -> hipError_t {
+            if (!n) return hipSuccess;
+            std::memcpy(h, src, n);
+            hipError_t e = hipMemcpyAsync(dst, h, n, hipMemcpyHostToDevice, s);
+            h += n;
+            return e;
+        };
+        FS_HIP_TRY(put(B.d_sys, descs.data(), sizeof(SysDesc) * m));
+        FS_HIP_TRY(put(B.d_smap, smap.data(), sizeof(int32_t) * sb));
+        FS_HIP_TRY(put(B.d_vmap, vmap.data(), sizeof(int32_t) * vb));
+        FS_HIP_TRY(put(B.d_cmap, B.cols.data(), sizeof(int2) * nc));
+        FS_HIP_TRY(hipEventRecord(B.up_ev, s));
+    } else {
+        // blocking copies: the host vectors are temporaries
+        FS_HIP_TRY(hipStreamSynchronize(s));
+        if (m) FS_HIP_TRY(hipMemcpy(B.d_sys, descs.data(),
+                                    sizeof(SysDesc) * m,
+                                    hipMemcpyHostToDevice));
+        if (sb) FS_HIP_TRY(hipMemcpy(B.d_smap, smap.data(),
+                                     sizeof(int32_t) * sb,
+                                     hipMemcpyHostToDevice));
+        if (vb) FS_HIP_TRY(hipMemcpy(B.d_vmap, vmap.data(),
+                                     sizeof(int32_t) * vb,
+                                     hipMemcpyHostToDevice));
+        if (nc) FS_HIP_TRY(hipMemcpy(B.d_cmap, B.cols.data(),
+                                     sizeof(int2) * nc,
+                                     hipMemcpyHostToDevice));
+    }
     B.km = km_for(kmax);
     B.L.vt = B.vt;
     B.L.st = B.st;
@@ -238,13 +349,20 @@ fs_status batch_iterations(Batch &B, int32_t iters, bool use_graph,
     return FS_OK;
 }
 
-fs_status batch_read_states(Batch &B, hipStream_t s)
+fs_status batch_stage_states(Batch &B, hipStream_t s)
 {
     if (B.L.ncols == 0) return FS_OK;
     FS_HIP_TRY(engine_gather_states(B.L, B.d_stage, s));
     FS_HIP_TRY(hipMemcpyAsync(B.h_stage, B.d_stage,
                               sizeof(ColState) * size_t(B.L.ncols),
                               hipMemcpyDeviceToHost, s));
+    return FS_OK;
+}
+
+fs_status batch_read_states(Batch &B, hipStream_t s)
+{
+    if (B.L.ncols == 0) return FS_OK;
+    FS_TRY(batch_stage_states(B, s));
     FS_HIP_TRY(hipStreamSynchronize(s));
     return FS_OK;
 }

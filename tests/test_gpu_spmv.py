@@ -102,6 +102,12 @@ def test_empty_and_zero_matrices(fs, orc):
     M = make(Z)
     y = host(fs.spmv(M, dev(np.ones(70))))
     assert not y.any()
+    # a value update of a matrix without entries reads no values (the slot
+    # refresh gathers only for slots that hold an entry)
+    fs.csr_update_values(M, torch.zeros(0, dtype=torch.float64,
+                                        device="cuda"))
+    y = host(fs.spmv(M, dev(np.ones(70))))
+    assert not y.any()
 
 
 def test_padding_never_touches_x(fs, orc):
