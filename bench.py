@@ -815,30 +815,34 @@ def main():
     # CPU oracle on a bounded sample of the headline workload: repeated
     # full products of the same matrix (single thread, then all cores)
     xh = W.random_vector(H.n_cols, 1, W.XVEC)
-    reps, tc = 0, 0.0
-    t0 = time.perf_counter()
-    while tc < args.cpu_seconds:
-        oracle.spmv(H, xh)
-        reps += 1
-        tc = time.perf_counter() - t0
-    cpu_gbs = bytes_alg * reps / tc / 1e9
-    cpu = {"value": round(cpu_gbs, 3), "unit": "GB/s", "cores": 1,
-           "kind": "oracle", "cpu": host_cpu_model(),
-           "sample": "%d full FP64 CSR products of the headline matrix "
-                     "(%d nnz), single thread, %.1f s" % (reps, H.nnz, tc)}
-    log("cpu oracle: %s" % json.dumps(cpu))
-    reps_p, tc_p, used = 0, 0.0, 1
-    t0 = time.perf_counter()
-    while tc_p < max(2.0, args.cpu_seconds / 2):
-        _, used = oracle.spmv_par(H, xh)
-        reps_p += 1
-        tc_p = time.perf_counter() - t0
-    cpu_all = {"value": round(bytes_alg * reps_p / tc_p / 1e9, 3),
-               "unit": "GB/s", "cores": used, "kind": "oracle",
-               "cpu": host_cpu_model(),
-               "sample": "%d full FP64 CSR products of the headline matrix, "
-                         "rows split over %d OpenMP threads" % (reps_p, used)}
-    log("cpu oracle, all cores: %s" % json.dumps(cpu_all))
+    cpu = cpu_all = None
+    if args.cpu_seconds > 0:
+        reps, tc = 0, 0.0
+        t0 = time.perf_counter()
+        while tc < args.cpu_seconds:
+            oracle.spmv(H, xh)
+            reps += 1
+            tc = time.perf_counter() - t0
+        cpu_gbs = bytes_alg * reps / tc / 1e9
+        cpu = {"value": round(cpu_gbs, 3), "unit": "GB/s", "cores": 1,
+               "kind": "oracle", "cpu": host_cpu_model(),
+               "sample": "%d full FP64 CSR products of the headline matrix "
+                         "(%d nnz), single thread, %.1f s" % (reps, H.nnz,
+                                                               tc)}
+        log("cpu oracle: %s" % json.dumps(cpu))
+        reps_p, tc_p, used = 0, 0.0, 1
+        t0 = time.perf_counter()
+        while tc_p < max(2.0, args.cpu_seconds / 2):
+            _, used = oracle.spmv_par(H, xh)
+            reps_p += 1
+            tc_p = time.perf_counter() - t0
+        cpu_all = {"value": round(bytes_alg * reps_p / tc_p / 1e9, 3),
+                   "unit": "GB/s", "cores": used, "kind": "oracle",
+                   "cpu": host_cpu_model(),
+                   "sample": "%d full FP64 CSR products of the headline "
+                             "matrix, rows split over %d OpenMP threads"
+                             % (reps_p, used)}
+        log("cpu oracle, all cores: %s" % json.dumps(cpu_all))
     MH.close()
     del MH, H
     torch.cuda.synchronize()

@@ -374,7 +374,7 @@ fs_status cg_solve(fs_csr_t A, const double *b, double *x,
  * asynchronous copy when s reaches the end of the solve; with pinned memory
  * (hipHostMalloc) the call returns at once, pageable memory makes that copy
  * synchronous.  opts->precision must be FP64 (else FS_E_UNSUPPORTED);
- * use_graph and check_every are ignored.  Uses per-handle workspace (6 n
+ * use_graph and check_every are ignored.  Uses per-handle workspace (7 n
  * doubles, allocated on the first call): calls on one handle must be
  * ordered on one stream.  Returns FS_OK once enqueued, or FS_E_ARG,
  * FS_E_NOT_SQUARE, FS_E_UNSUPPORTED (no cooperative launch), FS_E_OOM,
@@ -387,9 +387,9 @@ fs_status cg_solve_async(fs_csr_t A, const double *b, double *x,
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same stream-ordered solve, same kernels and results
  * (bitwise those of cg_solve_async on the same arguments), but its
- * workspace -- 6 n doubles of Krylov vectors, the block partials and the
+ * workspace -- 7 n doubles of Krylov vectors, the block partials and the
  * device result record -- is a fixed device array of the library, sized
- * for systems of up to 262,144 rows (12.6 MB, held by every GPU the
+ * for systems of up to 262,144 rows (14.7 MB, held by every GPU the
  * library runs on until the process ends).  The call allocates nothing:
  * no hipMalloc, no host or device allocation by the library.  Systems
  * above 262,144 rows return FS_E_ARG.  All calls on one GPU share that

@@ -243,7 +243,7 @@ fs_status batch_read_states(Batch &B, hipStream_t s);  // -> h_stage
 void free_solver_state(struct ::fs_csr *A);
 // Stream-ordered solve (cg_solve_async and its no-allocation variant):
 // argument checks (o receives the normalised options), then the enqueue
-// with workspace ws (6 n doubles), part (kPersistPartials doubles) and the
+// with workspace ws (7 n doubles), part (kPersistPartials doubles) and the
 // device result dinfo, copied to the host record info on s.
 fs_status async_check(struct ::fs_csr *A, const double *b, double *x,
                       const fs_cg_opts *opts, fs_cg_info *info,
@@ -347,12 +347,14 @@ hipError_t launch_spmv_batch(int32_t m, const fs_csr *const *A,
 // FP64, layout numbering): grid size for the handle, and the launch.  info
 // is a device struct written at the end.
 constexpr int kPersistMaxBlocks = 1024;
-// block partials of the persistent kernel: two regions of 3 per block
-constexpr int kPersistPartials = 2 * 3 * kPersistMaxBlocks;
+// block partials of the persistent kernel (two regions of 3 per block),
+// then its grid barrier counter (at double index kPersistBarrierAt)
+constexpr int kPersistBarrierAt = 2 * 3 * kPersistMaxBlocks;
+constexpr int kPersistPartials = kPersistBarrierAt + 32;
 int32_t persistent_blocks(const fs_csr *A);
 hipError_t launch_cg_persistent(const fs_csr *A, int32_t nblocks,
                                 const double *b, double *x, double *r,
-                                double *p, double *q, double *dinv,
+                                double *p, double *q, double *z, double *dinv,
                                 double *part, fs_cg_info *info, double rtol,
                                 int32_t maxit, bool x_zero, hipStream_t s);
 // Plain CSR product (no layout), lanes per row from the mean row length.

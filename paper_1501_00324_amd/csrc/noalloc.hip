@@ -18,13 +18,13 @@ namespace fs {
 namespace {
 
 constexpr int64_t kNoAllocMaxRows = int64_t(1) << 18;   // 262,144 rows
-// doubles: 6 vectors of the largest system, the block partials, and the
-// result record rounded up to whole doubles
+// doubles: 7 vectors of the largest system, the block partials and the
+// barrier counter, and the result record rounded up to whole doubles
 constexpr int64_t kInfoDoubles =
     (int64_t(sizeof(fs_cg_info)) + int64_t(sizeof(double)) - 1) /
     int64_t(sizeof(double));
 constexpr int64_t kScratchDoubles =
-    6 * kNoAllocMaxRows + kPersistPartials + kInfoDoubles;
+    7 * kNoAllocMaxRows + kPersistPartials + kInfoDoubles;
 
 static __device__ __align__(256) double scratch[kScratchDoubles];
 
@@ -74,8 +74,8 @@ extern "C" fs_status cg_solve_async_noalloc(fs_csr_t A, const double *b,
     DeviceGuard g(A->device);
     double *base = nullptr;
     FS_TRY(scratch_address(A->device, &base));
-    double *ws = base;                         // 6 n doubles
-    double *part = base + 6 * kNoAllocMaxRows; // kPersistPartials doubles
+    double *ws = base;                         // 7 n doubles
+    double *part = base + 7 * kNoAllocMaxRows; // kPersistPartials doubles
     fs_cg_info *dinfo =
         reinterpret_cast<fs_cg_info *>(part + kPersistPartials);
     return async_enqueue(A, b, x, o, ws, part, dinfo, info, s);

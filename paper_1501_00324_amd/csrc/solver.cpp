@@ -997,14 +997,14 @@ fs_status async_enqueue(fs_csr *A, const double *b, double *x,
 {
     const int64_t n = A->n_rows;
     double *B = ws, *X = B + n, *R = X + n, *P = R + n, *Q = P + n,
-           *Dv = Q + n;
+           *Dv = Q + n, *Z = Dv + n;
     FS_TRY(load_block(A, 1, b, 1, B, s));
     if (o.x0_zero)
         FS_HIP_TRY(fill_f64(n, 0.0, X, s));
     else
         FS_TRY(load_block(A, 1, x, 1, X, s));
     FS_HIP_TRY(launch_cg_persistent(A, persistent_blocks(A), B, X, R, P, Q,
-                                    o.precond ? Dv : nullptr, part, dinfo,
+                                    Z, o.precond ? Dv : nullptr, part, dinfo,
                                     o.rtol, o.maxit, o.x0_zero != 0, s));
     FS_TRY(store_block(A, 1, X, x, 1, s));
     FS_HIP_TRY(hipMemcpyAsync(info, dinfo, sizeof(fs_cg_info),
@@ -1030,7 +1030,7 @@ extern "C" fs_status cg_solve_async(fs_csr_t A, const double *b, double *x,
         // first use: workspace of the handle (allocation synchronises)
         int64_t acct = 0;
         FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_async),
-                       sizeof(double) * size_t(6 * n), acct));
+                       sizeof(double) * size_t(7 * n), acct));
         FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_apart),
                        sizeof(double) * kPersistPartials, acct));
         FS_TRY(dmalloc(reinterpret_cast<void **>(&A->d_ainfo),
