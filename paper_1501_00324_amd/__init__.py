@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys as _sys
 
 from . import _build
 
@@ -229,13 +230,14 @@ def _ptr(t, dtype=None, n=None, name="tensor"):
     return t.data_ptr() if t.numel() else None
 
 
-def _finalize(close):
+def _finalize(close, _is_finalizing=_sys.is_finalizing):
     """Release a handle from a finalizer.  While the interpreter shuts down
     the HIP runtime (and any tool attached to it) may already be gone, so
     nothing is released then: the process exit returns the memory.  Owners
-    that want a clean teardown call close() themselves."""
-    import sys
-    if sys.is_finalizing():
+    that want a clean teardown call close() themselves.  (Everything used
+    here is bound when the module loads: module globals may already be
+    cleared when a finalizer runs at shutdown.)"""
+    if _is_finalizing():
         return
     try:
         close()
@@ -250,8 +252,8 @@ class Matrix:
         self.handle = handle
         self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, nnz
 
-    def __del__(self):
-        _finalize(self.close)
+    def __del__(self, _fin=_finalize):
+        _fin(self.close)
 
     def close(self):
         if self.handle:
@@ -730,8 +732,8 @@ class Server:
             self.keep.clear()
             _check(st)
 
-    def __del__(self):
-        _finalize(self.close)
+    def __del__(self, _fin=_finalize):
+        _fin(self.close)
 
 
 class Assembly:
@@ -741,8 +743,8 @@ class Assembly:
         self.handle, self.A = handle, A
         self.n_elem, self.nde = n_elem, nde
 
-    def __del__(self):
-        _finalize(self.close)
+    def __del__(self, _fin=_finalize):
+        _fin(self.close)
 
     def close(self):
         if self.handle:

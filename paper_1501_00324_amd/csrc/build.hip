@@ -212,8 +212,10 @@ __global__ __launch_bounds__(kBlock) void k_value_refresh(
     const long end = base + long(G.width_lt & 0xffffff) * kWave;
     // U slots per thread at a time: all their positions are loaded, then
     // all their values gathered, then all stored, so each thread keeps U
-    // independent gathers in flight instead of one dependent pair
-    constexpr int U = 8;
+    // independent gathers in flight instead of one dependent pair (config
+    // 1: U = 4 / 8 / 16 take 195 / 178 / 160 us; with 16 a whole row group
+    // of up to 4096 slots is one batch)
+    constexpr int U = 16;
     for (long t0 = base + threadIdx.x; t0 < end; t0 += U * kBlock) {
         int k[U];
 #pragma unroll
