@@ -393,6 +393,145 @@ __device__ __forceinline__ void coop_group(const Group &g, int lane,
     }
 }
 
+// coop_group with two adjacent columns per lane: KM/2 lanes per gathered
+// row, 128/KM rows per round, KM/2 rounds per slot, and 16-byte X loads.
+// The texture address unit processes a gather instruction at a fixed rate of
+// lanes per cycle whatever each lane loads, and the KM = 16 product is bound
+// by it (counters: address unit busy 88% of the kernel); two columns per
+// lane halve its gather instructions.  Every (row, column) sum is formed
+// exactly as in coop_group (each slot lane's entries in order, then the same
+// tree over a row's lanes), and the values are handed to the lanes that
+// emit them in coop_group, so stores and p.q partials are bitwise
+// coop_group's.  Needs k even (16-byte aligned X rows); used for KM >= 8
+// (with fewer columns coop_group's early loads of the next slot win).
+template <typename VT, int V, int KM, bool N, class Emit>
+__device__ __forceinline__ void coop_group_pair(const Group &g, int lane,
+                                                gptr<VT> val, gptr<void> col,
+                                                int gb, gptr<double> X, int k,
+                                                long ldx, Emit emit)
+{
+    static_assert(KM >= 4, "pairs need at least four columns");
+    typedef typename Pack<VT, V>::T PV;
+    typedef ColStream<V, N> CS;
+    constexpr int H = KM / 2;
+    constexpr int R = kWave / H;
+    const int h = lane % H, m = lane / H;
+    const int width = g.width_lt & 0xffffff;
+    const long base = long(g.base64) * kWave;
+    gptr<PV> pv = reinterpret_cast<gptr<PV>>(val + base) + lane;
+    const CS cs(col, base, lane, gb);
+    double acc0[H], acc1[H];
+#pragma unroll
+    for (int r = 0; r < H; ++r) acc0[r] = acc1[r] = 0.0;
+    const bool hok = 2 * h < k;
+    const int hc = hok ? 2 * h : 0;
+    constexpr int RB = H < 8 ? H : 8;
+    const int nch = width / V;
+    SlotRec<double> *const recs = coop_buffer<double, V>() +
+                                  int(threadIdx.x >> 6) * 2 * V * kWave;
+    int buf = 0;
+    for (int j = 0; j < nch; ++j) {
+        int cc[V];
+        double aa[V];
+        const typename CS::P cv = cs.load(j);
+        const PV av = __builtin_nontemporal_load(pv + j * kWave);
+#pragma unroll
+        for (int t = 0; t < V; ++t) cc[t] = cs.get(cv, t);
+        unpack<VT, double, V>(av, aa);
+        SlotRec<double> *rb = recs + buf * V * kWave;
+        buf ^= 1;
+#pragma unroll
+        for (int t = 0; t < V; ++t) {
+            rb[t * kWave + lane].a = aa[t];
+            rb[t * kWave + lane].c = cc[t];
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int t = 0; t < V; ++t) {
+#pragma unroll
+            for (int r0 = 0; r0 < H; r0 += RB) {
+                int sc[RB];
+                double sa[RB];
+                dv2 xv[RB];
+#pragma unroll
+                for (int u = 0; u < RB; ++u) {
+                    const SlotRec<double> &e = rb[t * kWave + (r0 + u) * R + m];
+                    sc[u] = e.c;
+                    sa[u] = e.a;
+                }
+#pragma unroll
+                for (int u = 0; u < RB; ++u)
+                    xv[u] = *reinterpret_cast<gptr<dv2>>(
+                        X + long(sc[u] < 0 ? 0 : sc[u]) * ldx + hc);
+#pragma unroll
+                for (int u = 0; u < RB; ++u) {
+                    const bool ok = hok && sc[u] >= 0;
+                    acc0[r0 + u] = fma(sa[u], ok ? xv[u].x : 0.0, acc0[r0 + u]);
+                    acc1[r0 + u] = fma(sa[u], ok ? xv[u].y : 0.0, acc1[r0 + u]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    const int lt = g.width_lt >> 24, T = 1 << lt;
+    // the tree over a row's lanes, as in coop_group
+    if (T <= R) {
+#pragma unroll
+        for (int r = 0; r < H; ++r)
+            for (int o = H; o < H * T; o <<= 1) {
+                acc0[r] += __shfl_xor(acc0[r], o, kWave);
+                acc1[r] += __shfl_xor(acc1[r], o, kWave);
+            }
+    } else {
+        const int rounds = T / R;
+#pragma unroll
+        for (int r = 0; r < H; ++r)
+#pragma unroll
+            for (int o = H; o < kWave; o <<= 1) {
+                acc0[r] += __shfl_xor(acc0[r], o, kWave);
+                acc1[r] += __shfl_xor(acc1[r], o, kWave);
+            }
+#pragma unroll
+        for (int s = 1; s < H; s <<= 1)
+            if (s < rounds) {
+#pragma unroll
+                for (int r = 0; r + s < H; r += 2 * s) {
+                    acc0[r] += acc0[r + s];
+                    acc1[r] += acc1[r + s];
+                }
+            }
+    }
+    // hand every row's value to the lane that emits it in coop_group (lane
+    // q + KM mo, round r holds rows r * RO + mo), so the stores and the
+    // order of the p.q partials are exactly coop_group's: the value of
+    // round r sits in round r / 2 here, in lane ((r % 2) RO + mo) H + q / 2
+    constexpr int RO = kWave / KM;
+    const int q = lane % KM, mo = lane / KM;
+    double fin[KM];
+#pragma unroll
+    for (int r = 0; r < KM; ++r) {
+        const int src = ((r & 1) * RO + mo) * H + (q >> 1);
+        const double v0 = __shfl(acc0[r >> 1], src, kWave);
+        const double v1 = __shfl(acc1[r >> 1], src, kWave);
+        fin[r] = (q & 1) ? v1 : v0;
+    }
+    if (T <= RO) {
+#pragma unroll
+        for (int r = 0; r < KM; ++r) {
+            const int rg = (r * RO + mo) >> lt;
+            if ((mo & (T - 1)) == 0 && rg < g.nrows && q < k) emit(rg, q, fin[r]);
+        }
+    } else {
+        const int rounds = T / RO;
+#pragma unroll
+        for (int r = 0; r < KM; ++r) {
+            const int rg = (r * RO) >> lt;
+            if (r % rounds == 0 && mo == 0 && rg < g.nrows && q < k)
+                emit(rg, q, fin[r]);
+        }
+    }
+}
+
 // Occupancy floor (waves per SIMD) of the products in the CG iteration:
 // the gathers are latency bound; KM = 1 holds 7 waves (at 8 the FP64
 // product spills a register and the solve slows by 13%), KM = 8 and 16
@@ -440,13 +579,24 @@ __global__ __launch_bounds__(kBlock, spmm_dot_min_waves(KM, int(sizeof(ST)))) vo
                     dot[0] += double(pr) * double(v);
                 }
             } else {
-                coop_group<VT, ST, V, KM, N>(
-                    gd, lane, val, cst, gb, P, k, k,
-                    [&](int rg, int q, ST v) {
-                        const long e = long(gd.row0 + rg) * k + q;
-                        Q[e] = v;
-                        dot[0] += double(P[e]) * double(v);
-                    });
+                auto emit = [&](int rg, int q, ST v) {
+                    const long e = long(gd.row0 + rg) * k + q;
+                    Q[e] = v;
+                    dot[0] += double(P[e]) * double(v);
+                };
+                // engine vectors are n x k with rows of k values: 16-byte
+                // aligned when k is even
+                if constexpr (KM >= 8 && std::is_same<ST, double>::value) {
+                    if ((k & 1) == 0)
+                        coop_group_pair<VT, V, KM, N>(gd, lane, val, cst, gb,
+                                                      P, k, k, emit);
+                    else
+                        coop_group<VT, ST, V, KM, N>(gd, lane, val, cst, gb,
+                                                     P, k, k, emit);
+                } else {
+                    coop_group<VT, ST, V, KM, N>(gd, lane, val, cst, gb, P, k,
+                                                 k, emit);
+                }
             }
         }
     });
