@@ -116,6 +116,8 @@ def bench_small_batch(fs, W, oracle, d, torch, m=64):
     worst = max(float(np.linalg.norm(bs[i].cpu().numpy() - oracle.spmv(
         mats[i], xsb[i].reshape(-1).cpu().numpy())) /
         np.linalg.norm(bs[i].cpu().numpy())) for i in range(m))
+    for M in Ms:
+        M.close()
     return {"systems": m, "rows_each": mats[0].n_rows,
             "one_at_a_time_solves_per_s": m / t_one,
             "batched_solves_per_s": m / t_b,
@@ -237,6 +239,8 @@ def bench_serving(fs, W, oracle, d, torch, n_req=32, lam_factors=(1, 2, 4)):
                 Bh[:, c] - oracle.spmv(pool[mi], Xh[:, c].copy())) /
                 np.linalg.norm(Bh[:, c])))
     out["relres_oracle_worst"] = worst
+    for M in Ms:
+        M.close()
     return out
 
 
@@ -420,6 +424,8 @@ def bench_spmv_batch(fs, W, oracle, d, torch, stream, m=64):
     ok = all(np.all(np.abs(y.cpu().numpy() - oracle.spmv(A, x.cpu().numpy()))
                     <= 1e-12 * oracle.spmv_abs(A, x.cpu().numpy()))
              for A, x, y in zip(mats, xs, ys))
+    for M in Ms:
+        M.close()
     return {"products": m, "rows_each": mats[0].n_rows,
             "one_at_a_time_us_per_product": t_one / m,
             "batched_us_per_product": t_bat / m,
@@ -462,6 +468,7 @@ def bench_newton(fs, oracle, torch, A, d, stream, steps=4):
     B = CSR(A.n_rows, A.n_cols, A.rowptr, A.col, Ah_vals)
     rel = float(np.linalg.norm(b - oracle.spmv(B, x.cpu().numpy())) /
                 np.linalg.norm(b))
+    M.close()
     return {"steps": out, "relres_oracle_last": rel,
             "refresh_gbs": (20.0 * A.nnz) / (out[-1]["refresh_us"] * 1e-6)
             / 1e9}
@@ -541,7 +548,7 @@ def bench_assembly(fs, oracle, torch, A, d, stream, steps=20):
                 3, stream)
             out["parity_bitwise_all_loads"] = bool(np.array_equal(
                 r.cpu().numpy().view(np.int64), rwant.view(np.int64)))
-        del P
+        P.close()
     va = d(A.val)
     out["reorder_avoided_us"] = back_to_back_us(
         torch, lambda: fs.csr_update_values(M, va, stream), 10, 2, stream)
@@ -566,6 +573,8 @@ def bench_assembly(fs, oracle, torch, A, d, stream, steps=20):
                           "solve_ms": (t2 - t1) * 1e3, "iters": ci["iters"],
                           "status": ci["status"], "relres_oracle": rel,
                           "assembly_share": (t1 - t0) / (t2 - t0)}
+    P.close()
+    M.close()
     return out
 
 
