@@ -22,6 +22,7 @@ void free_handle(fs_csr *A)
     free_solver_state(A);
     dfree(A->d_groups); dfree(A->d_val); dfree(A->d_val_f32);
     dfree(A->d_val_bf16); dfree(A->d_col); dfree(A->d_map); dfree(A->d_imap);
+    dfree(A->d_jpos); dfree(A->d_rstart);
     dfree(A->d_col16); dfree(A->d_gbase);
     dfree(A->d_perm); dfree(A->d_iperm); dfree(A->d_xtmp); dfree(A->d_Xtmp);
 }
@@ -86,6 +87,26 @@ fs_status cg_opts_default(fs_cg_opts *o)
 
 namespace fs {
 namespace {
+
+// Row starts and byte-wide in-row positions of the slots (the value
+// refresh reads one byte per slot instead of the 4-byte inverse map), for
+// matrices whose rows hold at most 255 entries and whose positions fit 32
+// bits; otherwise the refresh keeps the inverse map.  After the inverse map
+// is built, on the same stream.
+fs_status build_refresh_rows(fs_csr *A, const int32_t *h_rp, int64_t &acct,
+                             hipStream_t s)
+{
+    if (A->slots == 0 || A->nnz > INT32_MAX) return FS_OK;
+    int32_t maxlen = 0;
+    for (int32_t i = 0; i < A->n_rows; ++i)
+        maxlen = std::max(maxlen, h_rp[size_t(i) + 1] - h_rp[size_t(i)]);
+    if (maxlen > 255) return FS_OK;
+    FS_TRY(dalloc(&A->d_jpos, A->slots, acct));
+    FS_TRY(dalloc(&A->d_rstart, A->n_rows, acct));
+    FS_HIP_TRY(launch_refresh_rows(A->d_groups, A->n_groups, A->host.vec,
+                                   A->d_imap, A->d_jpos, A->d_rstart, s));
+    return FS_OK;
+}
 
 // Device handle from host structure arrays (layout built here) and device
 // values.  Synchronises s.
@@ -173,6 +194,7 @@ fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
         FS_CREATE_HIP(hipMemsetAsync(A->d_imap, 0xff,
                                      sizeof(int32_t) * size_t(A->slots), s));
     FS_CREATE_HIP(launch_inverse_map(A->d_map, nnz, A->d_imap, s));
+    if ((st = build_refresh_rows(A, h_rp, acct, s))) return fail(st);
     if (n_rows) {
         FS_CREATE_HIP(hipMemcpyAsync(A->d_perm, L.perm.data(),
                                      sizeof(int32_t) * size_t(n_rows),
@@ -404,6 +426,7 @@ fs_status create_on_device(int32_t n_rows, int32_t n_cols, int64_t nnz,
         FS_DEV_HIP(hipMemsetAsync(A->d_imap, 0xff,
                                   sizeof(int32_t) * size_t(A->slots), s));
     FS_DEV_HIP(launch_inverse_map(A->d_map, nnz, A->d_imap, s));
+    if ((st = build_refresh_rows(A, h_rp.data(), acct, s))) return fail(st);
     FS_DEV_HIP(launch_value_scatter(vals, A->d_map, nnz, A->d_val,
                                     A->d_val_f32, A->d_val_bf16, s));
     FS_DEV_HIP(hipStreamSynchronize(s));
@@ -657,9 +680,14 @@ fs_status csr_update_values(fs_csr_t A, const double *vals, hipStream_t s)
     FS_TRY(check_handle(A));
     if (!vals && A->nnz > 0) return set_error(FS_E_ARG, "NULL values");
     DeviceGuard g(A->device);
-    FS_HIP_TRY(launch_value_refresh(A->d_groups, A->n_groups, A->d_imap,
-                                    vals, A->d_val, A->d_val_f32,
-                                    A->d_val_bf16, s));
+    if (A->d_jpos)
+        FS_HIP_TRY(launch_value_refresh_rows(
+            A->d_groups, A->n_groups, A->host.vec, A->d_jpos, A->d_rstart,
+            vals, A->d_val, A->d_val_f32, A->d_val_bf16, s));
+    else
+        FS_HIP_TRY(launch_value_refresh(A->d_groups, A->n_groups, A->d_imap,
+                                        vals, A->d_val, A->d_val_f32,
+                                        A->d_val_bf16, s));
     A->lo_scaled_dt = 0;   // the scaled copy is rebuilt by the next solve
     return FS_OK;
 }

@@ -243,6 +243,85 @@ __global__ __launch_bounds__(kBlock) void k_value_refresh(
     }
 }
 
+// Row starts and byte-wide positions for the refresh (one wavefront per row
+// group): a row's entries fill exactly its lanes' non-padding slots, so
+// the smallest CSR position among them is the row's start, and every slot
+// stores its entry's offset from that start.  Rows hold at most 255
+// entries (checked by the caller); 255 marks padding.
+__global__ __launch_bounds__(kBlock) void k_refresh_rows(
+    const Group *__restrict__ groups, int ngroups, int vec,
+    const int *__restrict__ imap, uint8_t *__restrict__ jpos,
+    int *__restrict__ rstart)
+{
+    const int g = int(blockIdx.x) * kWavesPerBlock + int(threadIdx.x >> 6);
+    if (g >= ngroups) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const Group G = load_group(gbl(groups), g);
+    const long base = long(G.base64) * kWave;
+    const int nch = (G.width_lt & 0xffffff) / vec, lt = G.width_lt >> 24;
+    int mn = 0x7fffffff;
+    for (int j = 0; j < nch; ++j)
+        for (int t = 0; t < vec; ++t) {
+            const int k = imap[base + (long(j) * kWave + lane) * vec + t];
+            if (k >= 0 && k < mn) mn = k;
+        }
+    for (int o = 1; o < (1 << lt); o <<= 1)
+        mn = min(mn, __shfl_xor(mn, o, kWave));
+    const int r = lane >> lt;
+    if ((lane & ((1 << lt) - 1)) == 0 && r < G.nrows)
+        rstart[G.row0 + r] = mn == 0x7fffffff ? 0 : mn;
+    for (int j = 0; j < nch; ++j)
+        for (int t = 0; t < vec; ++t) {
+            const long i = base + (long(j) * kWave + lane) * vec + t;
+            const int k = imap[i];
+            jpos[i] = k < 0 ? uint8_t(255) : uint8_t(k - mn);
+        }
+}
+
+// The refresh through row starts: the map read is one byte per slot
+// instead of four.  Thread x of a group's workgroup takes the group's slots
+// x, x + 256, ... -- always the same lane (256 is a multiple of 64 vec
+// slots), so one row and one row start per thread.
+__global__ __launch_bounds__(kBlock) void k_value_refresh_rows(
+    const Group *__restrict__ groups, int vec,
+    const uint8_t *__restrict__ jpos, const int *__restrict__ rstart,
+    const double *__restrict__ vals, double *__restrict__ val,
+    float *__restrict__ f32, uint16_t *__restrict__ bf16)
+{
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    const Group G = load_group(gbl(groups), g);
+    const long base = long(G.base64) * kWave;
+    const long end = base + long(G.width_lt & 0xffffff) * kWave;
+    const int lt = G.width_lt >> 24;
+    const int r = ((int(threadIdx.x) / vec) & (kWave - 1)) >> lt;
+    const long rs = r < G.nrows ? long(rstart[G.row0 + r]) : 0;
+    constexpr int U = 16;
+    for (long t0 = base + threadIdx.x; t0 < end; t0 += U * kBlock) {
+        int jp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long t = t0 + long(u) * kBlock;
+            jp[u] = t < end ? int(__builtin_nontemporal_load(jpos + t)) : 255;
+        }
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = jp[u] == 255 ? 0.0 : vals[rs + jp[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long t = t0 + long(u) * kBlock;
+            if (t >= end) continue;
+            const double v = a[u];
+            __builtin_nontemporal_store(v, val + t);
+            if (f32 || bf16) {
+                const float f = float(v);
+                if (f32) __builtin_nontemporal_store(f, f32 + t);
+                if (bf16)
+                    __builtin_nontemporal_store(f32_to_bf16_rne(f), bf16 + t);
+            }
+        }
+    }
+}
+
 int wave_grid(long waves)
 {
     const long b = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -269,6 +348,30 @@ hipError_t launch_value_refresh(const Group *groups, int32_t ngroups,
     if (ngroups == 0) return hipSuccess;
     hipLaunchKernelGGL(k_value_refresh, dim3(ngroups), dim3(kBlock), 0, s,
                        groups, imap, vals, val, f32, bf16);
+    return hipGetLastError();
+}
+
+hipError_t launch_refresh_rows(const Group *groups, int32_t ngroups,
+                               int32_t vec, const int32_t *imap,
+                               uint8_t *jpos, int32_t *rstart, hipStream_t s)
+{
+    if (ngroups == 0) return hipSuccess;
+    const int b = (ngroups + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(k_refresh_rows, dim3(b), dim3(kBlock), 0, s, groups,
+                       ngroups, vec, imap, jpos, rstart);
+    return hipGetLastError();
+}
+
+hipError_t launch_value_refresh_rows(const Group *groups, int32_t ngroups,
+                                     int32_t vec, const uint8_t *jpos,
+                                     const int32_t *rstart,
+                                     const double *vals, double *val,
+                                     float *f32, uint16_t *bf16,
+                                     hipStream_t s)
+{
+    if (ngroups == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_value_refresh_rows, dim3(ngroups), dim3(kBlock), 0,
+                       s, groups, vec, jpos, rstart, vals, val, f32, bf16);
     return hipGetLastError();
 }
 

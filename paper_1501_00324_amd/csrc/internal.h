@@ -270,6 +270,11 @@ struct fs_csr {
     int32_t *d_gbase = nullptr;    // per-group column base for d_col16
     int32_t *d_map = nullptr;
     int32_t *d_imap = nullptr;     // slot -> CSR position, -1 = padding
+    // per-Newton-step refresh through row starts (rows of <= 255 entries):
+    // d_rstart[row] = CSR position of the row's first entry, d_jpos[slot] =
+    // position within the row, 255 = padding; NULL: refresh through d_imap
+    uint8_t *d_jpos = nullptr;
+    int32_t *d_rstart = nullptr;
     int32_t *d_perm = nullptr;
     int32_t *d_iperm = nullptr;
     double *d_xtmp = nullptr;      // gathered x for caller-numbering spmv
@@ -312,6 +317,17 @@ hipError_t launch_value_refresh(const Group *groups, int32_t ngroups,
                                 const int32_t *imap, const double *vals,
                                 double *val, float *f32, uint16_t *bf16,
                                 hipStream_t s);
+// d_jpos / d_rstart from the inverse map (one wavefront per row group)
+hipError_t launch_refresh_rows(const Group *groups, int32_t ngroups,
+                               int32_t vec, const int32_t *imap,
+                               uint8_t *jpos, int32_t *rstart, hipStream_t s);
+// the refresh through them
+hipError_t launch_value_refresh_rows(const Group *groups, int32_t ngroups,
+                                     int32_t vec, const uint8_t *jpos,
+                                     const int32_t *rstart,
+                                     const double *vals, double *val,
+                                     float *f32, uint16_t *bf16,
+                                     hipStream_t s);
 hipError_t launch_check_cols(const int32_t *col, int64_t nnz, int32_t n_cols,
                              unsigned long long *first, hipStream_t s);
 hipError_t launch_band(int32_t n, const int32_t *rowptr, const int32_t *col,

@@ -203,14 +203,35 @@ def test_get_layout_rejects_offsets_of_32bit_layout(fs, orc):
                           np.sort(np.nonzero(lay["slot_col"] >= 0)[0]))
 
 
-@pytest.mark.parametrize("name", ["cfg0", "ragged", "ragged_rect"])
+def rows_of_lengths(lens, n_cols, seed):
+    """Rows of the given lengths, distinct random columns, values in
+    (-1, 1)."""
+    g = np.random.default_rng(seed)
+    cols = [g.choice(n_cols, L, replace=False) for L in lens]
+    vals = [g.uniform(-1, 1, L) for L in lens]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    return CSR(len(lens), n_cols, rp, np.concatenate(cols).astype(np.int32),
+               np.concatenate(vals))
+
+
+@pytest.mark.parametrize("name", ["cfg0", "ragged", "ragged_rect", "rows255",
+                                  "rows256", "long_rows"])
 def test_value_refresh_in_slot_order(fs, orc, name):
-    """csr_update_values (slot-ordered gather through the inverse map) leaves
-    every value array -- FP64 slots, FP32 and BF16 copies, padding -- equal
-    to those of a handle created with the new values."""
+    """csr_update_values (slot-ordered gather: through row starts and
+    byte-wide in-row positions when every row holds at most 255 entries,
+    else through the inverse map) leaves every value array -- FP64 slots,
+    FP32 and BF16 copies, padding -- equal to those of a handle created with
+    the new values.  rows255 has rows of exactly 255 entries (largest
+    position 254, next to the padding mark 255); rows256 and long_rows
+    exceed the byte-wide range and refresh through the inverse map."""
+    lens255 = np.array([255, 1, 0, 254, 255, 3] * 20)
     A = {"cfg0": W.config0_poisson2d,
          "ragged": lambda: ragged(1000, 1000, seed=96),
-         "ragged_rect": lambda: ragged(300, 1200, seed=97)}[name]()
+         "ragged_rect": lambda: ragged(300, 1200, seed=97),
+         "rows255": lambda: rows_of_lengths(lens255, 400, 93),
+         "rows256": lambda: rows_of_lengths(
+             np.where(lens255 == 255, 256, lens255), 400, 94),
+         "long_rows": lambda: ragged(400, 1000, seed=95, maxlen=600)}[name]()
     note("value refresh %s" % name)
     g = np.random.default_rng(98)
     v2 = g.uniform(-1, 1, A.nnz)
