@@ -377,6 +377,36 @@ def build_times(fs, A, rp, ci, va, M, gain, reps=2):
     return res
 
 
+def bench_autotune(fs, oracle, torch, A, d, steps, warmup, stream,
+                   default_us):
+    """The layout autotuner on one matrix: the lanes-per-row and
+    slots-per-load shapes it times, the one it keeps, and that layout's
+    product against the default layout's (every output row checked against
+    the oracle)."""
+    import workloads as W
+    t0 = time.perf_counter()
+    M = fs.csr_create(d(A.rowptr), d(A.col), d(A.val), A.n_rows, A.n_cols,
+                      autotune=1)
+    t_tune = time.perf_counter() - t0
+    info = fs.csr_info(M)
+    x = W.random_vector(A.n_cols, 1, W.XVEC)
+    perm = fs.csr_get_perm(M)
+    xp = d(x[perm])
+    yp = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+    fs.spmv_perm(M, xp, yp)
+    torch.cuda.synchronize()
+    ok = bool(np.all(np.abs(yp.cpu().numpy() - oracle.spmv(A, x)[perm]) <=
+                     1e-12 * oracle.spmv_abs(A, x)[perm]))
+    us = back_to_back_us(torch, lambda: fs.spmv_perm(M, xp, yp), steps,
+                         warmup, stream)
+    out = {"tune_s": t_tune, "candidates": info["tune_candidates"],
+           "vec": info["vec"], "groups_by_lanes": info["groups_by_lanes"],
+           "us": us, "default_layout_us": default_us,
+           "speedup_vs_default": default_us / us, "parity_all_rows": ok}
+    M.close()
+    return out
+
+
 def bench_async(fs, oracle, torch, A, M, d, b, reps):
     """One right-hand side: the host-driven solve (chunks of iterations as
     graphs, a state read per chunk) vs the stream-ordered solve (one
@@ -888,6 +918,9 @@ def main():
     c1_bytes = 12 * A.nnz + 8 * A.n_cols + 8 * A.n_rows
     log("config-1 spmv_perm: %.2f us/launch, %.1f GB/s; cold median %.2f us"
         % (c1["us"], c1["gbs"], c1["cold_us"]["median"]))
+    c1["autotuned"] = bench_autotune(fs, oracle, torch, A, d, args.steps,
+                                     args.warmup, stream, c1["us"])
+    log("config-1 autotuned layout: %s" % json.dumps(c1["autotuned"]))
 
     # achievable streaming read rate (project kernel, 2 GiB, best of three
     # grid sizes): the practical ceiling the product is compared with
