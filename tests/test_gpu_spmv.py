@@ -91,6 +91,28 @@ def test_ragged_rows(fs, orc, nr, nc, li):
     run_spmv(fs, orc, A, LAYOUTS[li], nr, "ragged%dx%d" % (nr, nc))
 
 
+@pytest.mark.parametrize("vec", [1, 2])
+def test_every_batch_count_and_tail(fs, orc, vec):
+    """One lane per row and one row group per length: group k holds 64 rows
+    of k entries, so the lanes own 1 .. 40 slots -- every count of full
+    8-slot batches (0 .. 5, odd and even, where the pipelined loop pairs
+    them) and every tail length after them; the caller-numbering and layout
+    products are checked on every row against the oracle."""
+    lens = np.repeat(np.arange(1, 41), 64)
+    g = np.random.default_rng(77 + vec)
+    n = len(lens)
+    cols = [np.sort(g.choice(n, L, replace=False)) for L in lens]
+    vals = [g.uniform(-1, 1, L) for L in lens]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    A = CSR(n, n, rp, np.concatenate(cols).astype(np.int32),
+            np.concatenate(vals))
+    M = run_spmv(fs, orc, A, dict(vec=vec, lanes_min=1, lanes_max=1,
+                                  reorder=1, sort_window=1), vec,
+                 "batches vec=%d" % vec)
+    info = fs.csr_info(M)
+    assert info["vec"] == vec and info["groups_by_lanes"][0] >= 40
+
+
 def test_empty_and_zero_matrices(fs, orc):
     import torch
     note("spmv empty")
