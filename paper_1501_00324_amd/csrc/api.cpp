@@ -130,6 +130,8 @@ fs_status create_from_host(int32_t n_rows, int32_t n_cols, int64_t nnz,
     HostLayout &L = A->host;
     A->n_groups = int32_t(L.groups.size());
     A->slots = L.slots;
+    A->pipe_product = A->n_groups > 0 &&
+                      L.slots >= 32 * int64_t(kWave) * A->n_groups;
 
     auto fail = [&](fs_status code) {
         (void)hipStreamSynchronize(s);
@@ -333,6 +335,8 @@ fs_status create_on_device(int32_t n_rows, int32_t n_cols, int64_t nnz,
     h_col.reset();
     A->n_groups = int32_t(L.groups.size());
     A->slots = L.slots;
+    A->pipe_product = A->n_groups > 0 &&
+                      L.slots >= 32 * int64_t(kWave) * A->n_groups;
     const bool square = n_rows == n_cols;
 
     int64_t &acct = A->device_bytes;

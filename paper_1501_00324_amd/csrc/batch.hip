@@ -75,13 +75,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_batch(
     const Group gd = load_group(gbl(p.groups), g);
     const int lt = gd.width_lt >> 24;
     const double acc =
-        p.gbase ? row_reduce(group_lane_sum<V, true>(
+        p.gbase ? row_reduce(group_lane_sum_plain<V, true>(
                                  gd, lane, gbl(p.val), gbl(p.col),
                                  load_gbase(gbl(p.gbase), g), gbl(p.x)),
                              lt)
-                : row_reduce(group_lane_sum<V, false>(gd, lane, gbl(p.val),
-                                                      gbl(p.col), 0,
-                                                      gbl(p.x)),
+                : row_reduce(group_lane_sum_plain<V, false>(
+                                 gd, lane, gbl(p.val), gbl(p.col), 0,
+                                 gbl(p.x)),
                              lt);
     const int r = lane >> lt;
     if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {

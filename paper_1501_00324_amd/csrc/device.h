@@ -205,10 +205,12 @@ __device__ __forceinline__ double group_lane_sum(const Group &g, int lane,
     return acc0 + acc1;
 }
 
-// The same sum without pipelining (one register set, 8 wavefronts per
-// SIMD): for kernels whose register budget is already spent, such as the
-// 1024-thread blocks of the persistent solve (128 registers per lane).
-template <int V, bool NARROW>
+// The same sum without pipelining, in batches of B slots (one register
+// set): for kernels whose register budget is already spent, such as the
+// 1024-thread blocks of the persistent solve (128 registers per lane, where
+// 16-slot batches fit and keep more loads in flight).  The order of the
+// sums does not depend on B.
+template <int V, bool NARROW, int B = 8>
 __device__ __forceinline__ double group_lane_sum_plain(const Group &g,
                                                        int lane,
                                                        gptr<double> val,
@@ -217,7 +219,7 @@ __device__ __forceinline__ double group_lane_sum_plain(const Group &g,
 {
     typedef typename Slots<V>::D D;
     typedef ColStream<V, NARROW> CS;
-    constexpr int U = 8 / V;
+    constexpr int U = B / V;
     const int width = g.width_lt & 0xffffff;
     const long base = long(g.base64) * kWave;
     gptr<D> pv = reinterpret_cast<gptr<D>>(val + base) + lane;

@@ -270,6 +270,9 @@ struct fs_csr {
     int32_t *d_gbase = nullptr;    // per-group column base for d_col16
     int32_t *d_map = nullptr;
     int32_t *d_imap = nullptr;     // slot -> CSR position, -1 = padding
+    // the product runs the pipelined lane sum: lanes own 32 or more slots
+    // on average (at least four 8-slot batches)
+    bool pipe_product = false;
     // per-Newton-step refresh through row starts (rows of <= 255 entries):
     // d_rstart[row] = CSR position of the row's first entry, d_jpos[slot] =
     // position within the row, 255 = padding; NULL: refresh through d_imap

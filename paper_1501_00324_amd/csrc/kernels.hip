@@ -29,8 +29,14 @@ namespace {
 
 // ---------------------------------------------------------------- SpMV
 // SCATTER: write y(yperm[row]) (caller numbering, the final re-mapping of
-// the paper's K1), else y(row) in layout numbering (K1r).
-template <int V, bool SCATTER, bool NARROW>
+// the paper's K1), else y(row) in layout numbering (K1r).  PIPE: the
+// software-pipelined lane sum (two register sets, 4 wavefronts per SIMD),
+// which pays when lanes own several 8-slot batches; matrices with short
+// rows (a lane owning one or two batches) run the plain loop at 8
+// wavefronts per SIMD -- measured: 3-D P1 Laplacian (15 entries per row)
+// 27% and graded 2-D triangles (7 per row) 34% slower pipelined, the
+// elasticity matrices (44-81 per row) 2-5% faster.
+template <int V, bool SCATTER, bool NARROW, bool PIPE>
 __global__ __launch_bounds__(kBlock) void k_spmv_f64(
     const Group *__restrict__ groups, int ngroups,
     const double *__restrict__ val, const void *__restrict__ col,
@@ -45,9 +51,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_f64(
     const Group gd = load_group(gbl(groups), g);
     const int lt = gd.width_lt >> 24;
     const int gb = NARROW ? load_gbase(gbl(gbase), g) : 0;
-    double acc = row_reduce(
-        group_lane_sum<V, NARROW>(gd, lane, gbl(val), gbl(col), gb, gbl(x)),
-        lt);
+    double acc;
+    if constexpr (PIPE)
+        acc = group_lane_sum<V, NARROW>(gd, lane, gbl(val), gbl(col), gb,
+                                        gbl(x));
+    else
+        acc = group_lane_sum_plain<V, NARROW>(gd, lane, gbl(val), gbl(col),
+                                              gb, gbl(x));
+    acc = row_reduce(acc, lt);
     const int r = lane >> lt;
     if ((lane & ((1 << lt) - 1)) == 0 && r < gd.nrows) {
         const int row = gd.row0 + r;
@@ -151,9 +162,16 @@ void spmv_go(const fs_csr *A, const double *x, double *y,
 {
     const void *col = N ? static_cast<const void *>(A->d_col16)
                         : static_cast<const void *>(A->d_col);
-    hipLaunchKernelGGL((k_spmv_f64<V, S, N>), dim3(spmv_blocks(A->n_groups)),
-                       dim3(kBlock), 0, s, A->d_groups, A->n_groups, A->d_val,
-                       col, A->d_gbase, x, y, yperm);
+    if (A->pipe_product)
+        hipLaunchKernelGGL((k_spmv_f64<V, S, N, true>),
+                           dim3(spmv_blocks(A->n_groups)), dim3(kBlock), 0, s,
+                           A->d_groups, A->n_groups, A->d_val, col,
+                           A->d_gbase, x, y, yperm);
+    else
+        hipLaunchKernelGGL((k_spmv_f64<V, S, N, false>),
+                           dim3(spmv_blocks(A->n_groups)), dim3(kBlock), 0, s,
+                           A->d_groups, A->n_groups, A->d_val, col,
+                           A->d_gbase, x, y, yperm);
 }
 
 template <int V>

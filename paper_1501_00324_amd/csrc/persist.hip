@@ -125,7 +125,7 @@ __device__ __forceinline__ void residual_rows(const PcgArgs &a, int g0, int g1,
         const int lt = gd.width_lt >> 24;
         double ax = 0.0;
         if (!XZ)
-            ax = row_reduce(group_lane_sum_plain<V, N>(
+            ax = row_reduce(group_lane_sum_plain<V, N, 16>(
                                 gd, lane, gbl(a.val), gbl(a.cstream),
                                 N ? load_gbase(gbl(a.gbase), g) : 0,
                                 gbl(a.x)),
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kPB) void k_cg_persistent(const PcgArgs a)
                 load_group(gbl(a.groups), __builtin_amdgcn_readfirstlane(g));
             const int lt = gd.width_lt >> 24;
             const double wv =
-                row_reduce(group_lane_sum_plain<V, N>(
+                row_reduce(group_lane_sum_plain<V, N, 16>(
                                gd, lane, gbl(a.val), gbl(a.cstream),
                                N ? load_gbase(gbl(a.gbase), g) : 0,
                                gbl(a.z)),
