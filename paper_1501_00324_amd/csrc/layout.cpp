@@ -55,8 +55,16 @@ bool sorted_symmetric_pattern(int32_t n, const int32_t *rowptr,
     const int64_t nch = (n + kRowChunk - 1) / kRowChunk;
     std::vector<uint64_t> s1(size_t(nch), 0), s2(size_t(nch), 0);
     std::vector<char> sorted(size_t(nch), 1);
+    // column counts, in parallel over row chunks (relaxed atomic adds: the
+    // counts do not depend on the order of the additions)
     std::vector<int64_t> colcount(size_t(n), 0);
-    for (int64_t k = 0; k < rowptr[n]; ++k) colcount[size_t(col[k])]++;
+    parallel_chunks(nch, [&](int64_t c) {
+        const int64_t k1 =
+            rowptr[std::min<int64_t>(n, (c + 1) * kRowChunk)];
+        for (int64_t k = rowptr[c * kRowChunk]; k < k1; ++k)
+            __atomic_fetch_add(&colcount[size_t(col[k])], int64_t(1),
+                               __ATOMIC_RELAXED);
+    });
     parallel_chunks(nch, [&](int64_t c) {
         uint64_t a = 0, b = 0;
         const int32_t i1 = int32_t(std::min<int64_t>(n, (c + 1) * kRowChunk));
