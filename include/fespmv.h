@@ -145,7 +145,14 @@ fs_status csr_create(int32_t n_rows, int32_t n_cols, int64_t nnz,
                      hipStream_t s, fs_csr_t *out);
 
 /* New values for the same pattern (vals in the CSR order that csr_create
- * saw), refreshing any low-precision copies.  Asynchronous on s. */
+ * saw), refreshing any low-precision copies: the per-Newton-step value
+ * reorder of section "Cost of Reordering Matrix Values".  One device pass
+ * in slot order; each slot reads its entry at its row's CSR start plus a
+ * byte-wide position within the row (kept from creation, 1 byte per slot
+ * and 5 per row, when no row holds more than 255 entries), else through a
+ * 4-byte slot-to-CSR map.  vals is a device array of nnz doubles the
+ * library only reads.  Asynchronous on s.
+ * Errors: FS_E_ARG (NULL handle or values), FS_E_HIP. */
 fs_status csr_update_values(fs_csr_t A, const double *vals, hipStream_t s);
 
 /* Materialise a low-precision copy (FS_DT_F32 or FS_DT_BF16) of the values
