@@ -142,7 +142,7 @@ struct EngineLaunch {            // one batched launch shape
 };
 
 int32_t engine_spmv_blocks(int32_t ngroups);
-int32_t engine_vec_blocks(int32_t n);
+int32_t engine_vec_blocks(int32_t n, int32_t k);
 // One CG iteration for every running right-hand side of every system:
 // Q = A P with p.q, then x/r update with r.z and r.r, then the p update.
 hipError_t engine_iteration(const EngineLaunch &L, hipStream_t s);

@@ -75,7 +75,7 @@ int64_t krylov_bytes(const fs_csr *A, int32_t k, int32_t precond)
 {
     const int64_t n = A->n_rows;
     const int64_t snb = engine_spmv_blocks(A->n_groups);
-    const int64_t vnb = engine_vec_blocks(A->n_rows);
+    const int64_t vnb = engine_vec_blocks(A->n_rows, k);
     return 5 * n * k * 8 + (precond ? n * 8 : 0) +
            int64_t(sizeof(ColState)) * k + 4 +
            8 * 3 * int64_t(k) * std::max(snb, vnb);

@@ -68,7 +68,7 @@ void sys_parts(const fs_csr *A, int32_t k, int32_t st, int32_t precond,
     const size_t n = size_t(A->n_rows);
     const size_t nk = n * size_t(k) * st_size(st);
     const size_t nbk = size_t(std::max(engine_spmv_blocks(A->n_groups),
-                                       engine_vec_blocks(A->n_rows)));
+                                       engine_vec_blocks(A->n_rows, k)));
     sz[0] = sz[1] = sz[2] = sz[3] = sz[4] = nk;
     sz[5] = precond ? n * st_size(st) : 0;
     sz[6] = sizeof(ColState) * size_t(k);
@@ -99,7 +99,7 @@ void sys_alloc_in(CgSys &S, fs_csr *A, int32_t k, int32_t vt, int32_t st,
     S.precond = precond;
     S.n = A->n_rows;
     S.snb = engine_spmv_blocks(A->n_groups);
-    S.vnb = engine_vec_blocks(S.n);
+    S.vnb = engine_vec_blocks(S.n, k);
     size_t sz[9];
     sys_parts(A, k, st, precond, sz);
     char *p = static_cast<char *>(block);
@@ -128,7 +128,7 @@ fs_status sys_alloc(CgSys &S, fs_csr *A, int32_t k, int32_t vt, int32_t st,
     S.precond = precond;
     S.n = A->n_rows;
     S.snb = engine_spmv_blocks(A->n_groups);
-    S.vnb = engine_vec_blocks(S.n);
+    S.vnb = engine_vec_blocks(S.n, k);
     const size_t nk = size_t(S.n) * size_t(k) * st_size(st);
     fs_status r = FS_OK;
     if ((r = dmalloc(&S.x, nk, S.bytes)) || (r = dmalloc(&S.r, nk, S.bytes)) ||
