@@ -113,9 +113,49 @@ def bench_small_batch(fs, W, oracle, d, torch, m=64):
     t_b = time.perf_counter() - t0
     same = all(torch.equal(a.reshape(-1), bb.reshape(-1))
                for a, bb in zip(xs1, xsb))
-    worst = max(float(np.linalg.norm(bs[i].cpu().numpy() - oracle.spmv(
-        mats[i], xsb[i].reshape(-1).cpu().numpy())) /
-        np.linalg.norm(bs[i].cpu().numpy())) for i in range(m))
+
+    def worst_relres(xs):
+        return max(float(np.linalg.norm(bs[i].cpu().numpy() - oracle.spmv(
+            mats[i], xs[i].reshape(-1).cpu().numpy())) /
+            np.linalg.norm(bs[i].cpu().numpy())) for i in range(m))
+
+    worst = worst_relres(xsb)
+    # one workgroup per system, whole solve in one launch: the first call
+    # times the three workgroup sizes and keeps the fastest
+    t0 = time.perf_counter()
+    fs.cg_solve_batch_wg(Ms, bs, precond=fs.PC_JACOBI)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    t_wg, xsw, infw = None, None, None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs_, inf_ = fs.cg_solve_batch_wg(Ms, bs, precond=fs.PC_JACOBI)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        if t_wg is None or t < t_wg:
+            t_wg, xsw, infw = t, xs_, inf_
+    by_threads = {}
+    for th in (256, 512, 1024):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs_, _ = fs.cg_solve_batch_wg(Ms, bs, precond=fs.PC_JACOBI,
+                                      wg_threads=th)
+        torch.cuda.synchronize()
+        by_threads[str(th)] = {
+            "solves_per_s": m / (time.perf_counter() - t0),
+            "bitwise_equal": all(torch.equal(a, c) for a, c in
+                                 zip(xs_, xsw))}
+    xa, _ = fs.cg_solve_batch_wg(Ms[:1], bs[:1], precond=fs.PC_JACOBI)
+    wg = {"solves_per_s": m / t_wg, "speedup_vs_batched": t_b / t_wg,
+          "speedup_vs_one_at_a_time": t_one / t_wg,
+          "first_call_with_tuning_ms": t_tune * 1e3,
+          "by_threads": by_threads,
+          "device_ms_max": max(i["ms"] for i in infw),
+          "iters_max": max(i["iters"] for i in infw),
+          "all_converged": all(i["status"] == 0 for i in infw),
+          "relres_oracle_worst": worst_relres(xsw),
+          "bitwise_equal_to_alone": bool(torch.equal(xa[0], xsw[0]))}
     for M in Ms:
         M.close()
     return {"systems": m, "rows_each": mats[0].n_rows,
@@ -123,7 +163,8 @@ def bench_small_batch(fs, W, oracle, d, torch, m=64):
             "batched_solves_per_s": m / t_b,
             "speedup": t_one / t_b, "bitwise_equal_to_alone": bool(same),
             "relres_oracle_worst": worst,
-            "iters_max": max(i["iters"] for i in infos)}
+            "iters_max": max(i["iters"] for i in infos),
+            "one_workgroup_per_system": wg}
 
 
 def serving_pool(W, n_mats=6):

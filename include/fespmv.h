@@ -329,7 +329,12 @@ typedef struct fs_cg_opts {
                              info->cond_est the ratio of the extreme
                              eigenvalues of their Lanczos tridiagonal, an
                              estimate of the condition number of M^-1 A   */
-    int32_t reserved[3];  /* must be zero                                    */
+    int32_t wg_threads;   /* cg_solve_batch_wg: threads per workgroup, 256,
+                             512 or 1024; 0 = the fastest of the three,
+                             timed on the first call for a batch shape and
+                             remembered for the process (the results do not
+                             depend on it)                                  */
+    int32_t reserved[2];  /* must be zero                                    */
 } fs_cg_opts;
 
 fs_status cg_opts_default(fs_cg_opts *o);
@@ -441,6 +446,35 @@ fs_status cg_solve_batch(int32_t m, const fs_csr_t *A, const int32_t *k,
                          const double *const *B, double *const *X,
                          const fs_cg_opts *opts, fs_cg_info *info,
                          hipStream_t s);
+
+/* m independent small systems A[i] x[i] = b[i], one right-hand side each,
+ * each solved to the end by one workgroup (not in the paper: the batching
+ * addition, for systems so small that cg_solve_batch is bound by its
+ * per-iteration launches and host checks; the solver is the Jacobi-PCG of
+ * sections "Computational Cost of the Finite Element Method" and
+ * "Description of Current GPU Methods").  One launch holds every system:
+ * the workgroup of system i runs its Jacobi scaling, start residual,
+ * iterations and true-residual confirmation with residual replacement,
+ * synchronising only within itself; the matrix stays in the cache of the
+ * compute unit's L2 between iterations.  The stopping rule is cg_solve's;
+ * the sums are ordered per row group and per 64-row chunk, so x and the
+ * iteration counts agree with cg_solve up to rounding, and are bitwise the
+ * same alone or in any batch and for every opts->wg_threads.  A handle may
+ * appear several times (several right-hand sides of one matrix).  b[i] and
+ * x[i] are device vectors of n_i entries in the caller's numbering; x[i]
+ * holds the initial guess unless opts->x0_zero; the x[i] must not overlap
+ * each other or any b[j].  Limits: each system square, at most 65,536 rows
+ * and 1,024 row groups (FS_E_ARG above), FP64 only (FS_E_UNSUPPORTED
+ * otherwise), all handles on one device.  Work space (7 n doubles per
+ * system, plus descriptors) is kept per device between calls, grown to the
+ * largest batch and held until the process ends; calls on one device run
+ * one at a time (a lock is held for the call).  info (may be NULL) receives
+ * m entries; ms = device time of that system's workgroup.  Blocking;
+ * returns the worst status. */
+fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
+                            const double *const *b, double *const *x,
+                            const fs_cg_opts *opts, fs_cg_info *info,
+                            hipStream_t s);
 
 /* ------------------------------------------------------------- serving */
 /* Not in the paper: the serving addition (continuous batching of solves

@@ -75,7 +75,7 @@ class CgOpts(C.Structure):
                 ("x0_zero", C.c_int32), ("use_graph", C.c_int32),
                 ("max_outer", C.c_int32), ("ir_restart", C.c_int32),
                 ("ir_scaled", C.c_int32), ("estimate_cond", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("wg_threads", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class CgInfo(C.Structure):
@@ -114,7 +114,8 @@ EXPORTS = ["fs_last_error", "csr_opts_default", "csr_create",
            "spmv_lowp", "cg_opts_default", "cg_solve", "cg_solve_async",
            "cg_solve_async_noalloc",
            "cg_solve_multi",
-           "cg_solve_batch", "server_opts_default", "server_create",
+           "cg_solve_batch", "cg_solve_batch_wg",
+           "server_opts_default", "server_create",
            "server_submit", "server_poll", "server_stats", "server_destroy",
            "asm_create", "asm_plan_host", "asm_plan_host_groups",
            "asm_matrix", "asm_vector", "asm_system", "asm_element_rows",
@@ -172,6 +173,7 @@ def load(build_if_missing=True):
         "cg_solve_multi": [vp, i32, vp, i64, vp, i64, P(CgOpts), P(CgInfo),
                            vp],
         "cg_solve_batch": [i32, vp, vp, vp, vp, P(CgOpts), P(CgInfo), vp],
+        "cg_solve_batch_wg": [i32, vp, vp, vp, P(CgOpts), P(CgInfo), vp],
         "asm_create": [vp, i32, i32, vp, i32, vp, P(vp)],
         "asm_plan_host_groups": [i32, i64, vp, vp, P(CsrOpts), i32, i32, vp,
                                  P(i32), P(i32), P(i64), P(i64), P(i32), vp,
@@ -624,6 +626,31 @@ def cg_solve_batch(mats, Bs, Xs=None, stream=None, check=True, **opts):
                                             FS_E_BREAKDOWN)):
         raise FsError(st, msg)
     return Xs, out
+
+
+def cg_solve_batch_wg(mats, bs, xs=None, stream=None, check=True, **opts):
+    """Solve m small systems mats[i] x_i = bs[i] (vectors), each by one
+    workgroup of a single launch; returns (xs, per-system info dicts)."""
+    import torch
+    m = len(mats)
+    if xs is None:
+        xs = [torch.zeros_like(b) for b in bs]
+        opts.setdefault("x0_zero", 1)
+    hs = (C.c_void_p * max(1, m))(*[M._h for M in mats])
+    bp = (C.c_void_p * max(1, m))(*[_ptr(b, torch.float64, M.n_rows, "b")
+                                    for M, b in zip(mats, bs)])
+    xp = (C.c_void_p * max(1, m))(*[_ptr(x, torch.float64, M.n_rows, "x")
+                                    for M, x in zip(mats, xs)])
+    o = cg_opts(**opts)
+    infos = (CgInfo * max(1, m))()
+    st = load().cg_solve_batch_wg(m, hs, bp, xp, C.byref(o), infos,
+                                  _stream(stream))
+    out = [infos[i].as_dict() for i in range(m)]
+    msg = last_error() if st != FS_OK else ""
+    if st != FS_OK and (check or st not in (FS_E_NOT_CONVERGED,
+                                            FS_E_BREAKDOWN)):
+        raise FsError(st, msg)
+    return xs, out
 
 
 # ------------------------------------------------------------------ serving

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfespmv.so")
 SOURCES = ["api.cpp", "layout.cpp", "solver.cpp", "server.cpp", "kernels.hip",
            "engine.hip", "batch.hip", "persist.hip", "csr.hip", "asm.cpp",
-           "asm.hip", "build.hip", "noalloc.hip"]
+           "asm.hip", "build.hip", "noalloc.hip", "wgsolve.hip"]
 ARCH = os.environ.get("FESPMV_ARCH", "gfx950")
 
 FLAGS = [

@@ -376,6 +376,35 @@ hipError_t launch_cg_persistent(const fs_csr *A, int32_t nblocks,
                                 double *p, double *q, double *z, double *dinv,
                                 double *part, fs_cg_info *info, double rtol,
                                 int32_t maxit, bool x_zero, hipStream_t s);
+// One-workgroup solves (FP64, one right-hand side per system, layout
+// numbering): the whole Jacobi-PCG solve of a system in one workgroup, one
+// launch for a batch.  A system's per-group and per-64-row sums live in LDS,
+// which bounds it to kWgMaxParts row groups and kWgMaxRows rows.
+constexpr int32_t kWgMaxParts = 1024;
+constexpr int32_t kWgMaxRows = 64 * kWgMaxParts;
+struct WgSys {
+    const Group *groups;
+    const double *val;
+    const int32_t *col;        // 32-bit layout columns (diagonal search)
+    const void *cstream;       // column stream of the product
+    const int32_t *gbase;      // group bases of 16-bit offsets, or NULL
+    int32_t n, ngroups, vec, narrow;
+    const int32_t *perm;       // layout row i is caller row perm[i] (NULL:
+                               // the same numbering)
+    const double *b_in, *x_in; // caller's b and initial guess
+    double *x_out;             // caller's x (written at the end)
+    double *b;                 // work space, layout numbering
+    double *x, *r, *p, *q, *z, *dinv;  // dinv NULL: no preconditioner
+    fs_cg_info *info;          // device record of the result
+    double nnz;
+};
+// threads: 256, 512 or 1024; parts >= every system's row groups and
+// 64-row chunks (LDS: 48 bytes per part).
+// write_out false: x_out is left alone (timed runs of the same inputs).
+hipError_t launch_cg_wg(const WgSys *d_sys, int32_t m, int32_t threads,
+                        int32_t parts, double rtol, int32_t maxit,
+                        bool x_zero, bool write_out, int device,
+                        hipStream_t s);
 // Plain CSR product (no layout), lanes per row from the mean row length.
 int32_t csr_lanes_log2(int32_t n_rows, int64_t nnz);
 hipError_t launch_spmv_csr(int32_t n_rows, int32_t n_cols, int64_t nnz,

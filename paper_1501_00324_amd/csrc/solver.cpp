@@ -4,9 +4,12 @@
 // true-residual confirmation with residual replacement), mixed-precision
 // iterative refinement, and the cg_solve* entry points.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "host.h"
 
@@ -1169,6 +1172,190 @@ extern "C" fs_status cg_solve_batch(int32_t m, const fs_csr_t *A,
     if (info) std::memcpy(info, local.data(), sizeof(fs_cg_info) * size_t(ncols));
     if (st != FS_OK)
         set_error(st, "batched CG: at least one right-hand side did not "
+                      "converge");
+    return st;
+}
+
+namespace fs {
+namespace {
+
+// Workgroup size of cg_solve_batch_wg per batch shape, chosen by timing the
+// candidates on the first call for that shape (results do not depend on
+// it, so the timed runs also produce the answer).
+constexpr int32_t kWgCandidates[] = {256, 512, 1024};
+std::mutex g_wg_mu;
+std::map<std::array<int64_t, 6>, int32_t> g_wg_tuned;
+
+// Work space of cg_solve_batch_wg per device, kept between calls and grown
+// to the largest batch (held until the process ends: freeing it from a
+// static destructor could run after the HIP runtime has shut down).  A
+// call holds its device's lock from the first use of the space to the
+// end, so calls on one device run one at a time.
+struct WgSpace {
+    std::mutex mu;
+    char *mem = nullptr;
+    size_t cap = 0;
+};
+constexpr int kWgDevices = 64;
+WgSpace g_wg_space[kWgDevices];
+
+}  // namespace
+}  // namespace fs
+
+extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
+                                       const double *const *b,
+                                       double *const *x,
+                                       const fs_cg_opts *opts,
+                                       fs_cg_info *info, hipStream_t s)
+{
+    fs_cg_opts o;
+    FS_TRY(normalise_opts(opts, o));
+    if (m < 0 || (m > 0 && (!A || !b || !x)))
+        return set_error(FS_E_ARG, "NULL batch array or negative count");
+    if (o.precision != FS_PREC_F64)
+        return set_error(FS_E_UNSUPPORTED,
+                         "one-workgroup solves run in FP64");
+    if (o.wg_threads != 0 && o.wg_threads != 256 && o.wg_threads != 512 &&
+        o.wg_threads != 1024)
+        return set_error(FS_E_ARG,
+                         "wg_threads = %d, must be 0, 256, 512 or 1024",
+                         o.wg_threads);
+    int dev = -1;
+    int32_t parts = 1;
+    int64_t ws = 0, rows = 0, nnz = 0, vmix = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        FS_TRY(check_solve_args(A[i], 1, b[i], x[i], 1, 1));
+        const fs_csr *Ai = A[i];
+        if (Ai->n_rows > kWgMaxRows || Ai->n_groups > kWgMaxParts)
+            return set_error(FS_E_ARG,
+                             "system %d: %d rows, %d row groups; one "
+                             "workgroup takes at most %d rows and %d groups",
+                             i, Ai->n_rows, Ai->n_groups, kWgMaxRows,
+                             kWgMaxParts);
+        if (dev >= 0 && Ai->device != dev)
+            return set_error(FS_E_ARG, "batch members on different devices");
+        dev = Ai->device;
+        parts = std::max({parts, Ai->n_groups, (Ai->n_rows + kWave - 1) / kWave});
+        ws += 7 * int64_t(Ai->n_rows);
+        rows += Ai->n_rows;
+        nnz += Ai->nnz;
+        vmix = vmix * 3 + Ai->host.vec + (Ai->d_col16 ? 2 : 0);
+    }
+    std::vector<fs_cg_info> local(static_cast<size_t>(std::max(m, 1)));
+    std::memset(local.data(), 0, sizeof(fs_cg_info) * local.size());
+    if (m == 0) return FS_OK;
+    DeviceGuard g(dev);
+    // one allocation: descriptors, result records, then the systems'
+    // vectors (b, x, r, p, q, z, D^-1; layout numbering)
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t o_info = up(sizeof(WgSys) * size_t(m));
+    const size_t o_vec = o_info + up(sizeof(fs_cg_info) * size_t(m));
+    if (dev < 0 || dev >= kWgDevices)
+        return set_error(FS_E_ARG, "device %d out of range", dev);
+    WgSpace &W = g_wg_space[dev];
+    std::lock_guard<std::mutex> space_lock(W.mu);
+    const size_t need = o_vec + sizeof(double) * size_t(ws);
+    if (need > W.cap) {
+        // the old space is idle: every call synchronises before it returns
+        dfree(W.mem);
+        W.cap = 0;
+        int64_t acct = 0;
+        FS_TRY(dmalloc(reinterpret_cast<void **>(&W.mem), need, acct));
+        W.cap = need;
+    }
+    char *mem = W.mem;
+    WgSys *dsys = reinterpret_cast<WgSys *>(mem);
+    fs_cg_info *dinfo = reinterpret_cast<fs_cg_info *>(mem + o_info);
+    double *vec = reinterpret_cast<double *>(mem + o_vec);
+    std::vector<WgSys> hs(static_cast<size_t>(m));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    auto run = [&]() -> fs_status {
+        double *cur = vec;
+        for (int32_t i = 0; i < m; ++i) {
+            const fs_csr *Ai = A[i];
+            WgSys &S = hs[size_t(i)];
+            std::memset(&S, 0, sizeof S);
+            S.info = dinfo + i;
+            const int64_t n = Ai->n_rows;
+            if (n == 0) continue;
+            double *B = cur;
+            S.groups = Ai->d_groups;
+            S.val = Ai->d_val;
+            S.col = Ai->d_col;
+            S.cstream = Ai->d_col16 ? static_cast<const void *>(Ai->d_col16)
+                                    : static_cast<const void *>(Ai->d_col);
+            S.gbase = Ai->d_col16 ? Ai->d_gbase : nullptr;
+            S.n = Ai->n_rows;
+            S.ngroups = Ai->n_groups;
+            S.vec = Ai->host.vec;
+            S.narrow = Ai->d_col16 ? 1 : 0;
+            S.perm = Ai->host.identity ? nullptr : Ai->d_perm;
+            S.b_in = b[i];
+            S.x_in = x[i];
+            S.x_out = x[i];
+            S.b = B;
+            S.x = B + n;
+            S.r = B + 2 * n;
+            S.p = B + 3 * n;
+            S.q = B + 4 * n;
+            S.z = B + 5 * n;
+            S.dinv = o.precond ? B + 6 * n : nullptr;
+            S.nnz = double(Ai->nnz);
+            cur += 7 * n;
+        }
+        FS_HIP_TRY(hipMemcpyAsync(dsys, hs.data(), sizeof(WgSys) * size_t(m),
+                                  hipMemcpyHostToDevice, s));
+        FS_HIP_TRY(hipMemsetAsync(dinfo, 0, sizeof(fs_cg_info) * size_t(m), s));
+        auto launch = [&](int32_t threads, bool write_out) -> fs_status {
+            FS_HIP_TRY(launch_cg_wg(dsys, m, threads, parts, o.rtol, o.maxit,
+                                    o.x0_zero != 0, write_out, dev, s));
+            return FS_OK;
+        };
+        int32_t threads = o.wg_threads;
+        const std::array<int64_t, 6> key = {dev, m, rows, nnz, parts, vmix};
+        if (!threads) {
+            std::lock_guard<std::mutex> lk(g_wg_mu);
+            auto it = g_wg_tuned.find(key);
+            if (it != g_wg_tuned.end()) threads = it->second;
+        }
+        if (threads) {
+            FS_TRY(launch(threads, true));
+        } else {
+            FS_HIP_TRY(hipEventCreate(&ev0));
+            FS_HIP_TRY(hipEventCreate(&ev1));
+            float best = 0.0f;
+            for (int32_t c : kWgCandidates) {
+                // every run starts from the caller's x; only the last writes
+                // it back (all give bitwise the same x)
+                FS_HIP_TRY(hipEventRecord(ev0, s));
+                FS_TRY(launch(c, c == kWgCandidates[2]));
+                FS_HIP_TRY(hipEventRecord(ev1, s));
+                FS_HIP_TRY(hipEventSynchronize(ev1));
+                float t = 0.0f;
+                FS_HIP_TRY(hipEventElapsedTime(&t, ev0, ev1));
+                if (!threads || t < best) {
+                    best = t;
+                    threads = c;
+                }
+            }
+            std::lock_guard<std::mutex> lk(g_wg_mu);
+            g_wg_tuned[key] = threads;
+        }
+        FS_HIP_TRY(hipMemcpyAsync(local.data(), dinfo,
+                                  sizeof(fs_cg_info) * size_t(m),
+                                  hipMemcpyDeviceToHost, s));
+        FS_HIP_TRY(hipStreamSynchronize(s));
+        return FS_OK;
+    };
+    fs_status st = run();
+    (void)hipStreamSynchronize(s);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (st != FS_OK) return st;
+    for (int32_t i = 0; i < m; ++i) st = worst(st, local[size_t(i)].status);
+    if (info) std::memcpy(info, local.data(), sizeof(fs_cg_info) * size_t(m));
+    if (st != FS_OK)
+        set_error(st, "one-workgroup CG: at least one system did not "
                       "converge");
     return st;
 }

@@ -51,6 +51,19 @@ def test_argument_errors_are_synchronous():
     o = fs.CgOpts()
     assert L.cg_opts_default(C.byref(o)) == fs.FS_OK
     assert o.rtol == 1e-8 and o.precond == fs.PC_JACOBI
+    assert o.wg_threads == 0
+    assert L.cg_solve_batch_wg(-1, None, None, None, None, None,
+                               None) == fs.FS_E_ARG
+    assert L.cg_solve_batch_wg(1, None, None, None, None, None,
+                               None) == fs.FS_E_ARG
+    o.wg_threads = 300
+    assert L.cg_solve_batch_wg(0, None, None, None, C.byref(o), None,
+                               None) == fs.FS_E_ARG
+    assert "wg_threads" in fs.last_error()
+    o.wg_threads = 0
+    o.precision = fs.PREC_IR_F32
+    assert L.cg_solve_batch_wg(0, None, None, None, C.byref(o), None,
+                               None) == fs.FS_E_UNSUPPORTED
 
 
 # ------------------------------------------------------------ host layout
