@@ -389,6 +389,7 @@ struct WgSys {
     const void *cstream;       // column stream of the product
     const int32_t *gbase;      // group bases of 16-bit offsets, or NULL
     int32_t n, ngroups, vec, narrow;
+    int32_t zl, pad;           // zl: z = D^-1 r kept in LDS
     const int32_t *perm;       // layout row i is caller row perm[i] (NULL:
                                // the same numbering)
     const double *b_in, *x_in; // caller's b and initial guess
@@ -398,13 +399,18 @@ struct WgSys {
     fs_cg_info *info;          // device record of the result
     double nnz;
 };
-// threads: 256, 512 or 1024; parts >= every system's row groups and
-// 64-row chunks (LDS: 48 bytes per part).
-// write_out false: x_out is left alone (timed runs of the same inputs).
+// Units of one wavefront's work: row groups per unit (product steps) and
+// 64-row chunks per unit (vector step).
+constexpr int32_t kWgGroupsPerUnit = 2;
+constexpr int32_t kWgChunksPerUnit = 4;
+// threads: 256, 512 or 1024; parts >= every system's group and chunk
+// units (LDS: 48 bytes per part, then zrows doubles for the z of systems
+// with zl set, zrows >= their rows).  write_out false: x_out is left alone
+// (timed runs of the same inputs).
 hipError_t launch_cg_wg(const WgSys *d_sys, int32_t m, int32_t threads,
-                        int32_t parts, double rtol, int32_t maxit,
-                        bool x_zero, bool write_out, int device,
-                        hipStream_t s);
+                        int32_t parts, int32_t zrows, double rtol,
+                        int32_t maxit, bool x_zero, bool write_out,
+                        int device, hipStream_t s);
 // Plain CSR product (no layout), lanes per row from the mean row length.
 int32_t csr_lanes_log2(int32_t n_rows, int64_t nnz);
 hipError_t launch_spmv_csr(int32_t n_rows, int32_t n_cols, int64_t nnz,

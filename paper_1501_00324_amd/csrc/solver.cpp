@@ -1235,7 +1235,11 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
         if (dev >= 0 && Ai->device != dev)
             return set_error(FS_E_ARG, "batch members on different devices");
         dev = Ai->device;
-        parts = std::max({parts, Ai->n_groups, (Ai->n_rows + kWave - 1) / kWave});
+        const int32_t nc = (Ai->n_rows + kWave - 1) / kWave;
+        parts = std::max({parts,
+                          (Ai->n_groups + kWgGroupsPerUnit - 1) /
+                              kWgGroupsPerUnit,
+                          (nc + kWgChunksPerUnit - 1) / kWgChunksPerUnit});
         ws += 7 * int64_t(Ai->n_rows);
         rows += Ai->n_rows;
         nnz += Ai->nnz;
@@ -1245,6 +1249,17 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
     std::memset(local.data(), 0, sizeof(fs_cg_info) * local.size());
     if (m == 0) return FS_OK;
     DeviceGuard g(dev);
+    // LDS per workgroup: the part regions, then z for the systems whose z
+    // fits beside them
+    int lds_max = 0;
+    FS_HIP_TRY(hipDeviceGetAttribute(
+        &lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int64_t zcap =
+        (int64_t(lds_max) - int64_t(sizeof(double)) * 6 * parts) /
+        int64_t(sizeof(double));
+    int32_t zrows = 0;
+    for (int32_t i = 0; i < m; ++i)
+        if (A[i]->n_rows <= zcap) zrows = std::max(zrows, A[i]->n_rows);
     // one allocation: descriptors, result records, then the systems'
     // vectors (b, x, r, p, q, z, D^-1; layout numbering)
     auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
@@ -1289,6 +1304,7 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
             S.ngroups = Ai->n_groups;
             S.vec = Ai->host.vec;
             S.narrow = Ai->d_col16 ? 1 : 0;
+            S.zl = Ai->n_rows <= zrows ? 1 : 0;
             S.perm = Ai->host.identity ? nullptr : Ai->d_perm;
             S.b_in = b[i];
             S.x_in = x[i];
@@ -1307,8 +1323,9 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
                                   hipMemcpyHostToDevice, s));
         FS_HIP_TRY(hipMemsetAsync(dinfo, 0, sizeof(fs_cg_info) * size_t(m), s));
         auto launch = [&](int32_t threads, bool write_out) -> fs_status {
-            FS_HIP_TRY(launch_cg_wg(dsys, m, threads, parts, o.rtol, o.maxit,
-                                    o.x0_zero != 0, write_out, dev, s));
+            FS_HIP_TRY(launch_cg_wg(dsys, m, threads, parts, zrows, o.rtol,
+                                    o.maxit, o.x0_zero != 0, write_out, dev,
+                                    s));
             return FS_OK;
         };
         int32_t threads = o.wg_threads;

@@ -34,10 +34,9 @@ namespace {
 
 enum { W_RUNNING = 0, W_CONVERGED = 1, W_BREAKDOWN = 2, W_MAXIT = 3 };
 
-// Units of work of one wavefront: row groups per unit in the product
-// steps, 64-row chunks per unit in the vector step.
-constexpr int kGU = 2;
-constexpr int kCU = 4;
+constexpr int kGU = kWgGroupsPerUnit;
+constexpr int kCU = kWgChunksPerUnit;
+static_assert(kGU == 2, "the product pairs the two groups of a unit");
 
 struct WgArgs {
     double rtol, clock_khz;
@@ -50,11 +49,11 @@ struct WgArgs {
 // stream; the G groups' loads are issued together, U slots of each per
 // batch.  A group's sum is formed in the same order for any G and U (two
 // accumulators by slot parity, each in slot order).
-template <int V, bool N, int G, int U>
+template <int V, bool N, int G, int U, class XP>
 __device__ __forceinline__ void wg_lane_sums(const Group (&g)[G],
                                              const int (&gb)[G], int lane,
                                              gptr<double> val, gptr<void> col,
-                                             gptr<double> x, double (&out)[G])
+                                             XP x, double (&out)[G])
 {
     static_assert(U % 2 == 0, "slot parity must match the batch position");
     typedef typename Slots<V>::D D;
@@ -81,12 +80,17 @@ __device__ __forceinline__ void wg_lane_sums(const Group (&g)[G],
     double acc0[G], acc1[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) acc0[k] = acc1[k] = 0.0;
+    // padded slots (column -1) read x[0] and add nothing
+    auto fma1 = [&](int c, double av, double &acc) {
+        const double xv = x[c < 0 ? 0 : c];
+        acc = fma(av, c >= 0 ? xv : 0.0, acc);
+    };
     auto use = [&](const P &c, const D &a, int k, int j) {
         if constexpr (V == 1) {
-            slot_fma(colof(c, 0, k), a, x, (j & 1) ? acc1[k] : acc0[k]);
+            fma1(colof(c, 0, k), a, (j & 1) ? acc1[k] : acc0[k]);
         } else {
-            slot_fma(colof(c, 0, k), a.x, x, acc0[k]);
-            slot_fma(colof(c, 1, k), a.y, x, acc1[k]);
+            fma1(colof(c, 0, k), a.x, acc0[k]);
+            fma1(colof(c, 1, k), a.y, acc1[k]);
         }
     };
     int j = 0;
@@ -135,8 +139,9 @@ __device__ __forceinline__ void part_totals(const double *buf, int np,
     }
 }
 
-template <int V, bool N>
-__device__ void wg_solve(const WgSys &S, const WgArgs &a, double *lds)
+template <int V, bool N, bool ZL>
+__device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
+                                         double *lds)
 {
     const long t_start = wall_clock64();
     const int lane = threadIdx.x & (kWave - 1);
@@ -152,6 +157,21 @@ __device__ void wg_solve(const WgSys &S, const WgArgs &a, double *lds)
     const gptr<void> cstream = gbl(S.cstream);
     const gptr<int32_t> col = gbl(S.col);
     double *const D = S.dinv;
+    // z = D^-1 r: in LDS after the two part regions when it fits (ZL), so
+    // the product's gathers of z are LDS reads; else in global memory
+    double *const zl = lds + 6 * P;
+    auto zget = [&](int i) -> double {
+        if constexpr (ZL) return zl[i];
+        else return S.z[i];
+    };
+    auto zput = [&](int i, double v) {
+        if constexpr (ZL) zl[i] = v;
+        else S.z[i] = v;
+    };
+    auto zsrc = [&]() {
+        if constexpr (ZL) return static_cast<const double *>(zl);
+        else return gbl(static_cast<const double *>(S.z));
+    };
     int red = 0;   // reductions so far: region (red & 1) is next
     auto region = [&]() {
         double *r = lds + (red & 1) * 3 * P;
@@ -163,7 +183,7 @@ __device__ void wg_solve(const WgSys &S, const WgArgs &a, double *lds)
     };
     auto gbase = [&](int g) { return N ? load_gbase(gbl(S.gbase), g) : 0; };
     // product of group g with x, reduced over the T lanes of each row
-    auto gsum = [&](const Group &gd, int g, gptr<double> x) {
+    auto gsum = [&](const Group &gd, int g, auto x) {
         const Group gg[1] = {gd};
         const int gb[1] = {gbase(g)};
         double o[1];
@@ -234,7 +254,7 @@ __device__ void wg_solve(const WgSys &S, const WgArgs &a, double *lds)
                 const double zi = D ? D[row] * ri : ri;
                 if (a.x_zero) S.x[row] = 0.0;
                 S.r[row] = ri;
-                S.z[row] = zi;
+                zput(row, zi);
                 v[0] += ri * ri;
                 v[1] += ri * zi;
                 v[2] += bi * bi;
@@ -269,7 +289,7 @@ __device__ void wg_solve(const WgSys &S, const WgArgs &a, double *lds)
             int row0, row1;
             const bool own0 = owner(gd0, row0), own1 = two && owner(gd1, row1);
             if (!two) row1 = row0;
-            const double z0 = S.z[row0], z1 = S.z[row1];
+            const double z0 = zget(row0), z1 = zget(row1);
             const double p0 = first ? 0.0 : S.p[row0];
             const double q0 = first ? 0.0 : S.q[row0];
             const double p1 = first ? 0.0 : S.p[row1];
@@ -280,12 +300,12 @@ __device__ void wg_solve(const WgSys &S, const WgArgs &a, double *lds)
                 const int gb[2] = {gbase(g0), gbase(g1)};
                 double o[2];
                 wg_lane_sums<V, N, 2, 4 / V>(gg, gb, lane, val, cstream,
-                                             gbl(S.z), o);
+                                             zsrc(), o);
                 w0 = row_reduce(o[0], gd0.width_lt >> 24);
                 w1 = row_reduce(o[1], gd1.width_lt >> 24);
             } else {
-                w0 = gsum(gd0, g0, gbl(S.z));
-                if (two) w1 = gsum(gd1, g1, gbl(S.z));
+                w0 = gsum(gd0, g0, zsrc());
+                if (two) w1 = gsum(gd1, g1, zsrc());
             }
             double v = 0.0;
             if (own0) {
@@ -339,7 +359,7 @@ __device__ void wg_solve(const WgSys &S, const WgArgs &a, double *lds)
                     S.x[i] = xv[k] + alpha * pv[k];
                     S.r[i] = ri;
                     const double zi = D ? dv[k] * ri : ri;
-                    S.z[i] = zi;
+                    zput(i, zi);
                     v0 += ri * zi;
                     v1 += ri * ri;
                 }
@@ -367,7 +387,7 @@ __device__ void wg_solve(const WgSys &S, const WgArgs &a, double *lds)
                     const double ri = S.b[row] - ax;
                     const double zi = D ? D[row] * ri : ri;
                     S.r[row] = ri;
-                    S.z[row] = zi;
+                    zput(row, zi);
                     v[0] += ri * zi;
                     v[1] += ri * ri;
                 }
@@ -444,20 +464,31 @@ __global__ __launch_bounds__(BS) void k_cg_wg(const WgSys *__restrict__ sys,
     extern __shared__ double lds[];
     const WgSys S = sys[blockIdx.x];
     if (S.n == 0) return;
-    if (S.vec == 2) {
-        if (S.narrow) wg_solve<2, true>(S, a, lds);
-        else wg_solve<2, false>(S, a, lds);
+    if (S.zl) {
+        if (S.vec == 2) {
+            if (S.narrow) wg_solve<2, true, true>(S, a, lds);
+            else wg_solve<2, false, true>(S, a, lds);
+        } else {
+            if (S.narrow) wg_solve<1, true, true>(S, a, lds);
+            else wg_solve<1, false, true>(S, a, lds);
+        }
     } else {
-        if (S.narrow) wg_solve<1, true>(S, a, lds);
-        else wg_solve<1, false>(S, a, lds);
+        if (S.vec == 2) {
+            if (S.narrow) wg_solve<2, true, false>(S, a, lds);
+            else wg_solve<2, false, false>(S, a, lds);
+        } else {
+            if (S.narrow) wg_solve<1, true, false>(S, a, lds);
+            else wg_solve<1, false, false>(S, a, lds);
+        }
     }
 }
 
 }  // namespace
 
 hipError_t launch_cg_wg(const WgSys *d_sys, int32_t m, int32_t threads,
-                        int32_t parts, double rtol, int32_t maxit, bool x_zero,
-                        bool write_out, int device, hipStream_t s)
+                        int32_t parts, int32_t zrows, double rtol,
+                        int32_t maxit, bool x_zero, bool write_out,
+                        int device, hipStream_t s)
 {
     int khz = 0;
     hipError_t e =
@@ -470,7 +501,19 @@ hipError_t launch_cg_wg(const WgSys *d_sys, int32_t m, int32_t threads,
     a.x_zero = x_zero ? 1 : 0;
     a.write_out = write_out ? 1 : 0;
     a.parts = parts;
-    const size_t lds = sizeof(double) * size_t(2 * 3 * parts);
+    const size_t lds = sizeof(double) * size_t(2 * 3 * parts + zrows);
+    const void *fn = threads == 256   ? reinterpret_cast<const void *>(k_cg_wg<256>)
+                     : threads == 512 ? reinterpret_cast<const void *>(k_cg_wg<512>)
+                     : threads == 1024
+                         ? reinterpret_cast<const void *>(k_cg_wg<1024>)
+                         : nullptr;
+    if (!fn) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        // above the default limit of dynamic LDS per workgroup
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(lds));
+        if (e != hipSuccess) return e;
+    }
     switch (threads) {
     case 256:
         hipLaunchKernelGGL(k_cg_wg<256>, dim3(m), dim3(256), lds, s, d_sys, a);
@@ -478,12 +521,10 @@ hipError_t launch_cg_wg(const WgSys *d_sys, int32_t m, int32_t threads,
     case 512:
         hipLaunchKernelGGL(k_cg_wg<512>, dim3(m), dim3(512), lds, s, d_sys, a);
         break;
-    case 1024:
+    default:
         hipLaunchKernelGGL(k_cg_wg<1024>, dim3(m), dim3(1024), lds, s, d_sys,
                            a);
         break;
-    default:
-        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -100,6 +100,29 @@ def test_wg_alone_equals_mix(fs, orc, precond):
         assert np.array_equal(host(x), alone[i][0])
 
 
+def test_wg_z_in_lds_or_global(fs, orc):
+    """A 29,929-row system (its z = D^-1 r does not fit in LDS beside the
+    part sums, 8 bytes per row, so it stays in global memory) with small
+    ones whose z does: bitwise the same alone and together."""
+    mats = [W.poisson_2d_p1(175, seed=(76, 0), bc="all"),
+            W.poisson_2d_p1(20, seed=(76, 1), bc="all"),
+            W.tet_p1(6, "elastic", seed=(76, 2), bc="x0", permute=True)]
+    assert mats[0].n_rows == 29929
+    note("cg wg lds/global z, n=%s" % [A.n_rows for A in mats])
+    Ms = [make(A) for A in mats]
+    bs = [W.random_vector(A.n_rows, 76, W.BVEC, i) for i, A in
+          enumerate(mats)]
+    alone = [host(fs.cg_solve_batch_wg([M], [dev(b)], precond=1,
+                                       wg_threads=1024)[0][0])
+             for M, b in zip(Ms, bs)]
+    xs, infos = fs.cg_solve_batch_wg(Ms, [dev(b) for b in bs], precond=1,
+                                     wg_threads=1024)
+    for A, x, b, xa, inf in zip(mats, xs, bs, alone, infos):
+        assert inf["status"] == fs.FS_OK
+        assert np.array_equal(host(x), xa)
+        assert true_relres(orc, A, host(x), b) <= 1.001e-8
+
+
 def test_wg_many_systems(fs, orc):
     """More workgroups than compute units: 300 jittered 2-D Poisson
     systems, each checked against the oracle."""
