@@ -1222,7 +1222,8 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
                          o.wg_threads);
     int dev = -1;
     int32_t parts = 1;
-    int64_t ws = 0, rows = 0, nnz = 0, vmix = 0;
+    int64_t ws = 0, rows = 0, nnz = 0;
+    uint64_t kinds = 0;   // the members' slot widths and column streams
     for (int32_t i = 0; i < m; ++i) {
         FS_TRY(check_solve_args(A[i], 1, b[i], x[i], 1, 1));
         const fs_csr *Ai = A[i];
@@ -1243,7 +1244,7 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
         ws += 7 * int64_t(Ai->n_rows);
         rows += Ai->n_rows;
         nnz += Ai->nnz;
-        vmix = vmix * 3 + Ai->host.vec + (Ai->d_col16 ? 2 : 0);
+        kinds = kinds * 1000003u + uint64_t(Ai->host.vec * 2 + (Ai->d_col16 ? 1 : 0));
     }
     std::vector<fs_cg_info> local(static_cast<size_t>(std::max(m, 1)));
     std::memset(local.data(), 0, sizeof(fs_cg_info) * local.size());
@@ -1329,7 +1330,8 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
             return FS_OK;
         };
         int32_t threads = o.wg_threads;
-        const std::array<int64_t, 6> key = {dev, m, rows, nnz, parts, vmix};
+        const std::array<int64_t, 6> key = {dev, m, rows, nnz, parts,
+                                            int64_t(kinds)};
         if (!threads) {
             std::lock_guard<std::mutex> lk(g_wg_mu);
             auto it = g_wg_tuned.find(key);
