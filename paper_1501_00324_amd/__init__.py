@@ -634,8 +634,14 @@ def cg_solve_batch_wg(mats, bs, xs=None, stream=None, check=True, **opts):
     import torch
     m = len(mats)
     if xs is None:
-        xs = [torch.zeros_like(b) for b in bs]
+        # one allocation, split into the systems' vectors; with a zero
+        # initial guess the solve writes every entry
         opts.setdefault("x0_zero", 1)
+        rows = [M.n_rows for M in mats]
+        dev = bs[0].device if m else "cuda"
+        mk = torch.empty if opts["x0_zero"] else torch.zeros
+        xs = list(torch.split(mk(sum(rows), dtype=torch.float64, device=dev),
+                              rows)) if m else []
     hs = (C.c_void_p * max(1, m))(*[M._h for M in mats])
     bp = (C.c_void_p * max(1, m))(*[_ptr(b, torch.float64, M.n_rows, "b")
                                     for M, b in zip(mats, bs)])

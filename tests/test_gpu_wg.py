@@ -103,11 +103,15 @@ def test_wg_alone_equals_mix(fs, orc, precond):
 def test_wg_z_in_lds_or_global(fs, orc):
     """A 29,929-row system (its z = D^-1 r does not fit in LDS beside the
     part sums, 8 bytes per row, so it stays in global memory) with small
-    ones whose z does: bitwise the same alone and together."""
+    ones whose z does, and one whose z fits only above 64 KB of LDS:
+    bitwise the same alone and together."""
     mats = [W.poisson_2d_p1(175, seed=(76, 0), bc="all"),
             W.poisson_2d_p1(20, seed=(76, 1), bc="all"),
-            W.tet_p1(6, "elastic", seed=(76, 2), bc="x0", permute=True)]
-    assert mats[0].n_rows == 29929
+            W.tet_p1(6, "elastic", seed=(76, 2), bc="x0", permute=True),
+            # 12,100 rows: z in LDS needs 97 KB where the device allows
+            # more than 64 KB per workgroup, else z stays in global memory
+            W.poisson_2d_p1(112, seed=(76, 3), bc="all")]
+    assert mats[0].n_rows == 29929 and mats[3].n_rows == 12100
     note("cg wg lds/global z, n=%s" % [A.n_rows for A in mats])
     Ms = [make(A) for A in mats]
     bs = [W.random_vector(A.n_rows, 76, W.BVEC, i) for i, A in
