@@ -4,19 +4,22 @@
 // Methods") inside one workgroup of a single launch.  For small systems a
 // solve is bound by launch and synchronisation latency, not by bandwidth:
 // here an iteration costs two workgroup barriers instead of three kernel
-// launches and a host round trip per chunk, and the matrix, re-read every
+// launches and a host round trip per chunk; the matrix, re-read every
 // iteration, stays in the L2 of the XCD that runs its workgroup (plain
-// cached loads, unlike the streaming loads of the large products).
+// cached loads, unlike the streaming loads of the large products), and
+// z = D^-1 r, which the product gathers, stays in LDS when it fits.
 //
-// Reductions do not depend on the workgroup size: every sum is formed per
-// row group (products) or per 64-row chunk (vector steps) by the one
-// wavefront that handles it, stored in LDS at that group's or chunk's
-// index, and every wavefront then adds the stored values in index order.
-// So x, the iteration count and the residuals are bitwise the same for 256,
-// 512 or 1024 threads, alone or in any batch, and the block size can be
-// chosen by timing alone.  Two LDS regions alternate between successive
-// reductions: a region is rewritten two reductions later, after a barrier
-// that every wavefront reaches only once it has read the region's sums.
+// Reductions do not depend on the workgroup size: the work is cut into
+// fixed units (two row groups in the product steps, four 64-row chunks in
+// the vector step); the one wavefront that takes a unit adds each lane's
+// share over the unit in a fixed order, reduces across the wavefront and
+// stores the result in LDS at the unit's index, and every wavefront then
+// adds the stored values in index order.  So x, the iteration count and
+// the residuals are bitwise the same for 256, 512 or 1024 threads, alone
+// or in any batch, and the workgroup size can be chosen by timing alone.
+// Two LDS regions alternate between successive reductions: a region is
+// rewritten two reductions later, after a barrier that every wavefront
+// reaches only once it has read the region's sums.
 //
 // Iteration (as in the persistent solve: the product gathers z, and p and
 // q = A p follow the same recurrence, so the direction update needs no
