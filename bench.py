@@ -765,6 +765,10 @@ def main():
     ap.add_argument("--only-multi", type=int, default=0, metavar="K",
                     help="only one K-column multi-RHS Jacobi-PCG solve on "
                          "the 3-D elasticity system (for counter profiles)")
+    ap.add_argument("--only-small-batch", action="store_true",
+                    help="only the 64 small systems: one at a time, "
+                         "batched, one workgroup per system (for counter "
+                         "profiles)")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--no-asm", action="store_true",
                     help="skip the finite-element assembly measurement")
@@ -832,6 +836,19 @@ def main():
                           "all_converged": all(i["status"] == fs.FS_OK
                                                for i in infos)}), flush=True)
         M.close()
+        release_host_cache(torch)
+        return
+
+    if args.only_small_batch:
+        if args.calibrate_copy:
+            ca = torch.ones(CALIB_DOUBLES, dtype=torch.float64, device=dev)
+            cb = torch.empty_like(ca)
+            for _ in range(3):
+                torch.neg(ca, out=cb)
+            torch.cuda.synchronize()
+            del ca, cb
+        print(json.dumps({"cg_batched_small": bench_small_batch(
+            fs, W, oracle, d, torch)}), flush=True)
         release_host_cache(torch)
         return
 
