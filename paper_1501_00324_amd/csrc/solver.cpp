@@ -1250,17 +1250,22 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
     std::memset(local.data(), 0, sizeof(fs_cg_info) * local.size());
     if (m == 0) return FS_OK;
     DeviceGuard g(dev);
-    // LDS per workgroup: the part regions, then z for the systems whose z
-    // fits beside them
+    // LDS per workgroup: the part regions, then the vectors a system keeps
+    // there -- all six (z, x, r, p, q, D^-1) when they fit beside the
+    // parts, else z alone when it fits, else none
     int lds_max = 0;
     FS_HIP_TRY(hipDeviceGetAttribute(
         &lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const int64_t zcap =
+    const int64_t vcap =
         (int64_t(lds_max) - int64_t(sizeof(double)) * 6 * parts) /
         int64_t(sizeof(double));
-    int32_t zrows = 0;
-    for (int32_t i = 0; i < m; ++i)
-        if (A[i]->n_rows <= zcap) zrows = std::max(zrows, A[i]->n_rows);
+    auto lds_mode = [&](int64_t n) { return 6 * n <= vcap ? 2 : n <= vcap ? 1 : 0; };
+    int32_t vec_doubles = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        const int64_t n = A[i]->n_rows, md = lds_mode(n);
+        vec_doubles = int32_t(std::max<int64_t>(
+            vec_doubles, md == 2 ? 6 * n : md == 1 ? n : 0));
+    }
     // one allocation: descriptors, result records, then the systems'
     // vectors (b, x, r, p, q, z, D^-1; layout numbering)
     auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
@@ -1305,7 +1310,7 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
             S.ngroups = Ai->n_groups;
             S.vec = Ai->host.vec;
             S.narrow = Ai->d_col16 ? 1 : 0;
-            S.zl = Ai->n_rows <= zrows ? 1 : 0;
+            S.zl = lds_mode(Ai->n_rows);
             S.perm = Ai->host.identity ? nullptr : Ai->d_perm;
             S.b_in = b[i];
             S.x_in = x[i];
@@ -1324,7 +1329,7 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
                                   hipMemcpyHostToDevice, s));
         FS_HIP_TRY(hipMemsetAsync(dinfo, 0, sizeof(fs_cg_info) * size_t(m), s));
         auto launch = [&](int32_t threads, bool write_out) -> fs_status {
-            FS_HIP_TRY(launch_cg_wg(dsys, m, threads, parts, zrows, o.rtol,
+            FS_HIP_TRY(launch_cg_wg(dsys, m, threads, parts, vec_doubles, o.rtol,
                                     o.maxit, o.x0_zero != 0, write_out, dev,
                                     s));
             return FS_OK;

@@ -142,7 +142,10 @@ __device__ __forceinline__ void part_totals(const double *buf, int np,
     }
 }
 
-template <int V, bool N, bool ZL>
+// Where the vectors live (MODE): 0 all in global memory; 1 z in LDS; 2 z,
+// x, r, p, q and D^-1 in LDS (only b stays in global memory; x is copied in
+// at the start and out at the end).
+template <int V, bool N, int MODE>
 __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
                                          double *lds)
 {
@@ -159,21 +162,30 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
     const gptr<double> val = gbl(S.val);
     const gptr<void> cstream = gbl(S.cstream);
     const gptr<int32_t> col = gbl(S.col);
-    double *const D = S.dinv;
-    // z = D^-1 r: in LDS after the two part regions when it fits (ZL), so
-    // the product's gathers of z are LDS reads; else in global memory
+    const bool pc = S.dinv != nullptr;   // Jacobi preconditioner
+    // the vectors: LDS after the two part regions (z first), or global
     double *const zl = lds + 6 * P;
-    auto zget = [&](int i) -> double {
-        if constexpr (ZL) return zl[i];
-        else return S.z[i];
+    auto vec = [&](double *g, int k) {
+        if constexpr (MODE == 2) return zl + long(k) * n;
+        else return gblw(g);
     };
-    auto zput = [&](int i, double v) {
-        if constexpr (ZL) zl[i] = v;
-        else S.z[i] = v;
-    };
+    auto zv = [&]() {
+        if constexpr (MODE >= 1) return zl;
+        else return gblw(S.z);
+    }();
+    const auto X = vec(S.x, 1), R = vec(S.r, 2), Pv = vec(S.p, 3),
+               Q = vec(S.q, 4), D = vec(S.dinv, 5);
+    const auto Bv = gblw(S.b);
+    const auto perm = gbl(S.perm);
+    auto zget = [&](int i) -> double { return zv[i]; };
+    auto zput = [&](int i, double v) { zv[i] = v; };
     auto zsrc = [&]() {
-        if constexpr (ZL) return static_cast<const double *>(zl);
+        if constexpr (MODE >= 1) return static_cast<const double *>(zl);
         else return gbl(static_cast<const double *>(S.z));
+    };
+    auto xsrc = [&]() {
+        if constexpr (MODE == 2) return static_cast<const double *>(X);
+        else return gbl(static_cast<const double *>(S.x));
     };
     int red = 0;   // reductions so far: region (red & 1) is next
     auto region = [&]() {
@@ -220,13 +232,13 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
 
     // b (and the guess) into the layout numbering
     for (int i = int(threadIdx.x); i < n; i += int(blockDim.x)) {
-        const int pi = S.perm ? S.perm[i] : i;
-        S.b[i] = S.b_in[pi];
-        if (!a.x_zero) S.x[i] = S.x_in[pi];
+        const int pi = S.perm ? perm[i] : i;
+        Bv[i] = gbl(S.b_in)[pi];
+        if (!a.x_zero) X[i] = gbl(S.x_in)[pi];
     }
     __syncthreads();
     // Jacobi scaling: 1 / a_ii from the row's slots
-    if (D) {
+    if (pc) {
         for (int g = w; g < ng; g += nw) {
             const Group gd = group(g);
             const int width = gd.width_lt & 0xffffff, lt = gd.width_lt >> 24;
@@ -250,13 +262,13 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
     {
         double *buf = region();
         group_pass(buf, [&](int g, const Group &gd, double (&v)[3]) {
-            const double ax = a.x_zero ? 0.0 : gsum(gd, g, gbl(S.x));
+            const double ax = a.x_zero ? 0.0 : gsum(gd, g, xsrc());
             int row;
             if (owner(gd, row)) {
-                const double bi = S.b[row], ri = bi - ax;
-                const double zi = D ? D[row] * ri : ri;
-                if (a.x_zero) S.x[row] = 0.0;
-                S.r[row] = ri;
+                const double bi = Bv[row], ri = bi - ax;
+                const double zi = pc ? D[row] * ri : ri;
+                if (a.x_zero) X[row] = 0.0;
+                R[row] = ri;
                 zput(row, zi);
                 v[0] += ri * ri;
                 v[1] += ri * zi;
@@ -270,7 +282,7 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
     double rho = s3[1], rr = s3[0], rr_true = s3[0];
     int status = W_RUNNING, it = 0, repl = 0;
     if (bb == 0.0) {
-        for (int i = int(threadIdx.x); i < n; i += int(blockDim.x)) S.x[i] = 0.0;
+        for (int i = int(threadIdx.x); i < n; i += int(blockDim.x)) X[i] = 0.0;
         status = W_CONVERGED;
         rr_true = 0.0;
     } else if (rr <= tol2) {
@@ -293,10 +305,10 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
             const bool own0 = owner(gd0, row0), own1 = two && owner(gd1, row1);
             if (!two) row1 = row0;
             const double z0 = zget(row0), z1 = zget(row1);
-            const double p0 = first ? 0.0 : S.p[row0];
-            const double q0 = first ? 0.0 : S.q[row0];
-            const double p1 = first ? 0.0 : S.p[row1];
-            const double q1 = first ? 0.0 : S.q[row1];
+            const double p0 = first ? 0.0 : Pv[row0];
+            const double q0 = first ? 0.0 : Q[row0];
+            const double p1 = first ? 0.0 : Pv[row1];
+            const double q1 = first ? 0.0 : Q[row1];
             double w0, w1 = 0.0;
             if (two && gd0.width_lt == gd1.width_lt) {
                 const Group gg[2] = {gd0, gd1};
@@ -314,15 +326,15 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
             if (own0) {
                 const double pi = first ? z0 : z0 + beta * p0;
                 const double qi = first ? w0 : w0 + beta * q0;
-                S.p[row0] = pi;
-                S.q[row0] = qi;
+                Pv[row0] = pi;
+                Q[row0] = qi;
                 v += pi * qi;
             }
             if (own1) {
                 const double pi = first ? z1 : z1 + beta * p1;
                 const double qi = first ? w1 : w1 + beta * q1;
-                S.p[row1] = pi;
-                S.q[row1] = qi;
+                Pv[row1] = pi;
+                Q[row1] = qi;
                 v += pi * qi;
             }
             v = wave_sum(v);
@@ -347,11 +359,11 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
             for (int k = 0; k < kCU; ++k) {
                 const int i = (u * kCU + k) * kWave + lane;
                 const int ic = i < n ? i : 0;
-                rv[k] = S.r[ic];
-                qv[k] = S.q[ic];
-                xv[k] = S.x[ic];
-                pv[k] = S.p[ic];
-                dv[k] = D ? D[ic] : 1.0;
+                rv[k] = R[ic];
+                qv[k] = Q[ic];
+                xv[k] = X[ic];
+                pv[k] = Pv[ic];
+                dv[k] = pc ? D[ic] : 1.0;
             }
             double v0 = 0.0, v1 = 0.0;
 #pragma unroll
@@ -359,9 +371,9 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
                 const int i = (u * kCU + k) * kWave + lane;
                 if (i < n) {
                     const double ri = rv[k] - alpha * qv[k];
-                    S.x[i] = xv[k] + alpha * pv[k];
-                    S.r[i] = ri;
-                    const double zi = D ? dv[k] * ri : ri;
+                    X[i] = xv[k] + alpha * pv[k];
+                    R[i] = ri;
+                    const double zi = pc ? dv[k] * ri : ri;
                     zput(i, zi);
                     v0 += ri * zi;
                     v1 += ri * ri;
@@ -384,12 +396,12 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
             // confirm against the true residual; replace r if it misses
             buf = region();
             group_pass(buf, [&](int g, const Group &gd, double (&v)[2]) {
-                const double ax = gsum(gd, g, gbl(S.x));
+                const double ax = gsum(gd, g, xsrc());
                 int row;
                 if (owner(gd, row)) {
-                    const double ri = S.b[row] - ax;
-                    const double zi = D ? D[row] * ri : ri;
-                    S.r[row] = ri;
+                    const double ri = Bv[row] - ax;
+                    const double zi = pc ? D[row] * ri : ri;
+                    R[row] = ri;
                     zput(row, zi);
                     v[0] += ri * zi;
                     v[1] += ri * ri;
@@ -425,10 +437,10 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
         // the barrier that preceded the exit)
         double *buf = region();
         group_pass(buf, [&](int g, const Group &gd, double (&v)[1]) {
-            const double ax = gsum(gd, g, gbl(S.x));
+            const double ax = gsum(gd, g, xsrc());
             int row;
             if (owner(gd, row)) {
-                const double ri = S.b[row] - ax;
+                const double ri = Bv[row] - ax;
                 v[0] += ri * ri;
             }
         }, std::integral_constant<int, 1>());
@@ -441,7 +453,7 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
         // x back into the caller's numbering (every wavefront's last
         // writes of x precede the barrier of the last reduction)
         for (int i = int(threadIdx.x); i < n; i += int(blockDim.x))
-            S.x_out[S.perm ? S.perm[i] : i] = S.x[i];
+            gblw(S.x_out)[S.perm ? perm[i] : i] = X[i];
     }
     if (threadIdx.x == 0) {
         fs_cg_info o;
@@ -454,7 +466,7 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
         o.cond_est = 0.0;
         o.relres = bb > 0.0 ? sqrt(rr_true / bb) : 0.0;
         o.ms = double(wall_clock64() - t_start) / a.clock_khz;
-        o.bytes = double(it) * (12.0 * S.nnz + (D ? 104.0 : 88.0) * n) +
+        o.bytes = double(it) * (12.0 * S.nnz + (pc ? 104.0 : 88.0) * n) +
                   2.0 * (12.0 * S.nnz + 16.0 * n);
         *S.info = o;
     }
@@ -467,29 +479,25 @@ __global__ __launch_bounds__(BS) void k_cg_wg(const WgSys *__restrict__ sys,
     extern __shared__ double lds[];
     const WgSys S = sys[blockIdx.x];
     if (S.n == 0) return;
-    if (S.zl) {
+    auto go = [&](auto mode) {
+        constexpr int M = decltype(mode)::value;
         if (S.vec == 2) {
-            if (S.narrow) wg_solve<2, true, true>(S, a, lds);
-            else wg_solve<2, false, true>(S, a, lds);
+            if (S.narrow) wg_solve<2, true, M>(S, a, lds);
+            else wg_solve<2, false, M>(S, a, lds);
         } else {
-            if (S.narrow) wg_solve<1, true, true>(S, a, lds);
-            else wg_solve<1, false, true>(S, a, lds);
+            if (S.narrow) wg_solve<1, true, M>(S, a, lds);
+            else wg_solve<1, false, M>(S, a, lds);
         }
-    } else {
-        if (S.vec == 2) {
-            if (S.narrow) wg_solve<2, true, false>(S, a, lds);
-            else wg_solve<2, false, false>(S, a, lds);
-        } else {
-            if (S.narrow) wg_solve<1, true, false>(S, a, lds);
-            else wg_solve<1, false, false>(S, a, lds);
-        }
-    }
+    };
+    if (S.zl == 2) go(std::integral_constant<int, 2>());
+    else if (S.zl == 1) go(std::integral_constant<int, 1>());
+    else go(std::integral_constant<int, 0>());
 }
 
 }  // namespace
 
 hipError_t launch_cg_wg(const WgSys *d_sys, int32_t m, int32_t threads,
-                        int32_t parts, int32_t zrows, double rtol,
+                        int32_t parts, int32_t vec_doubles, double rtol,
                         int32_t maxit, bool x_zero, bool write_out,
                         int device, hipStream_t s)
 {
@@ -504,7 +512,7 @@ hipError_t launch_cg_wg(const WgSys *d_sys, int32_t m, int32_t threads,
     a.x_zero = x_zero ? 1 : 0;
     a.write_out = write_out ? 1 : 0;
     a.parts = parts;
-    const size_t lds = sizeof(double) * size_t(2 * 3 * parts + zrows);
+    const size_t lds = sizeof(double) * size_t(2 * 3 * parts + vec_doubles);
     const void *fn = threads == 256   ? reinterpret_cast<const void *>(k_cg_wg<256>)
                      : threads == 512 ? reinterpret_cast<const void *>(k_cg_wg<512>)
                      : threads == 1024
