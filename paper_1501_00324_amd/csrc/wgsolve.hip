@@ -7,7 +7,9 @@
 // launches and a host round trip per chunk; the matrix, re-read every
 // iteration, stays in the L2 of the XCD that runs its workgroup (plain
 // cached loads, unlike the streaming loads of the large products), and
-// z = D^-1 r, which the product gathers, stays in LDS when it fits.
+// the Krylov vectors stay in LDS when they fit: all of them (then only the
+// slot stream and b are read from L2), else z = D^-1 r alone, which the
+// product gathers.
 //
 // Reductions do not depend on the workgroup size: the work is cut into
 // fixed units (two row groups in the product steps, four 64-row chunks in
