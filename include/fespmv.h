@@ -456,8 +456,8 @@ fs_status cg_solve_batch(int32_t m, const fs_csr_t *A, const int32_t *k,
  * the workgroup of system i runs its Jacobi scaling, start residual,
  * iterations and true-residual confirmation with residual replacement,
  * synchronising only within itself; the matrix stays in the L2 between
- * iterations, and the Krylov vectors stay in LDS where they fit (all of them
- * up to about 3,300 rows, z = D^-1 r alone up to about 19,000).  The stopping rule is cg_solve's;
+ * iterations, and the Krylov vectors stay in LDS where they fit (z, x, r, p
+ * and q up to about 4,000 rows, z = D^-1 r alone up to about 19,000).  The stopping rule is cg_solve's;
  * the sums are ordered per row group and per 64-row chunk, so x and the
  * iteration counts agree with cg_solve up to rounding, and are bitwise the
  * same alone or in any batch and for every opts->wg_threads.  A handle may

@@ -390,7 +390,7 @@ struct WgSys {
     const int32_t *gbase;      // group bases of 16-bit offsets, or NULL
     int32_t n, ngroups, vec, narrow;
     int32_t zl, pad;           // vectors in LDS: 0 none, 1 z = D^-1 r,
-                               // 2 z, x, r, p, q, D^-1
+                               // 2 z, x, r, p, q
     const int32_t *perm;       // layout row i is caller row perm[i] (NULL:
                                // the same numbering)
     const double *b_in, *x_in; // caller's b and initial guess
@@ -406,7 +406,7 @@ constexpr int32_t kWgGroupsPerUnit = 2;
 constexpr int32_t kWgChunksPerUnit = 4;
 // threads: 256, 512 or 1024; parts >= every system's group and chunk
 // units (LDS: 48 bytes per part, then vec_doubles for the vectors that the
-// systems keep in LDS: n per system with zl = 1, 6 n with zl = 2).
+// systems keep in LDS: n per system with zl = 1, 5 n with zl = 2).
 // write_out false: x_out is left alone (timed runs of the same inputs).
 hipError_t launch_cg_wg(const WgSys *d_sys, int32_t m, int32_t threads,
                         int32_t parts, int32_t vec_doubles, double rtol,

@@ -1251,20 +1251,22 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
     if (m == 0) return FS_OK;
     DeviceGuard g(dev);
     // LDS per workgroup: the part regions, then the vectors a system keeps
-    // there -- all six (z, x, r, p, q, D^-1) when they fit beside the
-    // parts, else z alone when it fits, else none
+    // there -- z, x, r, p and q when they fit beside the parts, else z
+    // alone when it fits, else none
     int lds_max = 0;
     FS_HIP_TRY(hipDeviceGetAttribute(
         &lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const int64_t vcap =
         (int64_t(lds_max) - int64_t(sizeof(double)) * 6 * parts) /
         int64_t(sizeof(double));
-    auto lds_mode = [&](int64_t n) { return 6 * n <= vcap ? 2 : n <= vcap ? 1 : 0; };
+    auto lds_mode = [&](int64_t n) {
+        return 5 * n <= vcap ? 2 : n <= vcap ? 1 : 0;
+    };
     int32_t vec_doubles = 0;
     for (int32_t i = 0; i < m; ++i) {
         const int64_t n = A[i]->n_rows, md = lds_mode(n);
         vec_doubles = int32_t(std::max<int64_t>(
-            vec_doubles, md == 2 ? 6 * n : md == 1 ? n : 0));
+            vec_doubles, md == 2 ? 5 * n : md == 1 ? n : 0));
     }
     // one allocation: descriptors, result records, then the systems'
     // vectors (b, x, r, p, q, z, D^-1; layout numbering)

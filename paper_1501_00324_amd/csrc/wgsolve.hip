@@ -7,9 +7,9 @@
 // launches and a host round trip per chunk; the matrix, re-read every
 // iteration, stays in the L2 of the XCD that runs its workgroup (plain
 // cached loads, unlike the streaming loads of the large products), and
-// the Krylov vectors stay in LDS when they fit: all of them (then only the
-// slot stream and b are read from L2), else z = D^-1 r alone, which the
-// product gathers.
+// the Krylov vectors stay in LDS when they fit: z, x, r, p, q (then only
+// the slot stream, D^-1 and b are read from L2), else z = D^-1 r alone,
+// which the product gathers.
 //
 // Reductions do not depend on the workgroup size: the work is cut into
 // fixed units (two row groups in the product steps, four 64-row chunks in
@@ -145,8 +145,8 @@ __device__ __forceinline__ void part_totals(const double *buf, int np,
 }
 
 // Where the vectors live (MODE): 0 all in global memory; 1 z in LDS; 2 z,
-// x, r, p, q and D^-1 in LDS (only b stays in global memory; x is copied in
-// at the start and out at the end).
+// x, r, p and q in LDS (x copied in at the start and out at the end; b and
+// D^-1, which the iterations only read, stay in global memory and L2).
 template <int V, bool N, int MODE>
 __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
                                          double *lds)
@@ -176,7 +176,8 @@ __device__ __forceinline__ void wg_solve(const WgSys &S, const WgArgs &a,
         else return gblw(S.z);
     }();
     const auto X = vec(S.x, 1), R = vec(S.r, 2), Pv = vec(S.p, 3),
-               Q = vec(S.q, 4), D = vec(S.dinv, 5);
+               Q = vec(S.q, 4);
+    const auto D = gblw(S.dinv);   // read-only after the scaling pass
     const auto Bv = gblw(S.b);
     const auto perm = gbl(S.perm);
     auto zget = [&](int i) -> double { return zv[i]; };
