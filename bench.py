@@ -10,7 +10,8 @@ effective bandwidth on the algorithmic-bytes model 12 nnz + 8 n_cols +
 8 n_rows (matrix values and int32 column indices once, x once, y once),
 with the inputs resident in HBM, timed with HIP events over K back-to-back
 launches on the launch stream.  The same JSON line reports the cold-cache
-product, the CPU oracle on the same matrix, and the 3-D elasticity system
+product (after a 1 GiB write, whose dirty lines are written back during the
+timed launch, and after a 1 GiB read), the CPU oracle on the same matrix, and the 3-D elasticity system
 (P1 Kuhn tetrahedra, 64^3 nodes, random node numbering, x = 0 face clamped:
 774,144 rows, 33,967,818 non-zeros): its product, Jacobi-PCG to a true
 relative residual of 1e-8 in FP64 and with FP32 / BF16 refinement, the
@@ -354,11 +355,21 @@ def measure_matrix(fs, oracle, torch, A, d, steps, warmup, stream,
            "reorder": info["reorder"], "t_build_ms": info["t_build_ms"]}
     out["frac"] = out["gbs"] / HBM_PEAK_GBS
     if cold:
+        # two flushes of the caches (L2, MALL) and the TLB between launches:
+        # writing 1 GiB (the reported cold figure; the caches are then full of
+        # dirty lines, and writing them back to HBM falls inside the timed
+        # launch), and reading 1 GiB (clean lines: only the product's own
+        # misses are timed)
         junk = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         c = event_times_us(torch, fn, 20, stream,
                            flush=lambda: junk.fill_(1.0))
         out["cold_us"] = dist(c)
         out["cold_gbs"] = bytes_alg / (out["cold_us"]["median"] * 1e-6) / 1e9
+        cr = event_times_us(torch, fn, 20, stream,
+                            flush=lambda: junk.sum())
+        out["cold_read_flush_us"] = dist(cr)
+        out["cold_read_flush_gbs"] = bytes_alg / (
+            out["cold_read_flush_us"]["median"] * 1e-6) / 1e9
         del junk
     if not extras:
         return M, out
@@ -908,6 +919,8 @@ def main():
             "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
             "cold_pct_hbm_peak": round(100.0 * prod["cold_gbs"] /
                                        HBM_PEAK_GBS, 2),
+            "cold_read_flush_pct_hbm_peak": round(
+                100.0 * prod["cold_read_flush_gbs"] / HBM_PEAK_GBS, 2),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 2),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4),
