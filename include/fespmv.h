@@ -330,10 +330,13 @@ typedef struct fs_cg_opts {
                              eigenvalues of their Lanczos tridiagonal, an
                              estimate of the condition number of M^-1 A   */
     int32_t wg_threads;   /* cg_solve_batch_wg: threads per workgroup, 256,
-                             512 or 1024; 0 = the fastest of the three,
-                             timed on the first call for a batch shape and
-                             remembered for the process (the results do not
-                             depend on it)                                  */
+                             512 or 1024; 0 = the fastest of the three, each
+                             with the Krylov vectors in LDS where they fit
+                             and with z = D^-1 r alone there (more
+                             workgroups per compute unit), timed on the
+                             first call for a batch shape and remembered
+                             for the process (the results do not depend on
+                             the choice)                                    */
     int32_t reserved[2];  /* must be zero                                    */
 } fs_cg_opts;
 

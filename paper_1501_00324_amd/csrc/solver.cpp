@@ -1183,6 +1183,9 @@ namespace {
 // candidates on the first call for that shape (results do not depend on
 // it, so the timed runs also produce the answer).
 constexpr int32_t kWgCandidates[] = {256, 512, 1024};
+// tuned choice: threads * 4 + the cap on the LDS mode (2: z, x, r, p, q in
+// LDS where they fit; 1: z alone, which leaves room for more workgroups
+// per compute unit)
 std::mutex g_wg_mu;
 std::map<std::array<int64_t, 6>, int32_t> g_wg_tuned;
 
@@ -1259,15 +1262,18 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
     const int64_t vcap =
         (int64_t(lds_max) - int64_t(sizeof(double)) * 6 * parts) /
         int64_t(sizeof(double));
-    auto lds_mode = [&](int64_t n) {
-        return 5 * n <= vcap ? 2 : n <= vcap ? 1 : 0;
+    auto lds_mode = [&](int64_t n, int cap) {
+        return std::min(cap, 5 * n <= vcap ? 2 : n <= vcap ? 1 : 0);
     };
-    int32_t vec_doubles = 0;
-    for (int32_t i = 0; i < m; ++i) {
-        const int64_t n = A[i]->n_rows, md = lds_mode(n);
-        vec_doubles = int32_t(std::max<int64_t>(
-            vec_doubles, md == 2 ? 5 * n : md == 1 ? n : 0));
-    }
+    auto lds_doubles = [&](int cap) {
+        int64_t v = 0;
+        for (int32_t i = 0; i < m; ++i) {
+            const int64_t n = A[i]->n_rows, md = lds_mode(n, cap);
+            v = std::max<int64_t>(v, md == 2 ? 5 * n : md == 1 ? n : 0);
+        }
+        return int32_t(v);
+    };
+    const bool two_modes = lds_doubles(2) != lds_doubles(1);
     // one allocation: descriptors, result records, then the systems'
     // vectors (b, x, r, p, q, z, D^-1; layout numbering)
     auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
@@ -1312,7 +1318,7 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
             S.ngroups = Ai->n_groups;
             S.vec = Ai->host.vec;
             S.narrow = Ai->d_col16 ? 1 : 0;
-            S.zl = lds_mode(Ai->n_rows);
+            S.zl = lds_mode(Ai->n_rows, 2);
             S.perm = Ai->host.identity ? nullptr : Ai->d_perm;
             S.b_in = b[i];
             S.x_in = x[i];
@@ -1327,45 +1333,63 @@ extern "C" fs_status cg_solve_batch_wg(int32_t m, const fs_csr_t *A,
             S.nnz = double(Ai->nnz);
             cur += 7 * n;
         }
-        FS_HIP_TRY(hipMemcpyAsync(dsys, hs.data(), sizeof(WgSys) * size_t(m),
-                                  hipMemcpyHostToDevice, s));
         FS_HIP_TRY(hipMemsetAsync(dinfo, 0, sizeof(fs_cg_info) * size_t(m), s));
-        auto launch = [&](int32_t threads, bool write_out) -> fs_status {
-            FS_HIP_TRY(launch_cg_wg(dsys, m, threads, parts, vec_doubles, o.rtol,
-                                    o.maxit, o.x0_zero != 0, write_out, dev,
-                                    s));
+        // the descriptors with the LDS modes under a cap (uploaded when the
+        // stream is idle: before the first launch, and between timed runs)
+        int cur_cap = -1;
+        auto modes = [&](int cap) -> fs_status {
+            if (cap == cur_cap) return FS_OK;
+            for (int32_t i = 0; i < m; ++i)
+                if (A[i]->n_rows > 0)
+                    hs[size_t(i)].zl = lds_mode(A[i]->n_rows, cap);
+            FS_HIP_TRY(hipMemcpyAsync(dsys, hs.data(),
+                                      sizeof(WgSys) * size_t(m),
+                                      hipMemcpyHostToDevice, s));
+            cur_cap = cap;
             return FS_OK;
         };
-        int32_t threads = o.wg_threads;
+        auto launch = [&](int32_t threads, int cap, bool write_out)
+            -> fs_status {
+            FS_TRY(modes(cap));
+            FS_HIP_TRY(launch_cg_wg(dsys, m, threads, parts, lds_doubles(cap),
+                                    o.rtol, o.maxit, o.x0_zero != 0,
+                                    write_out, dev, s));
+            return FS_OK;
+        };
+        int32_t choice = o.wg_threads ? o.wg_threads * 4 + 2 : 0;
         const std::array<int64_t, 6> key = {dev, m, rows, nnz, parts,
                                             int64_t(kinds)};
-        if (!threads) {
+        if (!choice) {
             std::lock_guard<std::mutex> lk(g_wg_mu);
             auto it = g_wg_tuned.find(key);
-            if (it != g_wg_tuned.end()) threads = it->second;
+            if (it != g_wg_tuned.end()) choice = it->second;
         }
-        if (threads) {
-            FS_TRY(launch(threads, true));
+        if (choice) {
+            FS_TRY(launch(choice / 4, choice % 4, true));
         } else {
             FS_HIP_TRY(hipEventCreate(&ev0));
             FS_HIP_TRY(hipEventCreate(&ev1));
+            std::vector<int32_t> cand;
+            for (int cap : {1, 2})
+                if (cap == 2 || two_modes)
+                    for (int32_t c : kWgCandidates) cand.push_back(c * 4 + cap);
             float best = 0.0f;
-            for (int32_t c : kWgCandidates) {
+            for (size_t j = 0; j < cand.size(); ++j) {
                 // every run starts from the caller's x; only the last writes
                 // it back (all give bitwise the same x)
                 FS_HIP_TRY(hipEventRecord(ev0, s));
-                FS_TRY(launch(c, c == kWgCandidates[2]));
+                FS_TRY(launch(cand[j] / 4, cand[j] % 4, j + 1 == cand.size()));
                 FS_HIP_TRY(hipEventRecord(ev1, s));
                 FS_HIP_TRY(hipEventSynchronize(ev1));
                 float t = 0.0f;
                 FS_HIP_TRY(hipEventElapsedTime(&t, ev0, ev1));
-                if (!threads || t < best) {
+                if (!choice || t < best) {
                     best = t;
-                    threads = c;
+                    choice = cand[j];
                 }
             }
             std::lock_guard<std::mutex> lk(g_wg_mu);
-            g_wg_tuned[key] = threads;
+            g_wg_tuned[key] = choice;
         }
         FS_HIP_TRY(hipMemcpyAsync(local.data(), dinfo,
                                   sizeof(fs_cg_info) * size_t(m),
